@@ -1,0 +1,276 @@
+/*
+ * lqtrace: deflated Hutchinson estimation of trace(A^{-1}) for the Wilson-Dirac
+ * operator on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: E. Romero, A. Stathopoulos, K. Orginos, "Multigrid deflation for Lattice
+ * QCD", arXiv:1909.12234.  Section 1 defines the Hutchinson estimator (Eq. 1), its
+ * variance (Eq. 2) and the inexact solve A^{-1}_xi; Section 2.1 the K-weighted oblique
+ * projector and its trace identity; Section 2.2 the a-posteriori choice of the deflation
+ * rank; Algorithm 1 (orthogonal projector of approximate singular vectors) and
+ * Algorithm 2 (oblique projector from the coarse operator of a multigrid prolongator).
+ *
+ * Operator:  (A psi)(x) = (4+m) psi(x)
+ *            - 1/2 sum_mu [ (1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ * DeGrand-Rossi gamma matrices, g5 = diag(1,1,-1,-1); periodic boundaries, with an extra
+ * -1 on hops across the time boundary when the context is created antiperiodic.
+ *
+ * Canonical host-visible layouts (x runs fastest, mu = 0..3 <-> x, y, z, t):
+ *   links   [t][z][y][x][mu][a][b]          complex128, (re, im) interleaved
+ *   spinor  [rhs][t][z][y][x][spin][colour] complex128 (complex64 for LQT_F32 in lqt_apply)
+ * i.e. spinor component index i = 12*site + 3*spin + colour, site = x + Lx*(y + Ly*(z + Lz*t)).
+ *
+ * Conventions for every call:
+ *  - Return LQT_OK (0) on success or a negative LQT_E* code; the message is kept in the
+ *    context (lqt_last_error).  No C++ exception or abort crosses this boundary.
+ *  - Pointers named d_* are device pointers (HBM of the context's device); h_* are host.
+ *    Buffers are owned by the caller and never retained after the call returns.
+ *  - All device work is ordered on the context's HIP stream.  Calls that return host
+ *    values synchronise that stream before returning.
+ *  - Calls on one context are not thread-safe; use one context per host thread.
+ */
+#ifndef LQTRACE_H
+#define LQTRACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lqt_ctx lqt_ctx;
+typedef struct lqt_basis lqt_basis;
+
+/* ---- error codes ------------------------------------------------------------------ */
+#define LQT_OK 0
+#define LQT_EINVAL -1      /* bad argument (null pointer, size, enum)                  */
+#define LQT_ENOMEM -2      /* device or host allocation failed                         */
+#define LQT_EHIP -3        /* a HIP runtime call failed                                */
+#define LQT_ENOTCONV -4    /* a solve did not reach its tolerance; outputs still filled */
+#define LQT_ENOTUNITARY -5 /* a gauge link is not special unitary to 1e-10             */
+#define LQT_ESTATE -6      /* call out of order (e.g. no gauge field set)              */
+#define LQT_ENAN -7        /* a NaN or Inf appeared in an input or a residual          */
+
+/* ---- operators (lqt_apply) ----------------------------------------------------------- */
+#define LQT_A 0     /* A                                                                  */
+#define LQT_A_DAG 1 /* A^+ (the adjoint: forward and backward spin projectors swap)       */
+#define LQT_A_G5 2  /* A g5 : the Hermitian, maximally indefinite operator of Section 3    */
+#define LQT_G5_A 3  /* g5 A                                                               */
+
+/* ---- storage precisions ------------------------------------------------------------ */
+#define LQT_F64 0
+#define LQT_F32 1
+#define LQT_F16 2
+#define LQT_BF16 3
+
+/* ---- projectors (lqt_trace) ---------------------------------------------------------- */
+#define LQT_OBLIQUE_G5 0 /* K = g5 oblique projector of Section 2.1 (Algorithm 2 form)  */
+#define LQT_ORTH 1       /* orthogonal projector U U^+ of Algorithm 1                    */
+
+/* Solver options.  Zero-initialised fields take the defaults in brackets. */
+typedef struct {
+    int inner_prec;  /* storage of links and Krylov vectors in inner cycles [LQT_F64]   */
+    int restart;     /* GMRES restart length m, 1..64 [32]                               */
+    int maxit;       /* cap on Arnoldi steps per right-hand side [100000]               */
+    int use_net;     /* 1: learned preconditioner (lqt_precond_set) inside FGMRES      */
+    int max_batch;   /* right-hand sides solved together, 0 = all [0]                    */
+    int cgs2;        /* 1: re-orthogonalise each Arnoldi step (CGS2) [0: single CGS]     */
+    double inner_tol;/* relative reduction asked of one inner cycle [0: one full cycle]  */
+} lqt_solver_opts;
+
+/* Per right-hand side solve statistics. */
+typedef struct {
+    int converged; /* 1 if the FP64 true residual ||b - A x|| <= xi ||b||                  */
+    int iters;     /* Arnoldi steps (operator applications inside cycles)               */
+    int cycles;    /* restart cycles = FP64 residual recomputations                      */
+    double relres; /* final FP64 true relative residual                                  */
+} lqt_solve_stats;
+
+/* Trace estimate, Section 1 and Algorithms 1/2.  All values are FP64. */
+typedef struct {
+    double trace_re, trace_im; /* t0 + mean_j t_j                                        */
+    double t0_re, t0_im;       /* deterministic part (deflated subspace)                 */
+    double var_sample;         /* sum_j |t_j - mean|^2 / (s-1): one-probe variance (Eq. 2) */
+    double var_mean;           /* var_sample / s: variance of the estimate               */
+    double jackknife_err;      /* leave-one-out jackknife standard error of the mean     */
+    double var_re_only;        /* one-probe variance of Re t_j alone                     */
+    int nsolves;               /* probe solves performed                                  */
+    int nfailed;               /* probe solves that missed the tolerance                  */
+    long long iters_total;     /* Arnoldi steps summed over the probe solves             */
+    double seconds_solve;      /* device time of the probe solves                         */
+    double seconds_setup;      /* device time of probe generation and projections         */
+} lqt_trace_result;
+
+/* Options of the learned-preconditioner training (lqt_precond_train). */
+typedef struct {
+    int epochs;        /* passes over the generated pairs [4]                            */
+    double lr;         /* Adam learning rate [1e-3]                                      */
+    int pair_iters;    /* GMRES steps used to harvest each residual/error pair [64]       */
+} lqt_train_opts;
+
+/* ---- context ---------------------------------------------------------------------- */
+
+/* Create a context for an Lx x Ly x Lz x Lt lattice (dims[0..3], each >= 2 and even for
+ * Lt when t_antiperiodic is used is not required) with bare mass m, bound to hip_stream
+ * (a hipStream_t; NULL = the null stream) on the current HIP device.  Operator as in the
+ * header comment.  On failure *ctx is NULL and the code is returned. */
+int lqt_create(lqt_ctx **ctx, const int dims[4], double mass, int t_antiperiodic,
+               void *hip_stream);
+
+/* Upload the gauge field (canonical layout, V*4*9 complex128 = 144*V doubles), from host
+ * memory (on_device = 0) or device memory (1).  The field is copied into the device
+ * layouts of every precision, with the antiperiodic sign folded into the links of the
+ * last time slice.  Rejects the field with LQT_ENOTUNITARY when any link has
+ * max|U^+U - 1| > 1e-10 or |det U - 1| > 1e-10, and with LQT_ENAN on non-finite values. */
+int lqt_set_gauge(lqt_ctx *ctx, const double *links, int on_device);
+
+/* Change the bare mass m of the operator. */
+int lqt_set_mass(lqt_ctx *ctx, double mass);
+
+/* out = op(in) for nrhs spinor fields in the canonical layout, device pointers.
+ * prec LQT_F64: complex128 in/out, computed in FP64.  LQT_F32: complex64 in/out with FP32
+ * links and FP32 arithmetic.  LQT_F16 / LQT_BF16: complex64 in/out, the fields are
+ * rounded to 16-bit storage (links and input spinor) and accumulated in FP32.
+ * in and out must not overlap. */
+int lqt_apply(lqt_ctx *ctx, int op, int prec, const void *d_in, void *d_out, int nrhs);
+
+/* Solve A x_r = b_r for r < nrhs (canonical complex128 device arrays), x0 = 0, until the
+ * FP64 true residual ||b - A x|| <= xi ||b|| (the inexact solve A^{-1}_xi of Section 1).
+ * Restarted GMRES(m) (FGMRES(m) with use_net) whose inner cycles run in opts->inner_prec
+ * storage with FP32 accumulation and whose restarts recompute the residual in FP64
+ * (defect correction).  stats (may be NULL) receives nrhs entries.  Returns LQT_ENOTCONV
+ * if any system missed the tolerance within opts->maxit steps (x and stats still filled). */
+int lqt_solve(lqt_ctx *ctx, const double *d_b, double *d_x, int nrhs, double xi,
+              const lqt_solver_opts *opts, lqt_solve_stats *stats);
+
+/* ---- deflation bases ---------------------------------------------------------------- */
+
+/* Algorithm 1, first step: the k eigenpairs of the Hermitian operator A g5 with the
+ * smallest |lambda| (its eigenvectors are left singular vectors of A), from block
+ * subspace iteration with inexact solves (A g5)^{-1}_xi = g5 A^{-1}_xi and FP64
+ * Rayleigh-Ritz.  A pair is accepted when ||A g5 u - theta u|| <= xi * sigma_max(A).
+ * tau must be 0 (the i*tau*g5 shift of Section 3.2 is not implemented; LQT_EINVAL).
+ * *out receives a basis owned by the caller (free with lqt_basis_free); the context
+ * must outlive it. */
+int lqt_basis_eig(lqt_ctx *ctx, int k, double xi, double tau, const lqt_solver_opts *opts,
+                  lqt_basis **out);
+
+/* Algorithm 2, first three steps: the multigrid prolongator W built from nv near-null
+ * vectors (Gaussian starts, inverse iteration with solves to null_xi or null_maxit Arnoldi
+ * steps), blocked on block[0..3]-site aggregates and split by chirality (spins {0,1} and
+ * {2,3}), orthonormalised per (aggregate, chirality); then the k eigenvectors of the
+ * Hermitian coarse operator g5^W W^+ A W with the smallest |lambda|, rotated so that
+ * U^+ g5 A U is diagonal.  Block extents must divide the lattice. */
+int lqt_basis_prolongator(lqt_ctx *ctx, const int block[4], int nv, int k, double null_xi,
+                          int null_maxit, const lqt_solver_opts *opts, lqt_basis **out);
+
+/* Build a basis from k caller-supplied fine vectors (canonical complex128, device).  The
+ * vectors X are used as given for the K = g5 oblique projector (Section 2.1): the library
+ * forms M = X^+ g5 A X, diagonalises it and rotates U = X U_hat.  For LQT_ORTH the columns
+ * are orthonormalised first. */
+int lqt_basis_from_vectors(lqt_ctx *ctx, const double *d_vectors, int k, lqt_basis **out);
+
+/* Eigenvalues lambda_i of U^+ g5 A U (ascending |lambda|) and the rank k.  lambda may be
+ * NULL to query k; otherwise it must hold 2*k doubles (complex). */
+int lqt_basis_eigenvalues(const lqt_basis *basis, double *h_lambda, int *k);
+
+/* Copy the k basis vectors U (canonical complex128 layout) to device memory d_out. */
+int lqt_basis_vectors(const lqt_basis *basis, double *d_out);
+
+void lqt_basis_free(lqt_basis *basis);
+
+/* ---- learned preconditioner ------------------------------------------------------- */
+
+/* Set the weights of the 4-layer gauge-equivariant parallel-transport network used as a
+ * right preconditioner (features 4 -> 8 -> 8 -> 4, each feature a colour 3-vector; the 4
+ * input/output features are the 4 spin components of a spinor).  Layer l maps
+ *   out_f(x) = sum_{p=0..8} sum_g W_l[p][f][g] (T_p v_g)(x),  T_0 = 1,
+ *   T_{1+2mu} v(x) = U_mu(x) v(x+mu),  T_{2+2mu} v(x) = U_mu(x-mu)^+ v(x-mu),
+ * weights concatenated layer by layer as complex FP32 (re, im): 2*9*(32+64+64+32) = 3456
+ * floats (nbytes = 13824); stored on the device in BF16.  Host pointer. */
+int lqt_precond_set(lqt_ctx *ctx, const void *h_weights, size_t nbytes);
+
+/* Copy the current weights (complex FP32 in the order above) to the host. */
+int lqt_precond_get(lqt_ctx *ctx, void *h_weights, size_t nbytes);
+
+/* Apply the network: out = M(in), canonical complex128 device arrays, nrhs fields. */
+int lqt_precond_apply(lqt_ctx *ctx, const double *d_in, double *d_out, int nrhs);
+
+/* Train the network on npairs residual/error pairs (r, e = A^{-1} r) generated on the
+ * device from seeded Gaussian vectors, loss ||M r - e||^2 / ||e||^2, Adam. */
+int lqt_precond_train(lqt_ctx *ctx, int npairs, uint64_t seed, const lqt_train_opts *opts,
+                      double *h_final_loss);
+
+/* ---- trace estimation -------------------------------------------------------------- */
+
+/* Deflated Hutchinson estimate of trace(A^{-1}) (Eq. 1 with the split of Section 2):
+ * nprobes real Rademacher probes z_j (entries 1 - 2*bit63(h(seed ^ h(j ^ h(i)))) with h
+ * the SplitMix64 output function), y_j = A^{-1}_xi z_j, and
+ *   LQT_OBLIQUE_G5: t_j = z_j^T y_j - (z_j^T U) Lambda^{-1} (U^+ g5 z_j),
+ *                   t0 = sum_i lambda_i^{-1} u_i^+ g5 u_i                  (Section 2.1)
+ *   LQT_ORTH:       y_j = A^{-1}_xi (1 - U U^+) z_j, t_j = z_j^T y_j,
+ *                   t0 = sum_i u_i^+ A^{-1}_xi u_i                         (Algorithm 1)
+ * basis = NULL gives the undeflated estimator.  rank_curve (may be NULL) receives
+ * (k+1) x 3 doubles: for each rank k' = 0..k the estimate (re), its one-probe variance
+ * and the jackknife error, recomputed from the stored k x s products (Section 2.2;
+ * oblique projector only, else zeros).  samples (may be NULL) receives the nprobes
+ * complex samples t_j (2*nprobes doubles). */
+int lqt_trace(lqt_ctx *ctx, const lqt_basis *basis, int projector, int nprobes, uint64_t seed,
+              double xi, const lqt_solver_opts *opts, lqt_trace_result *out,
+              double *h_rank_curve, double *h_samples);
+
+/* ---- building blocks (exposed for verification and measurement) ------------------- */
+
+/* Write the real Rademacher probes j0 .. j0+nprobes-1 as canonical complex128 fields. */
+int lqt_probes(lqt_ctx *ctx, uint64_t seed, long long j0, int nprobes, double *d_out);
+
+/* C = X^+ Y for ka fields X and kb fields Y (canonical complex128, device); C is ka x kb
+ * complex, row-major, written to host memory.  FP64 MFMA. */
+int lqt_gram(lqt_ctx *ctx, const double *d_x, int ka, const double *d_y, int kb, double *h_c);
+
+/* C_up = X^+ P_+ Z and C_dn = X^+ P_- Z for the Rademacher probes Z (generated on the
+ * fly, j0 .. j0+s-1) where P_+/- keep spins {0,1} / {2,3}: so X^+ Z = C_up + C_dn and
+ * X^+ g5 Z = C_up - C_dn.  Outputs ka x s complex row-major on the host.  FP64 MFMA. */
+int lqt_project_probes(lqt_ctx *ctx, const double *d_x, int ka, uint64_t seed, long long j0,
+                       int s, double *h_cup, double *h_cdn);
+
+/* Y = beta*Y + X C for ka fields X, a ka x kb complex matrix C (row-major, host) and kb
+ * output fields Y (device, canonical complex128).  beta is 0 or 1 or -1 (alpha = 1 or
+ * -1 via sign).  FP64 MFMA. */
+int lqt_combine(lqt_ctx *ctx, const double *d_x, int ka, const double *h_c, int kb, double beta,
+                double alpha, double *d_y);
+
+/* Prolongator blocks of a basis built by lqt_basis_prolongator: restrict (c = W^+ y) and
+ * prolongate (y = W c) nrhs fields.  Coarse vectors are complex128 with layout
+ * [rhs][aggregate][chirality][nv]; fine fields canonical complex128; device pointers. */
+int lqt_restrict(lqt_ctx *ctx, const lqt_basis *basis, const double *d_fine, double *d_coarse,
+                 int nrhs);
+int lqt_prolong(lqt_ctx *ctx, const lqt_basis *basis, const double *d_coarse, double *d_fine,
+                int nrhs);
+/* Copy W (layout [aggregate][chirality][nv][site_in_block][spin2][colour], complex128,
+ * site_in_block with x fastest, spin2 = spin - 2*chirality) to device memory.  Returns the
+ * coarse dimension in *nc. */
+int lqt_prolongator_get(const lqt_basis *basis, double *d_w, long long *nc);
+/* Install a prolongator from caller-supplied W in the layout above (device). */
+int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const double *d_w,
+                               lqt_basis **out);
+
+/* Autotuner: time the candidate dslash tilings for (prec, nrhs) now and cache the choice
+ * in the context; *ms receives the best time (may be NULL). */
+int lqt_tune(lqt_ctx *ctx, int prec, int nrhs, double *ms);
+
+/* Kernel timers: HIP event pairs recorded around the library's launches on the context
+ * stream, summed per kernel family (0 Wilson operator, 1 Arnoldi orthogonalisation,
+ * 2 other field BLAS, 3 deflation projections).  h_ms4 / h_calls4 (may be NULL) receive
+ * the totals so far.  mode 0: read; 1: read, then zero; 2: zero and start timing;
+ * 3: stop timing.  Timing is off by default. */
+int lqt_kernel_times(lqt_ctx *ctx, double *h_ms4, long long *h_calls4, int mode);
+
+const char *lqt_last_error(const lqt_ctx *ctx);
+void lqt_destroy(lqt_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQTRACE_H */

@@ -1,0 +1,199 @@
+// C-ABI entry points of lqtrace.  Every call catches library errors and converts them to
+// the LQT_E* codes; the message stays in the context.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "blas.h"
+#include "lqt_internal.h"
+#include "solver.h"
+
+using lqt::DBuf;
+using lqt::Error;
+
+namespace {
+
+template <typename F>
+int guard(lqt_ctx* c, F&& f) {
+    try {
+        f();
+        return LQT_OK;
+    } catch (const Error& e) {
+        if (c) c->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        return LQT_ENOMEM;
+    } catch (...) {
+        if (c) c->err = "unexpected exception";
+        return LQT_EINVAL;
+    }
+}
+
+void need_gauge(lqt_ctx* c) { LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)"); }
+
+}  // namespace
+
+extern "C" {
+
+int lqt_create(lqt_ctx** ctx, const int dims[4], double mass, int t_antiperiodic, void* hip_stream) {
+    if (!ctx) return LQT_EINVAL;
+    *ctx = nullptr;
+    if (!dims) return LQT_EINVAL;
+    long long V = 1;
+    for (int i = 0; i < 4; i++) {
+        if (dims[i] < 2) return LQT_EINVAL;
+        V *= dims[i];
+    }
+    if (V > (1LL << 30) / 12 || !std::isfinite(mass)) return LQT_EINVAL;
+    lqt_ctx* c = new (std::nothrow) lqt_ctx();
+    if (!c) return LQT_ENOMEM;
+    for (int i = 0; i < 4; i++) c->g.L[i] = dims[i];
+    c->g.V = (int)V;
+    c->N = 12 * V;
+    c->mass = mass;
+    c->antiperiodic = t_antiperiodic ? 1 : 0;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return LQT_EHIP;
+    }
+    c->timer.init();
+    *ctx = c;
+    return LQT_OK;
+}
+
+void lqt_destroy(lqt_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    c->timer.destroy();
+    delete c;
+}
+
+const char* lqt_last_error(const lqt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int lqt_set_gauge(lqt_ctx* c, const double* links, int on_device) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(links, LQT_EINVAL, "links is null");
+        double eu = 0, ed = 0;
+        lqt::gauge_upload(c, links, on_device, &eu, &ed);
+        c->have_gauge = false;
+        LQT_CHECK(eu < 1e299 && ed < 1e299, LQT_ENAN, "gauge field holds NaN or Inf");
+        LQT_CHECK(eu <= 1e-10 && ed <= 1e-10, LQT_ENOTUNITARY,
+                  "gauge link not special unitary: max|U^+U-1| = " + std::to_string(eu) +
+                      ", max|det U - 1| = " + std::to_string(ed));
+        c->have_gauge = true;
+        c->sigma_max = 0;
+    });
+}
+
+int lqt_set_mass(lqt_ctx* c, double mass) {
+    if (!c) return LQT_EINVAL;
+    if (!std::isfinite(mass)) return LQT_EINVAL;
+    c->mass = mass;
+    c->sigma_max = 0;
+    return LQT_OK;
+}
+
+int lqt_apply(lqt_ctx* c, int op, int prec, const void* in, void* out, int nrhs) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(op >= LQT_A && op <= LQT_G5_A, LQT_EINVAL, "bad operator");
+        LQT_CHECK(prec >= LQT_F64 && prec <= LQT_BF16, LQT_EINVAL, "bad precision");
+        LQT_CHECK(nrhs >= 0, LQT_EINVAL, "nrhs < 0");
+        if (nrhs == 0) return;
+        LQT_CHECK(in && out, LQT_EINVAL, "null field pointer");
+        need_gauge(c);
+        const long long n = 12LL * c->g.V;
+        const size_t eb = lqt::storage_bytes(prec);
+        c->scratch[5].ensure((size_t)n * nrhs * eb);
+        c->scratch[6].ensure((size_t)n * nrhs * eb);
+        void* a = c->scratch[5].p;
+        void* b = c->scratch[6].p;
+        switch (prec) {
+            case LQT_F64: lqt::to_device_layout(c, (const double2*)in, (double2*)a, nrhs); break;
+            case LQT_F32: lqt::convert_in_c64<float2>(c, (const float2*)in, (float2*)a, nrhs); break;
+            case LQT_F16: lqt::convert_in_c64<lqt::h2>(c, (const float2*)in, (lqt::h2*)a, nrhs); break;
+            default: lqt::convert_in_c64<lqt::b2>(c, (const float2*)in, (lqt::b2*)a, nrhs); break;
+        }
+        lqt::dslash(c, prec, op, a, b, nrhs, n, n);
+        switch (prec) {
+            case LQT_F64: lqt::from_device_layout(c, (const double2*)b, (double2*)out, nrhs); break;
+            case LQT_F32: lqt::convert_out_c64<float2>(c, (const float2*)b, (float2*)out, nrhs); break;
+            case LQT_F16: lqt::convert_out_c64<lqt::h2>(c, (const lqt::h2*)b, (float2*)out, nrhs); break;
+            default: lqt::convert_out_c64<lqt::b2>(c, (const lqt::b2*)b, (float2*)out, nrhs); break;
+        }
+    });
+}
+
+int lqt_solve(lqt_ctx* c, const double* b, double* x, int nrhs, double xi, const lqt_solver_opts* opts,
+              lqt_solve_stats* stats) {
+    if (!c) return LQT_EINVAL;
+    int nfail = 0;
+    int rc = guard(c, [&] {
+        LQT_CHECK(nrhs >= 0, LQT_EINVAL, "nrhs < 0");
+        if (nrhs == 0) return;
+        LQT_CHECK(b && x, LQT_EINVAL, "null field pointer");
+        LQT_CHECK(xi > 0 && std::isfinite(xi), LQT_EINVAL, "tolerance must be positive");
+        need_gauge(c);
+        lqt::SolveOpts o = lqt::make_opts(opts);
+        LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net without preconditioner weights");
+        const long long n = 12LL * c->g.V;
+        LQT_CHECK(!lqt::has_nonfinite(c, b, (size_t)(2 * n * nrhs)), LQT_ENAN, "right-hand side holds NaN or Inf");
+        DBuf bd, xd;
+        bd.ensure(sizeof(double2) * (size_t)n * nrhs);
+        xd.ensure(sizeof(double2) * (size_t)n * nrhs);
+        lqt::to_device_layout(c, (const double2*)b, bd.as<double2>(), nrhs);
+        nfail = lqt::solve_fields(c, bd.as<double2>(), xd.as<double2>(), nrhs, xi, o, stats);
+        lqt::from_device_layout(c, xd.as<double2>(), (double2*)x, nrhs);
+        LQT_HIP(hipStreamSynchronize(c->stream));
+        if (nfail) c->err = std::to_string(nfail) + " of " + std::to_string(nrhs) + " systems missed the tolerance";
+    });
+    if (rc == LQT_OK && nfail) return LQT_ENOTCONV;
+    return rc;
+}
+
+int lqt_probes(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double* out) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(nprobes >= 0 && j0 >= 0, LQT_EINVAL, "bad probe range");
+        if (nprobes == 0) return;
+        LQT_CHECK(out, LQT_EINVAL, "null output");
+        const long long n = 12LL * c->g.V;
+        DBuf t;
+        t.ensure(sizeof(double2) * (size_t)n * nprobes);
+        lqt::probes_gen(c, seed, j0, nprobes, t.as<double2>());
+        lqt::from_device_layout(c, t.as<double2>(), (double2*)out, nprobes);
+        LQT_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+int lqt_tune(lqt_ctx* c, int prec, int nrhs, double* ms) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(prec >= LQT_F64 && prec <= LQT_BF16 && nrhs >= 1, LQT_EINVAL, "bad tuning request");
+        need_gauge(c);
+        double t = lqt::dslash_tune(c, prec, nrhs);
+        if (ms) *ms = t;
+    });
+}
+
+int lqt_kernel_times(lqt_ctx* c, double* ms4, long long* calls4, int mode) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        c->timer.flush();
+        for (int i = 0; i < 4; i++) {
+            if (ms4) ms4[i] = c->timer.ms[i];
+            if (calls4) calls4[i] = c->timer.calls[i];
+        }
+        if (mode == 1) c->timer.reset();
+        if (mode == 2) {
+            c->timer.reset();
+            c->timer.on = true;
+        }
+        if (mode == 3) c->timer.on = false;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,14 @@
+// FP64 field BLAS and probe kernels (device layout [field][comp][site]).
+#pragma once
+#include "lqt_internal.h"
+
+namespace lqt {
+
+void norm2_fields(lqt_ctx* c, const double2* x, int nf, double* out_dev);
+void dot_fields(lqt_ctx* c, const double2* x, const double2* y, int nf, double2* out_dev);
+void probes_gen(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double2* out);
+void probe_dots(lqt_ctx* c, uint64_t seed, long long j0, const double2* y, int nprobes, double2* out_dev);
+void gamma5_fields(lqt_ctx* c, double2* x, int nf);
+bool has_nonfinite(lqt_ctx* c, const double* p, size_t n);
+
+}  // namespace lqt

@@ -1,0 +1,216 @@
+// Field-level BLAS on FP64 device-layout fields, and the Rademacher probes.
+//
+// Probes (Section 1: real +-1 entries, E[z_i z_j] = delta_ij): entry i (global index
+// 12*site + 3*spin + colour) of probe j is 1 - 2*bit63(h(seed ^ h(j ^ h(i)))) with h the
+// SplitMix64 output function of Steele, Lea and Flood (OOPSLA 2014).  They are generated
+// wherever they are consumed instead of being stored.
+#include "lqt_internal.h"
+#include "blas.h"
+
+namespace lqt {
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t sm64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double probe_entry(uint64_t seed, uint64_t j, uint64_t i) {
+    return (sm64(seed ^ sm64(j ^ sm64(i))) >> 63) ? -1.0 : 1.0;
+}
+
+// partial |x_f|^2 per (block, field): grid (nsb, nf)
+__global__ __launch_bounds__(256) void k_norm2_part(const double2* __restrict__ x, int V, double* __restrict__ part) {
+    __shared__ double red[4];
+    const int f = blockIdx.y, s = blockIdx.x * 256 + threadIdx.x;
+    const long long n = 12LL * V;
+    double a = 0;
+    if (s < V)
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            double2 v = x[f * n + (long long)c * V + s];
+            a += v.x * v.x + v.y * v.y;
+        }
+    a = wsum(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(long long)f * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_sum_rows(const double* __restrict__ part, int nparts, double* __restrict__ out) {
+    const int f = blockIdx.x;
+    double a = 0;
+    for (int k = threadIdx.x; k < nparts; k += 64) a += part[(long long)f * nparts + k];
+    a = wsum(a);
+    if (threadIdx.x == 0) out[f] = a;
+}
+
+void norm2_fields(lqt_ctx* c, const double2* x, int nf, double* out_dev) {
+    if (nf <= 0) return;
+    const int nsb = (c->g.V + 255) / 256;
+    c->scratch[6].ensure(sizeof(double) * (size_t)nsb * nf);
+    hipLaunchKernelGGL(k_norm2_part, dim3(nsb, nf), dim3(256), 0, c->stream, x, c->g.V, c->scratch[6].as<double>());
+    LQT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows, dim3(nf), dim3(64), 0, c->stream, c->scratch[6].as<double>(), nsb, out_dev);
+    LQT_HIP(hipGetLastError());
+}
+
+// out[j] = probe (seed, j0 + j) in device layout
+__global__ __launch_bounds__(256) void k_probe_gen(uint64_t seed, long long j0, int V, double2* __restrict__ out) {
+    const int j = blockIdx.y, s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= V) return;
+    const long long n = 12LL * V;
+#pragma unroll
+    for (int c = 0; c < 12; c++)
+        out[j * n + (long long)c * V + s] =
+            make_double2(probe_entry(seed, (uint64_t)(j0 + j), (uint64_t)(12LL * s + c)), 0.0);
+}
+
+void probes_gen(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double2* out) {
+    if (nprobes <= 0) return;
+    hipLaunchKernelGGL(k_probe_gen, dim3((c->g.V + 255) / 256, nprobes), dim3(256), 0, c->stream, seed, j0, c->g.V,
+                       out);
+    LQT_HIP(hipGetLastError());
+}
+
+// partial sums of z_j^T y_j (complex) per (block, probe): y device layout FP64
+__global__ __launch_bounds__(256) void k_probe_dot_part(uint64_t seed, long long j0, const double2* __restrict__ y,
+                                                        int V, double2* __restrict__ part) {
+    __shared__ double red[4][2];
+    const int j = blockIdx.y, s = blockIdx.x * 256 + threadIdx.x;
+    const long long n = 12LL * V;
+    double a = 0, b = 0;
+    if (s < V)
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            double z = probe_entry(seed, (uint64_t)(j0 + j), (uint64_t)(12LL * s + c));
+            double2 v = y[j * n + (long long)c * V + s];
+            a += z * v.x;
+            b += z * v.y;
+        }
+    a = wsum(a);
+    b = wsum(b);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = a;
+        red[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(long long)j * gridDim.x + blockIdx.x] =
+            make_double2(red[0][0] + red[1][0] + red[2][0] + red[3][0], red[0][1] + red[1][1] + red[2][1] + red[3][1]);
+}
+
+__global__ void k_sum_rows2(const double2* __restrict__ part, int nparts, double2* __restrict__ out) {
+    const int f = blockIdx.x;
+    double a = 0, b = 0;
+    for (int k = threadIdx.x; k < nparts; k += 64) {
+        double2 p = part[(long long)f * nparts + k];
+        a += p.x;
+        b += p.y;
+    }
+    a = wsum(a);
+    b = wsum(b);
+    if (threadIdx.x == 0) out[f] = make_double2(a, b);
+}
+
+void probe_dots(lqt_ctx* c, uint64_t seed, long long j0, const double2* y, int nprobes, double2* out_dev) {
+    if (nprobes <= 0) return;
+    const int nsb = (c->g.V + 255) / 256;
+    c->scratch[6].ensure(sizeof(double2) * (size_t)nsb * nprobes);
+    hipLaunchKernelGGL(k_probe_dot_part, dim3(nsb, nprobes), dim3(256), 0, c->stream, seed, j0, y, c->g.V,
+                       c->scratch[6].as<double2>());
+    LQT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows2, dim3(nprobes), dim3(64), 0, c->stream, c->scratch[6].as<double2>(), nsb, out_dev);
+    LQT_HIP(hipGetLastError());
+}
+
+// partial conj(x_f)^T y_f per (block, field)
+__global__ __launch_bounds__(256) void k_dot_part(const double2* __restrict__ x, const double2* __restrict__ y, int V,
+                                                  double2* __restrict__ part) {
+    __shared__ double red[4][2];
+    const int f = blockIdx.y, s = blockIdx.x * 256 + threadIdx.x;
+    const long long n = 12LL * V;
+    double a = 0, b = 0;
+    if (s < V)
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            double2 u = x[f * n + (long long)c * V + s], v = y[f * n + (long long)c * V + s];
+            a += u.x * v.x + u.y * v.y;
+            b += u.x * v.y - u.y * v.x;
+        }
+    a = wsum(a);
+    b = wsum(b);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = a;
+        red[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(long long)f * gridDim.x + blockIdx.x] =
+            make_double2(red[0][0] + red[1][0] + red[2][0] + red[3][0], red[0][1] + red[1][1] + red[2][1] + red[3][1]);
+}
+
+void dot_fields(lqt_ctx* c, const double2* x, const double2* y, int nf, double2* out_dev) {
+    if (nf <= 0) return;
+    const int nsb = (c->g.V + 255) / 256;
+    c->scratch[6].ensure(sizeof(double2) * (size_t)nsb * nf);
+    hipLaunchKernelGGL(k_dot_part, dim3(nsb, nf), dim3(256), 0, c->stream, x, y, c->g.V, c->scratch[6].as<double2>());
+    LQT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows2, dim3(nf), dim3(64), 0, c->stream, c->scratch[6].as<double2>(), nsb, out_dev);
+    LQT_HIP(hipGetLastError());
+}
+
+// x <- g5 x (flip spins 2, 3) for nf FP64 fields
+__global__ void k_g5(double2* __restrict__ x, int V, long long total) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    long long n = 12LL * V;
+    long long e = i % n;
+    int comp = (int)(e / V);
+    if (comp >= 6) {
+        double2 v = x[i];
+        x[i] = make_double2(-v.x, -v.y);
+    }
+}
+
+void gamma5_fields(lqt_ctx* c, double2* x, int nf) {
+    long long total = 12LL * c->g.V * nf;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_g5, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream, x, c->g.V, total);
+    LQT_HIP(hipGetLastError());
+}
+
+// NaN / Inf scan of n doubles: bad[0] = 1 if any is not finite (flag must be zeroed first)
+__global__ void k_nan(const double* __restrict__ p, size_t n, int* __restrict__ bad) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t st = (size_t)gridDim.x * blockDim.x;
+    int b = 0;
+    for (; i < n; i += st) {
+        double v = p[i];
+        if (!(v - v == 0.0)) b = 1;
+    }
+    if (b) bad[0] = 1;
+}
+
+bool has_nonfinite(lqt_ctx* c, const double* p, size_t n) {
+    c->scratch[5].ensure(sizeof(int));
+    int* d = c->scratch[5].as<int>();
+    LQT_HIP(hipMemsetAsync(d, 0, sizeof(int), c->stream));
+    if (n) {
+        hipLaunchKernelGGL(k_nan, dim3(1024), dim3(256), 0, c->stream, p, n, d);
+        LQT_HIP(hipGetLastError());
+    }
+    int h = 0;
+    LQT_HIP(hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    LQT_HIP(hipStreamSynchronize(c->stream));
+    return h != 0;
+}
+
+}  // namespace lqt

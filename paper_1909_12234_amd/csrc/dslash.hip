@@ -1,0 +1,416 @@
+// Wilson-Dirac operator on gfx950.
+//
+//   (A psi)(x) = (4+m) psi(x)
+//              - 1/2 sum_mu [ (1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+//
+// Each hop is done on a half spinor: the rank-2 projector (1 + s g_mu) (s = -1 forward,
+// +1 backward; swapped for A^+) maps the 4 spin components to two colour vectors h0, h1,
+// the 3x3 link multiplies only those two, and the lower two spin rows are rebuilt from
+// them.  The projection and rebuild rules follow from the DeGrand-Rossi matrices:
+//   mu=x: h0 = p0 + s i p3, h1 = p1 + s i p2;  rows 2,3 += -s i Uh1, -s i Uh0
+//   mu=y: h0 = p0 - s p3,   h1 = p1 + s p2;    rows 2,3 +=  s Uh1,   -s Uh0
+//   mu=z: h0 = p0 + s i p2, h1 = p1 - s i p3;  rows 2,3 += -s i Uh0,  s i Uh1
+//   mu=t: h0 = p0 + s p2,   h1 = p1 + s p3;    rows 2,3 +=  s Uh0,    s Uh1
+// giving 1320 flops per site and right-hand side for the hopping term.
+//
+// One thread owns one site and R right-hand sides: each link is loaded once and applied
+// to R spinors.  Algorithmic traffic per site: 72 link reals + R*(24 in + 24 out) reals.
+#include "lqt_internal.h"
+
+namespace lqt {
+
+template <typename C>
+struct cpx {
+    C x, y;
+};
+
+template <typename C>
+__device__ __forceinline__ cpx<C> ld_c(const double2* p) {
+    double2 v = *p;
+    return {(C)v.x, (C)v.y};
+}
+template <typename C, typename S>
+__device__ __forceinline__ cpx<C> ld_c(const S* p) {
+    float2 v = io<S>::ld(p);
+    return {(C)v.x, (C)v.y};
+}
+template <typename C>
+__device__ __forceinline__ void st_c(double2* p, cpx<C> v) {
+    *p = make_double2((double)v.x, (double)v.y);
+}
+template <typename C, typename S>
+__device__ __forceinline__ void st_c(S* p, cpx<C> v) {
+    io<S>::st(p, make_float2((float)v.x, (float)v.y));
+}
+
+// a + s*i*b  (s = +1 or -1)
+template <int SG, typename C>
+__device__ __forceinline__ cpx<C> add_si(cpx<C> a, cpx<C> b) {
+    return SG > 0 ? cpx<C>{a.x - b.y, a.y + b.x} : cpx<C>{a.x + b.y, a.y - b.x};
+}
+template <int SG, typename C>
+__device__ __forceinline__ cpx<C> add_s(cpx<C> a, cpx<C> b) {
+    return SG > 0 ? cpx<C>{a.x + b.x, a.y + b.y} : cpx<C>{a.x - b.x, a.y - b.y};
+}
+
+// h = (1 + SG g_MU) p restricted to its two independent rows
+template <int MU, int SG, typename C>
+__device__ __forceinline__ void project(const cpx<C> p[12], cpx<C> h0[3], cpx<C> h1[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (MU == 0) {
+            h0[a] = add_si<SG>(p[a], p[9 + a]);
+            h1[a] = add_si<SG>(p[3 + a], p[6 + a]);
+        } else if (MU == 1) {
+            h0[a] = add_s<-SG>(p[a], p[9 + a]);
+            h1[a] = add_s<SG>(p[3 + a], p[6 + a]);
+        } else if (MU == 2) {
+            h0[a] = add_si<SG>(p[a], p[6 + a]);
+            h1[a] = add_si<-SG>(p[3 + a], p[9 + a]);
+        } else {
+            h0[a] = add_s<SG>(p[a], p[6 + a]);
+            h1[a] = add_s<SG>(p[3 + a], p[9 + a]);
+        }
+    }
+}
+
+template <int MU, int SG, typename C>
+__device__ __forceinline__ void rebuild_add(cpx<C> acc[12], const cpx<C> u0[3], const cpx<C> u1[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        acc[a].x += u0[a].x;
+        acc[a].y += u0[a].y;
+        acc[3 + a].x += u1[a].x;
+        acc[3 + a].y += u1[a].y;
+        if (MU == 0) {
+            acc[6 + a] = add_si<-SG>(acc[6 + a], u1[a]);
+            acc[9 + a] = add_si<-SG>(acc[9 + a], u0[a]);
+        } else if (MU == 1) {
+            acc[6 + a] = add_s<SG>(acc[6 + a], u1[a]);
+            acc[9 + a] = add_s<-SG>(acc[9 + a], u0[a]);
+        } else if (MU == 2) {
+            acc[6 + a] = add_si<-SG>(acc[6 + a], u0[a]);
+            acc[9 + a] = add_si<SG>(acc[9 + a], u1[a]);
+        } else {
+            acc[6 + a] = add_s<SG>(acc[6 + a], u0[a]);
+            acc[9 + a] = add_s<SG>(acc[9 + a], u1[a]);
+        }
+    }
+}
+
+template <bool DAGGER_LINK, typename C>
+__device__ __forceinline__ void su3_mul(const cpx<C> u[9], const cpx<C> h[3], cpx<C> o[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        C re = 0, im = 0;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            cpx<C> l = DAGGER_LINK ? cpx<C>{u[3 * b + a].x, -u[3 * b + a].y} : u[3 * a + b];
+            re += l.x * h[b].x - l.y * h[b].y;
+            im += l.x * h[b].y + l.y * h[b].x;
+        }
+        o[a] = {re, im};
+    }
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ void load_spinor(const S* __restrict__ f, int V, int s, bool g5, cpx<C> p[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        p[c] = ld_c<C>(f + (long long)c * V + s);
+        if (g5 && c >= 6) {
+            p[c].x = -p[c].x;
+            p[c].y = -p[c].y;
+        }
+    }
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ void load_link(const S* __restrict__ U, int V, int mu, int s, cpx<C> u[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; i++) u[i] = ld_c<C>(U + (long long)(mu * 9 + i) * V + s);
+}
+
+// hop for one direction: acc[r] += (1 - g) U(x) psi(x+mu) + (1 + g) U(x-mu)^+ psi(x-mu)
+// (projector signs swap for the adjoint)
+template <int MU, bool DAG, int R, typename S, typename C>
+__device__ __forceinline__ void hop_dir(const S* __restrict__ U, const S* __restrict__ in, long long in_stride, int V,
+                                        int s, int sf, int sb, int nr, bool g5in, cpx<C> acc[R][12]) {
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    cpx<C> u[9], p[12], h0[3], h1[3], o0[3], o1[3];
+    load_link<S, C>(U, V, MU, s, u);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (r < nr) {
+            load_spinor<S, C>(in + r * in_stride, V, sf, g5in, p);
+            project<MU, SF>(p, h0, h1);
+            su3_mul<false>(u, h0, o0);
+            su3_mul<false>(u, h1, o1);
+            rebuild_add<MU, SF>(acc[r], o0, o1);
+        }
+    }
+    load_link<S, C>(U, V, MU, sb, u);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (r < nr) {
+            load_spinor<S, C>(in + r * in_stride, V, sb, g5in, p);
+            project<MU, SB>(p, h0, h1);
+            su3_mul<true>(u, h0, o0);
+            su3_mul<true>(u, h1, o1);
+            rebuild_add<MU, SB>(acc[r], o0, o1);
+        }
+    }
+}
+
+// EPI 0: out = op(in).  EPI 1 (FP64 only): out = b - A in, with per-block partial |out|^2.
+template <typename S, int R, bool DAG, int EPI>
+__global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S* __restrict__ in, S* __restrict__ out,
+                                                const S* __restrict__ bvec, double* __restrict__ part, const int* act,
+                                                int L0, int L1, int L2, int L3, typename acc_of<S>::type diag, int nrhs,
+                                                long long in_stride, long long out_stride, int g5in, int g5out) {
+    using C = typename acc_of<S>::type;
+    const int V = L0 * L1 * L2 * L3;
+    const int nsb = (V + blockDim.x - 1) / blockDim.x;
+    const int ngrp = (nrhs + R - 1) / R;
+    const int lb = xcd_block(nsb * ngrp);
+    if (lb < 0) return;
+    const int sblk = lb / ngrp, grp = lb - sblk * ngrp;
+    const int s = sblk * blockDim.x + threadIdx.x;
+    const int r0 = grp * R;
+    const int nr = min(R, nrhs - r0);
+    double nrm[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) nrm[r] = 0;
+    if (s < V) {
+        const int x = s % L0;
+        const int y = (s / L0) % L1;
+        const int z = (s / (L0 * L1)) % L2;
+        const int t = s / (L0 * L1 * L2);
+        const int s1 = L0, s2 = L0 * L1, s3 = L0 * L1 * L2;
+        const int xf = (x == L0 - 1) ? s - (L0 - 1) : s + 1;
+        const int xb = (x == 0) ? s + (L0 - 1) : s - 1;
+        const int yf = (y == L1 - 1) ? s - (L1 - 1) * s1 : s + s1;
+        const int yb = (y == 0) ? s + (L1 - 1) * s1 : s - s1;
+        const int zf = (z == L2 - 1) ? s - (L2 - 1) * s2 : s + s2;
+        const int zb = (z == 0) ? s + (L2 - 1) * s2 : s - s2;
+        const int tf = (t == L3 - 1) ? s - (L3 - 1) * s3 : s + s3;
+        const int tb = (t == 0) ? s + (L3 - 1) * s3 : s - s3;
+
+        const long long istr = in_stride;
+        const S* inr = in + (long long)(act ? act[r0] : r0) * istr;
+
+        cpx<C> acc[R][12];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int c = 0; c < 12; c++) acc[r][c] = {0, 0};
+
+        const bool g5 = g5in != 0;
+        hop_dir<0, DAG, R, S, C>(U, inr, istr, V, s, xf, xb, nr, g5, acc);
+        hop_dir<1, DAG, R, S, C>(U, inr, istr, V, s, yf, yb, nr, g5, acc);
+        hop_dir<2, DAG, R, S, C>(U, inr, istr, V, s, zf, zb, nr, g5, acc);
+        hop_dir<3, DAG, R, S, C>(U, inr, istr, V, s, tf, tb, nr, g5, acc);
+
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (r < nr) {
+                cpx<C> p[12];
+                load_spinor<S, C>(inr + r * istr, V, s, g5, p);
+                S* o = out + (long long)(r0 + r) * out_stride;
+#pragma unroll
+                for (int c = 0; c < 12; c++) {
+                    cpx<C> v = {diag * p[c].x - (C)0.5 * acc[r][c].x, diag * p[c].y - (C)0.5 * acc[r][c].y};
+                    if (g5out && c >= 6) {
+                        v.x = -v.x;
+                        v.y = -v.y;
+                    }
+                    if (EPI == 1) {
+                        cpx<C> bb = ld_c<C>(bvec + (long long)(act ? act[r0 + r] : r0 + r) * in_stride +
+                                            (long long)c * V + s);
+                        v.x = bb.x - v.x;
+                        v.y = bb.y - v.y;
+                        nrm[r] += (double)v.x * v.x + (double)v.y * v.y;
+                    }
+                    st_c<C>(o + (long long)c * V + s, v);
+                }
+            }
+        }
+    }
+    if (EPI == 1) {
+        // deterministic block reduction of |r|^2 per right-hand side
+        __shared__ double red[256];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            red[threadIdx.x] = nrm[r];
+            __syncthreads();
+            for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+                if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0 && r0 + r < nrhs) part[(long long)(r0 + r) * nsb + sblk] = red[0];
+            __syncthreads();
+        }
+    }
+}
+
+template <typename S, int R>
+static void launch_R(lqt_ctx* c, int op, const S* U, const S* in, S* out, int nrhs, long long is, long long os,
+                     int bs) {
+    const Geom& g = c->g;
+    using C = typename acc_of<S>::type;
+    int nsb = (g.V + bs - 1) / bs;
+    int ngrp = (nrhs + R - 1) / R;
+    int nl = nsb * ngrp;
+    C diag = (C)(4.0 + c->mass);
+    int g5in = (op == LQT_A_G5), g5out = (op == LQT_G5_A);
+    if (op == LQT_A_DAG)
+        hipLaunchKernelGGL((k_dslash<S, R, true, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,
+                           (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.L[0], g.L[1], g.L[2], g.L[3],
+                           diag, nrhs, is, os, 0, 0);
+    else
+        hipLaunchKernelGGL((k_dslash<S, R, false, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,
+                           (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.L[0], g.L[1], g.L[2], g.L[3],
+                           diag, nrhs, is, os, g5in, g5out);
+    LQT_HIP(hipGetLastError());
+}
+
+template <typename S>
+static const S* gauge_of(lqt_ctx* c);
+template <>
+const double2* gauge_of<double2>(lqt_ctx* c) {
+    return c->U[LQT_F64].as<double2>();
+}
+template <>
+const float2* gauge_of<float2>(lqt_ctx* c) {
+    return c->U[LQT_F32].as<float2>();
+}
+template <>
+const h2* gauge_of<h2>(lqt_ctx* c) {
+    return c->U[LQT_F16].as<h2>();
+}
+template <>
+const b2* gauge_of<b2>(lqt_ctx* c) {
+    return c->U[LQT_BF16].as<b2>();
+}
+
+template <typename S>
+static void launch_prec(lqt_ctx* c, int op, const void* in, void* out, int nrhs, long long is, long long os, int R,
+                        int bs) {
+    const S* U = gauge_of<S>(c);
+    switch (R) {
+        case 1: launch_R<S, 1>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, bs); break;
+        case 2: launch_R<S, 2>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, bs); break;
+        default: launch_R<S, 4>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, bs); break;
+    }
+}
+
+static long long tune_key(int prec, int nrhs) { return ((long long)prec << 32) | (unsigned)nrhs; }
+
+static Tuned default_tile(int prec, int nrhs) {
+    Tuned t;
+    t.block = 256;
+    if (prec == LQT_F64)
+        t.rhs_per_thread = nrhs >= 2 ? 2 : 1;
+    else
+        t.rhs_per_thread = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
+    return t;
+}
+
+static void dslash_cfg(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long is, long long os,
+                       Tuned t) {
+    switch (prec) {
+        case LQT_F64: launch_prec<double2>(c, op, in, out, nrhs, is, os, t.rhs_per_thread, t.block); break;
+        case LQT_F32: launch_prec<float2>(c, op, in, out, nrhs, is, os, t.rhs_per_thread, t.block); break;
+        case LQT_F16: launch_prec<h2>(c, op, in, out, nrhs, is, os, t.rhs_per_thread, t.block); break;
+        default: launch_prec<b2>(c, op, in, out, nrhs, is, os, t.rhs_per_thread, t.block); break;
+    }
+}
+
+void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long in_stride,
+            long long out_stride) {
+    if (nrhs <= 0) return;
+    Tuned t;
+    auto it = c->tuned.find(tune_key(prec, nrhs));
+    t = (it != c->tuned.end()) ? it->second : default_tile(prec, nrhs);
+    c->timer.begin(c->stream, KT_DSLASH);
+    dslash_cfg(c, prec, op, in, out, nrhs, in_stride, out_stride, t);
+    c->timer.end(c->stream);
+}
+
+// Autotuner: time every (rhs per thread, block size) candidate on scratch fields and keep
+// the fastest for this (precision, nrhs).
+double dslash_tune(lqt_ctx* c, int prec, int nrhs) {
+    const size_t eb = storage_bytes(prec);
+    const long long n = 12LL * c->g.V;
+    DBuf a, b;
+    a.ensure((size_t)n * nrhs * eb);
+    b.ensure((size_t)n * nrhs * eb);
+    LQT_HIP(hipMemsetAsync(a.p, 0, (size_t)n * nrhs * eb, c->stream));
+    const int Rs[3] = {1, 2, 4};
+    const int Bs[3] = {64, 128, 256};
+    hipEvent_t e0, e1;
+    LQT_HIP(hipEventCreate(&e0));
+    LQT_HIP(hipEventCreate(&e1));
+    double best = 1e30;
+    Tuned bt = default_tile(prec, nrhs);
+    for (int ri = 0; ri < 3; ri++) {
+        if (Rs[ri] > nrhs) continue;
+        if (prec == LQT_F64 && Rs[ri] > 2) continue;
+        for (int bi = 0; bi < 3; bi++) {
+            Tuned t{Rs[ri], Bs[bi]};
+            dslash_cfg(c, prec, LQT_A, a.p, b.p, nrhs, n, n, t);  // warm
+            LQT_HIP(hipEventRecord(e0, c->stream));
+            const int reps = 5;
+            for (int k = 0; k < reps; k++) dslash_cfg(c, prec, LQT_A, a.p, b.p, nrhs, n, n, t);
+            LQT_HIP(hipEventRecord(e1, c->stream));
+            LQT_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            LQT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / reps < best) {
+                best = ms / reps;
+                bt = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tuned[tune_key(prec, nrhs)] = bt;
+    return best;
+}
+
+// r = b - A x for nrhs FP64 fields (device layout), rnorm2[r] = |r|^2 (device).
+__global__ void k_sum_partials(const double* __restrict__ part, int nparts, int nrhs, double* __restrict__ out) {
+    __shared__ double red[256];
+    int r = blockIdx.x;
+    double s = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[(long long)r * nparts + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && r < nrhs) out[r] = red[0];
+}
+
+void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, double* rnorm2, int nrhs,
+                const int* act) {
+    if (nrhs <= 0) return;
+    const Geom& g = c->g;
+    const int bs = 256;
+    const int nsb = (g.V + bs - 1) / bs;
+    const long long n = 12LL * g.V;
+    c->scratch[7].ensure(sizeof(double) * (size_t)nsb * nrhs);
+    double* part = c->scratch[7].as<double>();
+    c->timer.begin(c->stream, KT_DSLASH);
+    hipLaunchKernelGGL((k_dslash<double2, 1, false, 1>), dim3(xcd_grid(nsb * nrhs)), dim3(bs), 0, c->stream,
+                       c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.L[0], g.L[1], g.L[2], g.L[3],
+                       4.0 + c->mass, nrhs, n, n, 0, 0);
+    LQT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, c->stream, part, nsb, nrhs, rnorm2);
+    LQT_HIP(hipGetLastError());
+    c->timer.end(c->stream);
+}
+
+}  // namespace lqt

@@ -1,0 +1,42 @@
+// Device state of a batch of restarted GMRES cycles (one entry per slot).
+#pragma once
+#include "lqt_internal.h"
+
+namespace lqt {
+
+constexpr int KRY_MAXM = 64;  // largest restart length
+
+struct KryState {
+    int m;            // restart length
+    double2* H;       // [slot][(m+1)*m]  Hessenberg, overwritten by its QR factor
+    double* cs;       // [slot][m]        Givens cosines
+    double2* sn;      // [slot][m]        Givens sines
+    double2* g;       // [slot][m+1]      rotated right-hand side
+    double* sc;       // [slot][m+1]      scale of each stored basis vector
+    double2* alpha;   // [slot][m+1]      update coefficients of the current step
+    double2* y;       // [slot][m+1]      least-squares solution
+    double2* beta;    // [slot][m+1]      y_i * sc_i
+    double* fac;      // [slot]           write scale of the current step
+    double* nu;       // [slot]
+    double* est;      // [slot]           Arnoldi residual estimate |g_{k}|
+    double* target;   // [slot]           absolute residual target of the cycle
+    int* kdim;        // [slot]           steps taken in the current cycle
+    int* frozen;      // [slot]           1 once the cycle of the slot has ended
+};
+
+template <typename S>
+void kry_dots(lqt_ctx* c, const void* Vb, long long vstride, int j, int ns, double2* part);
+template <typename S>
+void kry_update(lqt_ctx* c, void* Vb, long long vstride, int j, int ns, const KryState& st, int scale, double* part);
+template <typename S>
+void kry_xupdate(lqt_ctx* c, double2* x, const int* act, const void* Zb, long long zstride, int ns,
+                 const KryState& st);
+template <typename S>
+void kry_start(lqt_ctx* c, void* V0, const double2* r, const int* src, const double* rn2, int ns);
+void kry_finish(lqt_ctx* c, const double2* part, int j, int ns, const KryState& st, int pass);
+void kry_norm_givens(lqt_ctx* c, const double* part, int j, int ns, const KryState& st);
+void kry_backsolve(lqt_ctx* c, int ns, const KryState& st);
+void kry_start_state(lqt_ctx* c, const KryState& st, const int* src, const double* rn2, const double* target_abs,
+                     int ns);
+
+}  // namespace lqt

@@ -1,0 +1,402 @@
+// Batched restarted GMRES building blocks (gfx950).
+//
+// A batch of `ns` systems ("slots") advances in lock step.  The Krylov basis of slot q is
+// stored as V[i][q][comp][site] in storage type S.  Stored vectors are not unit vectors:
+// the true basis vector is v_i = sc[i] * vhat_i, and every stored vector is written with
+// norm ~ sqrt(N) so that 16-bit storage neither overflows nor underflows.  With w = A v_j
+// computed on stored vectors (true w = sc_j * what):
+//   d_i        = vhat_i^+ what                         (dot pass, FP32 per lane, FP64 sums)
+//   H[i][j]    = sc_i sc_j d_i
+//   what'      = what - sum_i sc_i^2 d_i vhat_i        (update pass)
+//   nu^2       = |what|^2 - sum_i sc_i^2 |d_i|^2       (used only to pick a write scale)
+//   vhat_{j+1} = what' sqrt(N) / nu,  mu = |vhat_{j+1}|^2 (of the rounded stored values)
+//   sc_{j+1}   = 1/sqrt(mu),  H[j+1][j] = sc_j nu sqrt(mu) / sqrt(N)
+// The Hessenberg matrix is reduced with complex Givens rotations on the device, one
+// thread per slot, so a cycle needs no host round trip except the convergence flag.
+#include "lqt_internal.h"
+#include "krylov.h"
+
+namespace lqt {
+
+template <typename C>
+struct cx {
+    C x, y;
+};
+
+template <typename S, typename C>
+__device__ __forceinline__ cx<C> ldk(const S* p) {
+    if constexpr (sizeof(S) == 16) {
+        double2 v = *(const double2*)p;
+        return {(C)v.x, (C)v.y};
+    } else {
+        float2 v = io<S>::ld(p);
+        return {(C)v.x, (C)v.y};
+    }
+}
+template <typename S, typename C>
+__device__ __forceinline__ cx<C> stk(S* p, cx<C> v) {  // store and return what was stored
+    if constexpr (sizeof(S) == 16) {
+        *(double2*)p = make_double2((double)v.x, (double)v.y);
+        return v;
+    } else {
+        io<S>::st(p, make_float2((float)v.x, (float)v.y));
+        float2 r = io<S>::ld(p);
+        return {(C)r.x, (C)r.y};
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------- dot pass
+// part[(q*nsb + blk)*(j+2) + i]: i <= j: d_i, i = j+1: (|what|^2, 0)
+template <typename S>
+__global__ __launch_bounds__(256) void k_cgs_dots(const S* __restrict__ Vb, long long vstride, int j, int V,
+                                                  double2* __restrict__ part) {
+    using C = typename acc_of<S>::type;
+    __shared__ double red[4][KRY_MAXM + 2][2];
+    const int q = blockIdx.y;
+    const int nsb = gridDim.x;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long n = 12LL * V;
+    const S* w = Vb + (long long)(j + 1) * vstride + q * n;
+    cx<C> wv[12];
+    double nw = 0;
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        wv[c] = s < V ? ldk<S, C>(w + (long long)c * V + s) : cx<C>{0, 0};
+        nw += (double)wv[c].x * wv[c].x + (double)wv[c].y * wv[c].y;
+    }
+    for (int i = 0; i <= j; i++) {
+        const S* vi = Vb + (long long)i * vstride + q * n;
+        C dr = 0, di = 0;
+        if (s < V) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                cx<C> v = ldk<S, C>(vi + (long long)c * V + s);
+                dr += v.x * wv[c].x + v.y * wv[c].y;
+                di += v.x * wv[c].y - v.y * wv[c].x;
+            }
+        }
+        double a = wave_sum((double)dr), b = wave_sum((double)di);
+        if (lane == 0) {
+            red[wave][i][0] = a;
+            red[wave][i][1] = b;
+        }
+    }
+    nw = wave_sum(nw);
+    if (lane == 0) {
+        red[wave][j + 1][0] = nw;
+        red[wave][j + 1][1] = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += 256) {
+        double a = red[0][i][0] + red[1][i][0] + red[2][i][0] + red[3][i][0];
+        double b = red[0][i][1] + red[1][i][1] + red[2][i][1] + red[3][i][1];
+        part[((long long)q * nsb + blockIdx.x) * (j + 2) + i] = make_double2(a, b);
+    }
+}
+
+// One block (64 threads) per slot: finish the sums, fill column j of H, the update
+// coefficients alpha_i = sc_i^2 d_i and the write scale fac = sqrt(N)/nu.
+// pass 0 overwrites H[:, j], pass 1 (re-orthogonalisation) adds to it.
+__global__ void k_cgs_finish(const double2* __restrict__ part, int nsb, int j, KryState st, int pass, double sqrtN) {
+    const int q = blockIdx.x;
+    __shared__ double2 d[KRY_MAXM + 2];
+    for (int i = 0; i <= j + 1; i++) {
+        double a = 0, b = 0;
+        for (int k = threadIdx.x; k < nsb; k += 64) {
+            double2 p = part[((long long)q * nsb + k) * (j + 2) + i];
+            a += p.x;
+            b += p.y;
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (threadIdx.x == 0) d[i] = make_double2(a, b);
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int m = st.m;
+    double* sc = st.sc + (long long)q * (m + 1);
+    double2* H = st.H + (long long)q * (m + 1) * m;
+    double2* alpha = st.alpha + (long long)q * (m + 1);
+    if (st.frozen[q]) {  // cycle of this slot has ended: keep its (unused) vectors finite
+        for (int i = 0; i <= j; i++) alpha[i] = make_double2(0, 0);
+        st.fac[q] = 1.0;
+        st.nu[q] = 1.0;
+        return;
+    }
+    double nu2 = d[j + 1].x;
+    for (int i = 0; i <= j; i++) {
+        double f = sc[i] * sc[j];
+        double2 h = make_double2(f * d[i].x, f * d[i].y);
+        if (pass == 0)
+            H[i * m + j] = h;
+        else
+            H[i * m + j] = make_double2(H[i * m + j].x + h.x, H[i * m + j].y + h.y);
+        double g = sc[i] * sc[i];
+        alpha[i] = make_double2(g * d[i].x, g * d[i].y);
+        nu2 -= g * (d[i].x * d[i].x + d[i].y * d[i].y);
+    }
+    double floor2 = 1e-10 * d[j + 1].x;
+    if (!(nu2 > floor2)) nu2 = floor2 > 0 ? floor2 : 1e-300;
+    st.fac[q] = sqrtN / sqrt(nu2);
+    st.nu[q] = sqrt(nu2);
+}
+
+// ---------------------------------------------------------------------------- update pass
+// what' = what - sum_i alpha_i vhat_i, optionally scaled by fac; partial |stored|^2.
+template <typename S>
+__global__ __launch_bounds__(256) void k_cgs_update(S* __restrict__ Vb, long long vstride, int j, int V, KryState st,
+                                                    int scale, double* __restrict__ part) {
+    using C = typename acc_of<S>::type;
+    __shared__ double red[4];
+    const int q = blockIdx.y;
+    const int nsb = gridDim.x;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const long long n = 12LL * V;
+    const int m = st.m;
+    S* w = Vb + (long long)(j + 1) * vstride + q * n;
+    double nrm = 0;
+    if (s < V) {
+        cx<C> wv[12];
+#pragma unroll
+        for (int c = 0; c < 12; c++) wv[c] = ldk<S, C>(w + (long long)c * V + s);
+        for (int i = 0; i <= j; i++) {
+            double2 a = st.alpha[(long long)q * (m + 1) + i];
+            C ar = (C)a.x, ai = (C)a.y;
+            const S* vi = Vb + (long long)i * vstride + q * n;
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                cx<C> v = ldk<S, C>(vi + (long long)c * V + s);
+                wv[c].x -= ar * v.x - ai * v.y;
+                wv[c].y -= ar * v.y + ai * v.x;
+            }
+        }
+        C f = scale ? (C)st.fac[q] : (C)1;
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            cx<C> o = stk<S, C>(w + (long long)c * V + s, cx<C>{wv[c].x * f, wv[c].y * f});
+            nrm += (double)o.x * o.x + (double)o.y * o.y;
+        }
+    }
+    nrm = wave_sum(nrm);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(long long)q * nsb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// One block (64 threads) per slot: mu, sc_{j+1}, H[j+1][j], then the Givens step.
+__global__ void k_norm_givens(const double* __restrict__ part, int nsb, int j, KryState st, double sqrtN) {
+    const int q = blockIdx.x;
+    double a = 0;
+    for (int k = threadIdx.x; k < nsb; k += 64) a += part[(long long)q * nsb + k];
+    a = wave_sum(a);
+    if (threadIdx.x != 0) return;
+    const int m = st.m;
+    double* sc = st.sc + (long long)q * (m + 1);
+    double2* H = st.H + (long long)q * (m + 1) * m;
+    double* cs = st.cs + (long long)q * m;
+    double2* sn = st.sn + (long long)q * m;
+    double2* g = st.g + (long long)q * (m + 1);
+    if (st.frozen[q]) return;  // this slot's cycle already ended
+    double mu = a;
+    double hn = sc[j] * st.nu[q] * sqrt(mu) / sqrtN;
+    sc[j + 1] = mu > 0 ? 1.0 / sqrt(mu) : 0.0;
+    H[(j + 1) * m + j] = make_double2(hn, 0);
+    // previous rotations on column j: [c s; -conj(s) c]
+    for (int i = 0; i < j; i++) {
+        double2 h0 = H[i * m + j], h1 = H[(i + 1) * m + j];
+        double c = cs[i];
+        double2 s = sn[i];
+        double2 t0 = make_double2(c * h0.x + s.x * h1.x - s.y * h1.y, c * h0.y + s.x * h1.y + s.y * h1.x);
+        double2 t1 = make_double2(-(s.x * h0.x + s.y * h0.y) + c * h1.x, -(s.x * h0.y - s.y * h0.x) + c * h1.y);
+        H[i * m + j] = t0;
+        H[(i + 1) * m + j] = t1;
+    }
+    double2 av = H[j * m + j];
+    double absa = sqrt(av.x * av.x + av.y * av.y);
+    double r = sqrt(absa * absa + hn * hn);
+    double c;
+    double2 s;
+    if (r == 0) {
+        c = 1;
+        s = make_double2(0, 0);
+    } else if (absa == 0) {
+        c = 0;
+        s = make_double2(1, 0);
+    } else {
+        c = absa / r;
+        s = make_double2(av.x / absa * hn / r, av.y / absa * hn / r);
+    }
+    cs[j] = c;
+    sn[j] = s;
+    H[j * m + j] = make_double2(c * av.x + s.x * hn, c * av.y + s.y * hn);
+    H[(j + 1) * m + j] = make_double2(0, 0);
+    double2 g0 = g[j];
+    g[j] = make_double2(c * g0.x, c * g0.y);
+    g[j + 1] = make_double2(-(s.x * g0.x + s.y * g0.y), -(s.x * g0.y - s.y * g0.x));
+    double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
+    st.est[q] = est;
+    st.kdim[q] = j + 1;
+    bool breakdown = !(hn > 1e-300) || !(mu > 0);
+    if (est <= st.target[q] || breakdown || !(est == est)) st.frozen[q] = 1;
+}
+
+// ---------------------------------------------------------------------------- cycle ends
+// Back substitution R y = g and beta_i = y_i sc_i (one thread per slot).
+__global__ void k_backsolve(KryState st, int ns) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ns) return;
+    const int m = st.m;
+    const int k = st.kdim[q];
+    const double2* H = st.H + (long long)q * (m + 1) * m;
+    const double2* g = st.g + (long long)q * (m + 1);
+    const double* sc = st.sc + (long long)q * (m + 1);
+    double2* y = st.y + (long long)q * (m + 1);
+    for (int i = k - 1; i >= 0; i--) {
+        double2 t = g[i];
+        for (int l = i + 1; l < k; l++) {
+            double2 h = H[i * m + l], yl = y[l];
+            t.x -= h.x * yl.x - h.y * yl.y;
+            t.y -= h.x * yl.y + h.y * yl.x;
+        }
+        double2 d = H[i * m + i];
+        double den = d.x * d.x + d.y * d.y;
+        double2 v = den > 0 ? make_double2((t.x * d.x + t.y * d.y) / den, (t.y * d.x - t.x * d.y) / den)
+                            : make_double2(0, 0);
+        y[i] = v;
+    }
+    for (int i = 0; i < k; i++) st.beta[(long long)q * (m + 1) + i] = make_double2(y[i].x * sc[i], y[i].y * sc[i]);
+    for (int i = k; i <= m; i++) st.beta[(long long)q * (m + 1) + i] = make_double2(0, 0);
+}
+
+// x[act[q]] += sum_i beta_i Zhat_i  (FP64 solution, basis in S; Z = V without preconditioner)
+template <typename S>
+__global__ __launch_bounds__(256) void k_xupdate(double2* __restrict__ x, const int* __restrict__ act,
+                                                 const S* __restrict__ Zb, long long zstride, int V, KryState st) {
+    const int q = blockIdx.y;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= V) return;
+    const long long n = 12LL * V;
+    const int m = st.m;
+    const int k = st.kdim[q];
+    double2* xq = x + (long long)act[q] * n;
+    double2 acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = xq[(long long)c * V + s];
+    for (int i = 0; i < k; i++) {
+        double2 b = st.beta[(long long)q * (m + 1) + i];
+        const S* zi = Zb + (long long)i * zstride + q * n;
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            cx<double> v = ldk<S, double>(zi + (long long)c * V + s);
+            acc[c].x += b.x * v.x - b.y * v.y;
+            acc[c].y += b.x * v.y + b.y * v.x;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 12; c++) xq[(long long)c * V + s] = acc[c];
+}
+
+// vhat_0[q] = r[src[q]] * sqrt(N)/|r|, in storage S.  Also resets the slot's cycle state.
+template <typename S>
+__global__ __launch_bounds__(256) void k_start(S* __restrict__ V0, const double2* __restrict__ r,
+                                               const int* __restrict__ src, const double* __restrict__ rn2, int V,
+                                               double sqrtN) {
+    const int q = blockIdx.y;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= V) return;
+    const long long n = 12LL * V;
+    const int sq = src[q];
+    double nr = sqrt(rn2[sq]);
+    double f = nr > 0 ? sqrtN / nr : 0.0;
+    const double2* rq = r + (long long)sq * n;
+    S* vq = V0 + (long long)q * n;
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        double2 v = rq[(long long)c * V + s];
+        stk<S, double>(vq + (long long)c * V + s, cx<double>{v.x * f, v.y * f});
+    }
+}
+
+__global__ void k_start_state(KryState st, const int* __restrict__ src, const double* __restrict__ rn2,
+                              const double* __restrict__ target_abs, int ns, double sqrtN) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ns) return;
+    const int m = st.m;
+    double nr = sqrt(rn2[src[q]]);
+    st.sc[(long long)q * (m + 1)] = 1.0 / sqrtN;
+    st.g[(long long)q * (m + 1)] = make_double2(nr, 0);
+    for (int i = 1; i <= m; i++) st.g[(long long)q * (m + 1) + i] = make_double2(0, 0);
+    st.kdim[q] = 0;
+    st.est[q] = nr;
+    st.frozen[q] = nr > 0 ? 0 : 1;
+    st.target[q] = target_abs[q];
+}
+
+// ---------------------------------------------------------------------------- host side
+template <typename S>
+void kry_dots(lqt_ctx* c, const void* Vb, long long vstride, int j, int ns, double2* part) {
+    dim3 grid((c->g.V + 255) / 256, ns);
+    hipLaunchKernelGGL(k_cgs_dots<S>, grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, j, c->g.V, part);
+    LQT_HIP(hipGetLastError());
+}
+template <typename S>
+void kry_update(lqt_ctx* c, void* Vb, long long vstride, int j, int ns, const KryState& st, int scale, double* part) {
+    dim3 grid((c->g.V + 255) / 256, ns);
+    hipLaunchKernelGGL(k_cgs_update<S>, grid, dim3(256), 0, c->stream, (S*)Vb, vstride, j, c->g.V, st, scale, part);
+    LQT_HIP(hipGetLastError());
+}
+template <typename S>
+void kry_xupdate(lqt_ctx* c, double2* x, const int* act, const void* Zb, long long zstride, int ns,
+                 const KryState& st) {
+    dim3 grid((c->g.V + 255) / 256, ns);
+    hipLaunchKernelGGL(k_xupdate<S>, grid, dim3(256), 0, c->stream, x, act, (const S*)Zb, zstride, c->g.V, st);
+    LQT_HIP(hipGetLastError());
+}
+template <typename S>
+void kry_start(lqt_ctx* c, void* V0, const double2* r, const int* src, const double* rn2, int ns) {
+    dim3 grid((c->g.V + 255) / 256, ns);
+    hipLaunchKernelGGL(k_start<S>, grid, dim3(256), 0, c->stream, (S*)V0, r, src, rn2, c->g.V,
+                       sqrt(12.0 * c->g.V));
+    LQT_HIP(hipGetLastError());
+}
+
+void kry_finish(lqt_ctx* c, const double2* part, int j, int ns, const KryState& st, int pass) {
+    int nsb = (c->g.V + 255) / 256;
+    hipLaunchKernelGGL(k_cgs_finish, dim3(ns), dim3(64), 0, c->stream, part, nsb, j, st, pass, sqrt(12.0 * c->g.V));
+    LQT_HIP(hipGetLastError());
+}
+void kry_norm_givens(lqt_ctx* c, const double* part, int j, int ns, const KryState& st) {
+    int nsb = (c->g.V + 255) / 256;
+    hipLaunchKernelGGL(k_norm_givens, dim3(ns), dim3(64), 0, c->stream, part, nsb, j, st, sqrt(12.0 * c->g.V));
+    LQT_HIP(hipGetLastError());
+}
+void kry_backsolve(lqt_ctx* c, int ns, const KryState& st) {
+    hipLaunchKernelGGL(k_backsolve, dim3((ns + 63) / 64), dim3(64), 0, c->stream, st, ns);
+    LQT_HIP(hipGetLastError());
+}
+void kry_start_state(lqt_ctx* c, const KryState& st, const int* src, const double* rn2, const double* target_abs,
+                     int ns) {
+    hipLaunchKernelGGL(k_start_state, dim3((ns + 63) / 64), dim3(64), 0, c->stream, st, src, rn2, target_abs, ns,
+                       sqrt(12.0 * c->g.V));
+    LQT_HIP(hipGetLastError());
+}
+
+#define INST(S)                                                                                          \
+    template void kry_dots<S>(lqt_ctx*, const void*, long long, int, int, double2*);                     \
+    template void kry_update<S>(lqt_ctx*, void*, long long, int, int, const KryState&, int, double*);    \
+    template void kry_xupdate<S>(lqt_ctx*, double2*, const int*, const void*, long long, int,            \
+                                 const KryState&);                                                      \
+    template void kry_start<S>(lqt_ctx*, void*, const double2*, const int*, const double*, int);
+INST(double2)
+INST(float2)
+INST(h2)
+INST(b2)
+
+}  // namespace lqt

@@ -1,0 +1,333 @@
+// Internal declarations of the lqtrace HIP library (gfx950).
+//
+// Device layouts
+//   gauge   [mu][ab][V]        complex<S>; the antiperiodic -1 is folded into U_t on the
+//                              last time slice (t = Lt-1), so kernels never test borders
+//                              for signs.
+//   fields  [rhs][comp][V]     complex<S>, comp = 3*spin + colour (12 per site); every
+//                              component of every site is one coalesced lane load.
+//   FP64 canonical fields at the boundary are converted to/from this layout on entry.
+// Storage types S: double2, float2, h2 (two FP16), b2 (two BF16).  Arithmetic is FP64 for
+// double2 and FP32 for the others.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lqtrace.h"
+
+namespace lqt {
+
+// ------------------------------------------------------------------ storage types
+struct h2 {
+    __half x, y;
+};
+struct b2 {
+    uint16_t x, y;
+};
+
+template <typename S>
+struct acc_of {
+    using type = float;
+};
+template <>
+struct acc_of<double2> {
+    using type = double;
+};
+
+template <typename C>
+struct cplx2;
+template <>
+struct cplx2<float> {
+    using type = float2;
+};
+template <>
+struct cplx2<double> {
+    using type = double2;
+};
+
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+template <typename S>
+struct io;
+template <>
+struct io<double2> {
+    __device__ __forceinline__ static double2 ld(const double2* p) { return *p; }
+    __device__ __forceinline__ static void st(double2* p, double2 v) { *p = v; }
+};
+template <>
+struct io<float2> {
+    __device__ __forceinline__ static float2 ld(const float2* p) { return *p; }
+    __device__ __forceinline__ static void st(float2* p, float2 v) { *p = v; }
+};
+template <>
+struct io<h2> {
+    __device__ __forceinline__ static float2 ld(const h2* p) {
+        h2 v = *p;
+        return make_float2(__half2float(v.x), __half2float(v.y));
+    }
+    __device__ __forceinline__ static void st(h2* p, float2 v) {
+        h2 o;
+        o.x = __float2half_rn(v.x);
+        o.y = __float2half_rn(v.y);
+        *p = o;
+    }
+};
+template <>
+struct io<b2> {
+    __device__ __forceinline__ static float2 ld(const b2* p) {
+        b2 v = *p;
+        return make_float2(bf16_to_f(v.x), bf16_to_f(v.y));
+    }
+    __device__ __forceinline__ static void st(b2* p, float2 v) {
+        b2 o;
+        o.x = f_to_bf16(v.x);
+        o.y = f_to_bf16(v.y);
+        *p = o;
+    }
+};
+
+inline size_t storage_bytes(int prec) {
+    switch (prec) {
+        case LQT_F64: return 16;
+        case LQT_F32: return 8;
+        default: return 4;
+    }
+}
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int L[4];
+    int V;  // sites (fits 32 bits up to 64^3x128)
+};
+
+// XCD-aware block order: hardware hands consecutive workgroup ids to the 8 XCDs in turn;
+// remapping gives each XCD one contiguous range of logical blocks so neighbouring sites
+// (and the links they share) stay in one L2.
+__device__ __forceinline__ int xcd_block(int nlogical) {
+    int b = blockIdx.x;
+    int per = (nlogical + 7) >> 3;
+    int l = (b & 7) * per + (b >> 3);
+    return l < nlogical ? l : -1;
+}
+inline int xcd_grid(int nlogical) { return ((nlogical + 7) >> 3) << 3; }
+
+// ------------------------------------------------------------------ error handling
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define LQT_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw ::lqt::Error{LQT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define LQT_CHECK(cond, code, msg)                           \
+    do {                                                     \
+        if (!(cond)) throw ::lqt::Error{(code), (msg)};      \
+    } while (0)
+
+// Device buffer that frees itself.
+struct DBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void ensure(size_t bytes) {
+        if (bytes <= n) return;
+        reset();
+        if (bytes == 0) return;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error{LQT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+        }
+        n = bytes;
+    }
+    template <typename T>
+    T* as() const {
+        return (T*)p;
+    }
+};
+
+// Pinned host buffer.
+struct HBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    HBuf() = default;
+    HBuf(const HBuf&) = delete;
+    HBuf& operator=(const HBuf&) = delete;
+    ~HBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void ensure(size_t bytes) {
+        if (bytes <= n) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess)
+            throw Error{LQT_ENOMEM, "hipHostMalloc failed"};
+        n = bytes;
+    }
+    template <typename T>
+    T* as() const {
+        return (T*)p;
+    }
+};
+
+// Kernel-family timers (HIP events on the context stream).
+enum { KT_DSLASH = 0, KT_ORTH = 1, KT_BLAS = 2, KT_PROJ = 3 };
+
+// Non-blocking kernel timer: event pairs recorded around launches on the context stream,
+// folded into per-family totals only when the pool fills or the totals are read.
+struct KTimer {
+    static constexpr int POOL = 2048;
+    bool on = false;
+    std::vector<hipEvent_t> e0, e1;
+    std::vector<int> fam;
+    int used = 0;
+    int open_fam = -1;
+    double ms[4] = {0, 0, 0, 0};
+    long long calls[4] = {0, 0, 0, 0};
+    void init() {
+        if (!e0.empty()) return;
+        e0.resize(POOL);
+        e1.resize(POOL);
+        fam.resize(POOL);
+        for (int i = 0; i < POOL; i++) {
+            (void)hipEventCreate(&e0[i]);
+            (void)hipEventCreate(&e1[i]);
+        }
+    }
+    void destroy() {
+        for (size_t i = 0; i < e0.size(); i++) {
+            (void)hipEventDestroy(e0[i]);
+            (void)hipEventDestroy(e1[i]);
+        }
+        e0.clear();
+        e1.clear();
+    }
+    void flush() {
+        if (used == 0) return;
+        (void)hipEventSynchronize(e1[used - 1]);
+        for (int i = 0; i < used; i++) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, e0[i], e1[i]) == hipSuccess) {
+                ms[fam[i]] += t;
+                calls[fam[i]] += 1;
+            }
+        }
+        used = 0;
+    }
+    void begin(hipStream_t s, int f) {
+        if (!on) return;
+        if (used == POOL) flush();
+        (void)hipEventRecord(e0[used], s);
+        fam[used] = f;
+        open_fam = f;
+    }
+    void end(hipStream_t s) {
+        if (!on || open_fam < 0) return;
+        (void)hipEventRecord(e1[used], s);
+        used++;
+        open_fam = -1;
+    }
+    void reset() {
+        flush();
+        for (int i = 0; i < 4; i++) ms[i] = 0, calls[i] = 0;
+    }
+};
+
+struct Tuned {
+    int rhs_per_thread;
+    int block;
+};
+
+struct Net {
+    bool set = false;
+    int feats[5] = {4, 8, 8, 4, 0};
+    std::vector<float> w;  // complex FP32 weights, host copy
+    DBuf wd;               // BF16 weights on device (complex pairs)
+    DBuf wf;               // FP32 weights on device
+};
+
+}  // namespace lqt
+
+struct lqt_ctx {
+    lqt::Geom g;
+    long long N;  // 12 V
+    double mass;
+    int antiperiodic;
+    hipStream_t stream;
+    int device;
+    std::string err;
+    bool have_gauge = false;
+    lqt::DBuf U[4];  // gauge per precision (LQT_F64 .. LQT_BF16)
+    lqt::DBuf scratch[8];
+    lqt::HBuf pinned;
+    std::map<long long, lqt::Tuned> tuned;
+    lqt::KTimer timer;
+    lqt::Net net;
+    double sigma_max = 0;  // power-iteration estimate, filled on demand
+};
+
+struct lqt_basis {
+    lqt_ctx* ctx;
+    int k = 0;
+    int kind = 0;               // 0: fine vectors, 1: prolongator
+    lqt::DBuf U;                // k fine vectors, device layout FP64 [k][12][V]
+    std::vector<double> lambda; // 2k (complex) eigenvalues of U^+ g5 A U, ascending |.|
+    std::vector<double> ug5u;   // 2k: u_i^+ g5 u_i
+    bool orthonormal = false;
+    // prolongator data
+    int block[4] = {0, 0, 0, 0};
+    int nv = 0;
+    int nagg = 0;
+    lqt::DBuf W;  // [agg][chi][nv][bsites][2][3] complex double
+    lqt::DBuf Wf; // FP32 copy
+    lqt::DBuf Uc; // coarse eigenvectors (k x Nc) FP64
+};
+
+namespace lqt {
+
+// ---- layout (layout.hip)
+void gauge_upload(lqt_ctx* c, const double* links, int on_device, double* max_unit_err, double* max_det_err);
+void to_device_layout(lqt_ctx* c, const double2* canon, double2* dev, int nrhs);
+void from_device_layout(lqt_ctx* c, const double2* dev, double2* canon, int nrhs);
+template <typename S>
+void convert_in_c64(lqt_ctx* c, const float2* canon, S* dev, int nrhs);
+template <typename S>
+void convert_out_c64(lqt_ctx* c, const S* dev, float2* canon, int nrhs);
+
+// ---- dslash (dslash.hip): out = op(in), device layout, nrhs fields
+void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long in_stride,
+            long long out_stride);
+double dslash_tune(lqt_ctx* c, int prec, int nrhs);
+// FP64 residual r = b - A x for nrhs fields and squared norms (device layout FP64).
+// act maps slot -> field index (nullptr = identity).
+// act (device, may be null) maps slot -> field index of b and x; r is slot-ordered.
+void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, double* rnorm2, int nrhs,
+                const int* act = nullptr);
+
+}  // namespace lqt

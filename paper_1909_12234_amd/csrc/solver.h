@@ -1,0 +1,23 @@
+// Inexact solves A^{-1}_xi on device-layout FP64 fields.
+#pragma once
+#include "lqt_internal.h"
+
+namespace lqt {
+
+struct SolveOpts {
+    int prec = LQT_F64;
+    int restart = 32;
+    int maxit = 100000;
+    int use_net = 0;
+    int max_batch = 0;
+    int cgs2 = 0;
+    double inner_tol = 0.0;
+};
+
+SolveOpts make_opts(const lqt_solver_opts* u);
+
+// x = A^{-1}_xi b for nrhs fields; returns the number of systems that missed xi.
+int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, const SolveOpts& o,
+                 lqt_solve_stats* stats);
+
+}  // namespace lqt

@@ -1,0 +1,247 @@
+// Inexact solves A^{-1}_xi (Section 1: stop when ||A y - x|| <= xi ||x||).
+//
+// Restarted GMRES(m) over a batch of right-hand sides.  Each restart is an FP64 defect
+// correction step: r = b - A x is recomputed with the FP64 operator and tested against
+// xi ||b||; the following cycle of at most m Arnoldi steps runs on r / ||r|| with links
+// and Krylov vectors in the inner storage precision (FP64, FP32, FP16 or BF16) and
+// FP32 (FP64 for FP64 storage) arithmetic, and its correction is added to x in FP64.
+// With FP64 storage this is plain restarted GMRES(m).  Systems that converge leave the
+// batch at the next restart, so the remaining ones stay contiguous.
+#include <algorithm>
+#include <cmath>
+
+#include "blas.h"
+#include "krylov.h"
+#include "lqt_internal.h"
+#include "solver.h"
+
+namespace lqt {
+
+namespace {
+
+struct StateBuf {
+    KryState st;
+    void carve(DBuf& buf, int ns, int m) {
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off += (bytes + 255) & ~size_t(255);
+            return o;
+        };
+        size_t oH = take(sizeof(double2) * ns * (m + 1) * m), ocs = take(sizeof(double) * ns * m),
+               osn = take(sizeof(double2) * ns * m), og = take(sizeof(double2) * ns * (m + 1)),
+               osc = take(sizeof(double) * ns * (m + 1)), oal = take(sizeof(double2) * ns * (m + 1)),
+               oy = take(sizeof(double2) * ns * (m + 1)), obe = take(sizeof(double2) * ns * (m + 1)),
+               ofa = take(sizeof(double) * ns), onu = take(sizeof(double) * ns), oes = take(sizeof(double) * ns),
+               ota = take(sizeof(double) * ns), okd = take(sizeof(int) * ns), ofr = take(sizeof(int) * ns);
+        buf.ensure(off);
+        char* b = (char*)buf.p;
+        st.m = m;
+        st.H = (double2*)(b + oH);
+        st.cs = (double*)(b + ocs);
+        st.sn = (double2*)(b + osn);
+        st.g = (double2*)(b + og);
+        st.sc = (double*)(b + osc);
+        st.alpha = (double2*)(b + oal);
+        st.y = (double2*)(b + oy);
+        st.beta = (double2*)(b + obe);
+        st.fac = (double*)(b + ofa);
+        st.nu = (double*)(b + onu);
+        st.est = (double*)(b + oes);
+        st.target = (double*)(b + ota);
+        st.kdim = (int*)(b + okd);
+        st.frozen = (int*)(b + ofr);
+    }
+};
+
+template <typename S>
+void kry_step_orth(lqt_ctx* c, void* basis, long long vstride, int j, int na, const KryState& st, bool cgs2,
+                   double2* part, double* partn) {
+    c->timer.begin(c->stream, KT_ORTH);
+    kry_dots<S>(c, basis, vstride, j, na, part);
+    kry_finish(c, part, j, na, st, 0);
+    if (cgs2) {
+        kry_update<S>(c, basis, vstride, j, na, st, 0, partn);
+        kry_dots<S>(c, basis, vstride, j, na, part);
+        kry_finish(c, part, j, na, st, 1);
+    }
+    kry_update<S>(c, basis, vstride, j, na, st, 1, partn);
+    kry_norm_givens(c, partn, j, na, st);
+    c->timer.end(c->stream);
+}
+
+// Solve nb systems b[0..nb) -> x[0..nb) (device layout FP64, contiguous).
+template <typename S>
+int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, double xi, const SolveOpts& o,
+                lqt_solve_stats* stats) {
+    const long long n = 12LL * c->g.V;
+    const int m = o.restart;
+    const size_t eb = sizeof(S);
+    const int nsb = (c->g.V + 255) / 256;
+
+    DBuf& basisb = c->scratch[0];
+    DBuf& rb = c->scratch[1];
+    DBuf& stb = c->scratch[2];
+    DBuf& partb = c->scratch[3];
+    DBuf& partnb = c->scratch[4];
+    basisb.ensure((size_t)(m + 1) * nb * n * eb);
+    rb.ensure((size_t)nb * n * sizeof(double2) + 4 * 256 * (size_t)nb);
+    StateBuf sb;
+    sb.carve(stb, nb, m);
+    partb.ensure(sizeof(double2) * (size_t)nb * nsb * (m + 2));
+    partnb.ensure(sizeof(double) * (size_t)nb * nsb + sizeof(double) * 2 * nb + sizeof(int) * 2 * nb +
+                  sizeof(double) * nb + 1024);
+
+    double2* r = rb.as<double2>();
+    char* extra = (char*)partnb.p + sizeof(double) * (size_t)nb * nsb;
+    double* rn2 = (double*)extra;
+    double* bn2 = rn2 + nb;
+    int* act_d = (int*)(bn2 + nb);
+    int* src_d = act_d + nb;
+    double* tgt_d = (double*)(((uintptr_t)(src_d + nb) + 7) & ~uintptr_t(7));
+    double* partn = partnb.as<double>();
+    double2* part = partb.as<double2>();
+    void* basis = basisb.p;
+
+    c->pinned.ensure(sizeof(double) * 4 * (size_t)nb + 64);
+    double* h_rn2 = c->pinned.as<double>();
+    int* h_flags = (int*)(h_rn2 + nb);
+
+    std::vector<double> bnorm(nb);
+    c->timer.begin(c->stream, KT_BLAS);
+    norm2_fields(c, b, nb, bn2);
+    LQT_HIP(hipMemsetAsync(x, 0, sizeof(double2) * (size_t)nb * n, c->stream));
+    c->timer.end(c->stream);
+    LQT_HIP(hipMemcpyAsync(h_rn2, bn2, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+    LQT_HIP(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < nb; i++) bnorm[i] = std::sqrt(h_rn2[i]);
+
+    std::vector<int> act(nb), its(nb, 0), cyc(nb, 0), done(nb, 0);
+    std::vector<double> rel(nb, 1.0);
+    for (int i = 0; i < nb; i++) act[i] = i;
+    int nfail = 0;
+    const double sqrtN = std::sqrt((double)n);
+    (void)sqrtN;
+
+    while (!act.empty()) {
+        const int na = (int)act.size();
+        LQT_HIP(hipMemcpyAsync(act_d, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
+        residual64(c, b, x, r, rn2, na, act_d);
+        LQT_HIP(hipMemcpyAsync(h_rn2, rn2, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream));
+        LQT_HIP(hipStreamSynchronize(c->stream));
+        std::vector<int> nact, src;
+        std::vector<double> tgt;
+        for (int k = 0; k < na; k++) {
+            const int i = act[k];
+            cyc[i]++;
+            double rr = std::sqrt(h_rn2[k]);
+            rel[i] = bnorm[i] > 0 ? rr / bnorm[i] : 0.0;
+            if (!(rel[i] == rel[i])) {
+                done[i] = 1;
+                nfail++;
+                continue;
+            }
+            if (rel[i] <= xi) {
+                done[i] = 1;
+                continue;
+            }
+            if (its[i] >= o.maxit) {
+                done[i] = 1;
+                nfail++;
+                continue;
+            }
+            nact.push_back(i);
+            src.push_back(k);
+            tgt.push_back(std::max(xi * bnorm[i], o.inner_tol * rr));
+        }
+        if (nact.empty()) break;
+        const int nn = (int)nact.size();
+        // new active list; src maps new slot -> slot of r
+        LQT_HIP(hipMemcpyAsync(act_d, nact.data(), sizeof(int) * nn, hipMemcpyHostToDevice, c->stream));
+        LQT_HIP(hipMemcpyAsync(src_d, src.data(), sizeof(int) * nn, hipMemcpyHostToDevice, c->stream));
+        LQT_HIP(hipMemcpyAsync(tgt_d, tgt.data(), sizeof(double) * nn, hipMemcpyHostToDevice, c->stream));
+        const long long vstride = (long long)nn * n;
+        c->timer.begin(c->stream, KT_BLAS);
+        kry_start_state(c, sb.st, src_d, rn2, tgt_d, nn);
+        kry_start<S>(c, basis, r, src_d, rn2, nn);
+        c->timer.end(c->stream);
+        for (int j = 0; j < m; j++) {
+            const void* vj = (const char*)basis + (size_t)j * vstride * eb;
+            void* vj1 = (char*)basis + (size_t)(j + 1) * vstride * eb;
+            dslash(c, prec, LQT_A, vj, vj1, nn, n, n);
+            kry_step_orth<S>(c, basis, vstride, j, nn, sb.st, o.cgs2 != 0, part, partn);
+            if (j + 1 < m) {
+                LQT_HIP(hipMemcpyAsync(h_flags, sb.st.frozen, sizeof(int) * nn, hipMemcpyDeviceToHost, c->stream));
+                LQT_HIP(hipStreamSynchronize(c->stream));
+                bool all = true;
+                for (int k = 0; k < nn; k++) all = all && h_flags[k];
+                if (all) break;
+            }
+        }
+        c->timer.begin(c->stream, KT_BLAS);
+        kry_backsolve(c, nn, sb.st);
+        kry_xupdate<S>(c, x, act_d, basis, vstride, nn, sb.st);
+        c->timer.end(c->stream);
+        LQT_HIP(hipMemcpyAsync(h_flags, sb.st.kdim, sizeof(int) * nn, hipMemcpyDeviceToHost, c->stream));
+        LQT_HIP(hipStreamSynchronize(c->stream));
+        for (int k = 0; k < nn; k++) its[nact[k]] += h_flags[k];
+        act = nact;
+    }
+    if (stats)
+        for (int i = 0; i < nb; i++) {
+            stats[i].converged = (rel[i] <= xi) ? 1 : 0;
+            stats[i].iters = its[i];
+            stats[i].cycles = cyc[i];
+            stats[i].relres = rel[i];
+        }
+    return nfail;
+}
+
+}  // namespace
+
+SolveOpts make_opts(const lqt_solver_opts* u) {
+    SolveOpts o;
+    if (u) {
+        o.prec = u->inner_prec;
+        o.restart = u->restart > 0 ? u->restart : 32;
+        o.maxit = u->maxit > 0 ? u->maxit : 100000;
+        o.use_net = u->use_net;
+        o.max_batch = u->max_batch;
+        o.cgs2 = u->cgs2;
+        o.inner_tol = u->inner_tol > 0 ? u->inner_tol : 0.0;
+    }
+    return o;
+}
+
+int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, const SolveOpts& o,
+                 lqt_solve_stats* stats) {
+    LQT_CHECK(o.restart >= 1 && o.restart <= KRY_MAXM, LQT_EINVAL, "restart must be in 1..64");
+    LQT_CHECK(o.prec >= LQT_F64 && o.prec <= LQT_BF16, LQT_EINVAL, "bad inner precision");
+    LQT_CHECK(xi > 0, LQT_EINVAL, "tolerance must be positive");
+    const long long n = 12LL * c->g.V;
+    // batch size: caller cap, else what fits in 70% of free device memory
+    size_t fr = 0, tot = 0;
+    LQT_HIP(hipMemGetInfo(&fr, &tot));
+    size_t per = (size_t)(o.restart + 1) * n * storage_bytes(o.prec) + (size_t)n * 16 * 2 +
+                 (size_t)((c->g.V + 255) / 256) * (o.restart + 2) * 16;
+    size_t have = (size_t)(0.7 * (double)(fr + c->scratch[0].n + c->scratch[1].n + c->scratch[3].n));
+    int fit = (int)std::max<size_t>(1, have / per);
+    int batch = o.max_batch > 0 ? o.max_batch : nrhs;
+    batch = std::min(batch, fit);
+    int nfail = 0;
+    for (int b0 = 0; b0 < nrhs; b0 += batch) {
+        int nb = std::min(batch, nrhs - b0);
+        const double2* bb = b + (size_t)b0 * n;
+        double2* xx = x + (size_t)b0 * n;
+        lqt_solve_stats* ss = stats ? stats + b0 : nullptr;
+        switch (o.prec) {
+            case LQT_F64: nfail += solve_batch<double2>(c, o.prec, bb, xx, nb, xi, o, ss); break;
+            case LQT_F32: nfail += solve_batch<float2>(c, o.prec, bb, xx, nb, xi, o, ss); break;
+            case LQT_F16: nfail += solve_batch<h2>(c, o.prec, bb, xx, nb, xi, o, ss); break;
+            default: nfail += solve_batch<b2>(c, o.prec, bb, xx, nb, xi, o, ss); break;
+        }
+    }
+    return nfail;
+}
+
+}  // namespace lqt

@@ -1,0 +1,349 @@
+"""Thin ctypes binding of liblqtrace (include/lqtrace.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.  Torch tensors
+provide device memory and the HIP stream; fields are complex128 tensors in the canonical
+layout (nrhs, Lt, Lz, Ly, Lx, 4, 3) or flattened (nrhs, 12*V).  The library must have been
+built (python -m paper_1909_12234_amd.build); importing this module raises if it has not.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblqtrace.so")
+
+LQT_OK, LQT_EINVAL, LQT_ENOMEM, LQT_EHIP, LQT_ENOTCONV, LQT_ENOTUNITARY, LQT_ESTATE, LQT_ENAN = 0, -1, -2, -3, -4, -5, -6, -7
+A, A_DAG, A_G5, G5_A = 0, 1, 2, 3
+F64, F32, F16, BF16 = 0, 1, 2, 3
+OBLIQUE_G5, ORTH = 0, 1
+
+ERROR_NAMES = {0: "LQT_OK", -1: "LQT_EINVAL", -2: "LQT_ENOMEM", -3: "LQT_EHIP", -4: "LQT_ENOTCONV",
+               -5: "LQT_ENOTUNITARY", -6: "LQT_ESTATE", -7: "LQT_ENAN"}
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("inner_prec", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("use_net", ctypes.c_int), ("max_batch", ctypes.c_int), ("cgs2", ctypes.c_int),
+                ("inner_tol", ctypes.c_double)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int), ("iters", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("relres", ctypes.c_double)]
+
+
+class TraceResult(ctypes.Structure):
+    _fields_ = [("trace_re", ctypes.c_double), ("trace_im", ctypes.c_double), ("t0_re", ctypes.c_double),
+                ("t0_im", ctypes.c_double), ("var_sample", ctypes.c_double), ("var_mean", ctypes.c_double),
+                ("jackknife_err", ctypes.c_double), ("var_re_only", ctypes.c_double), ("nsolves", ctypes.c_int),
+                ("nfailed", ctypes.c_int), ("iters_total", ctypes.c_longlong), ("seconds_solve", ctypes.c_double),
+                ("seconds_setup", ctypes.c_double)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("lr", ctypes.c_double), ("pair_iters", ctypes.c_int)]
+
+
+class LqtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIGS = {
+    "lqt_create": ([ctypes.POINTER(_P), _P, _D, _I, _P], _I),
+    "lqt_set_gauge": ([_P, _P, _I], _I),
+    "lqt_set_mass": ([_P, _D], _I),
+    "lqt_apply": ([_P, _I, _I, _P, _P, _I], _I),
+    "lqt_solve": ([_P, _P, _P, _I, _D, _P, _P], _I),
+    "lqt_basis_eig": ([_P, _I, _D, _D, _P, ctypes.POINTER(_P)], _I),
+    "lqt_basis_prolongator": ([_P, _P, _I, _I, _D, _I, _P, ctypes.POINTER(_P)], _I),
+    "lqt_basis_from_vectors": ([_P, _P, _I, ctypes.POINTER(_P)], _I),
+    "lqt_basis_eigenvalues": ([_P, _P, ctypes.POINTER(_I)], _I),
+    "lqt_basis_vectors": ([_P, _P], _I),
+    "lqt_basis_free": ([_P], None),
+    "lqt_precond_set": ([_P, _P, ctypes.c_size_t], _I),
+    "lqt_precond_get": ([_P, _P, ctypes.c_size_t], _I),
+    "lqt_precond_apply": ([_P, _P, _P, _I], _I),
+    "lqt_precond_train": ([_P, _I, ctypes.c_uint64, _P, _P], _I),
+    "lqt_trace": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _P, _P, _P, _P], _I),
+    "lqt_probes": ([_P, ctypes.c_uint64, ctypes.c_longlong, _I, _P], _I),
+    "lqt_gram": ([_P, _P, _I, _P, _I, _P], _I),
+    "lqt_project_probes": ([_P, _P, _I, ctypes.c_uint64, ctypes.c_longlong, _I, _P, _P], _I),
+    "lqt_combine": ([_P, _P, _I, _P, _I, _D, _D, _P], _I),
+    "lqt_restrict": ([_P, _P, _P, _P, _I], _I),
+    "lqt_prolong": ([_P, _P, _P, _P, _I], _I),
+    "lqt_prolongator_get": ([_P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
+    "lqt_basis_prolongator_from": ([_P, _P, _I, _P, ctypes.POINTER(_P)], _I),
+    "lqt_tune": ([_P, _I, _I, ctypes.POINTER(_D)], _I),
+    "lqt_kernel_times": ([_P, _P, _P, _I], _I),
+    "lqt_last_error": ([_P], ctypes.c_char_p),
+    "lqt_destroy": ([_P], None),
+}
+
+
+def lib():
+    """Load liblqtrace.so; raises when it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1909_12234_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0):
+    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol)
+
+
+class Context:
+    """A lattice, its gauge field and the mass, bound to the current torch HIP stream."""
+
+    def __init__(self, dims, mass, antiperiodic=True, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.N = 12 * self.V
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = ctypes.c_void_p()
+        d = (ctypes.c_int * 4)(*self.dims)
+        rc = lib().lqt_create(ctypes.byref(self._h), d, float(mass), int(antiperiodic),
+                              ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise LqtError(rc, "lqt_create failed")
+
+    # -- plumbing
+    def _check(self, rc, allow=()):
+        if rc != 0 and rc not in allow:
+            raise LqtError(rc, lib().lqt_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if self._h:
+            lib().lqt_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def field(self, nrhs, dtype=torch.complex128):
+        return torch.zeros((nrhs, self.N), dtype=dtype, device="cuda")
+
+    # -- operator
+    def set_gauge(self, links):
+        """links: complex128 array/tensor (Lt, Lz, Ly, Lx, 4, 3, 3) on host or device."""
+        t = torch.as_tensor(links)
+        if t.dtype != torch.complex128:
+            raise TypeError("links must be complex128")
+        t = t.contiguous()
+        on_dev = 1 if t.is_cuda else 0
+        return self._check(lib().lqt_set_gauge(self._h, _ptr(t), on_dev))
+
+    def set_mass(self, mass):
+        return self._check(lib().lqt_set_mass(self._h, float(mass)))
+
+    def apply(self, x, op=A, prec=F64):
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        nrhs = x.numel() // self.N
+        self._check(lib().lqt_apply(self._h, int(op), int(prec), _ptr(x), _ptr(out), nrhs))
+        return out
+
+    def solve(self, b, xi, raise_on_fail=True, **opts):
+        b = b.contiguous()
+        x = torch.empty_like(b)
+        nrhs = b.numel() // self.N
+        st = (SolveStats * max(nrhs, 1))()
+        o = _opts(**opts)
+        rc = lib().lqt_solve(self._h, _ptr(b), _ptr(x), nrhs, float(xi), ctypes.byref(o), st)
+        self._check(rc, allow=() if raise_on_fail else (LQT_ENOTCONV,))
+        return x, [(s.converged, s.iters, s.cycles, s.relres) for s in st[:nrhs]], rc
+
+    def probes(self, seed, nprobes, j0=0):
+        out = torch.empty((nprobes, self.N), dtype=torch.complex128, device="cuda")
+        self._check(lib().lqt_probes(self._h, ctypes.c_uint64(seed), int(j0), int(nprobes), _ptr(out)))
+        return out
+
+    def tune(self, prec, nrhs):
+        ms = ctypes.c_double(0)
+        self._check(lib().lqt_tune(self._h, int(prec), int(nrhs), ctypes.byref(ms)))
+        return ms.value
+
+    def kernel_times(self, mode=0):
+        ms = (ctypes.c_double * 4)()
+        calls = (ctypes.c_longlong * 4)()
+        self._check(lib().lqt_kernel_times(self._h, ms, calls, int(mode)))
+        return list(ms), list(calls)
+
+    # -- dense building blocks
+    def gram(self, X, Y):
+        ka, kb = X.shape[0], Y.shape[0]
+        X, Y = X.contiguous(), Y.contiguous()
+        out = torch.empty((ka, kb), dtype=torch.complex128)
+        self._check(lib().lqt_gram(self._h, _ptr(X), ka, _ptr(Y), kb, _ptr(out)))
+        return out
+
+    def project_probes(self, X, seed, j0, s):
+        ka = X.shape[0]
+        X = X.contiguous()
+        cup = torch.empty((ka, s), dtype=torch.complex128)
+        cdn = torch.empty((ka, s), dtype=torch.complex128)
+        self._check(lib().lqt_project_probes(self._h, _ptr(X), ka, ctypes.c_uint64(seed), int(j0), int(s),
+                                             _ptr(cup), _ptr(cdn)))
+        return cup, cdn
+
+    def combine(self, X, C, Y=None, beta=0.0, alpha=1.0):
+        ka, kb = C.shape
+        X = X.contiguous()
+        C = torch.as_tensor(C, dtype=torch.complex128).contiguous().cpu()
+        if Y is None:
+            Y = torch.zeros((kb, self.N), dtype=torch.complex128, device="cuda")
+        self._check(lib().lqt_combine(self._h, _ptr(X), ka, _ptr(C), kb, float(beta), float(alpha), _ptr(Y)))
+        return Y
+
+    # -- deflation bases
+    def basis_eig(self, k, xi=1e-2, tau=0.0, **opts):
+        h = ctypes.c_void_p()
+        o = _opts(**opts)
+        self._check(lib().lqt_basis_eig(self._h, int(k), float(xi), float(tau), ctypes.byref(o), ctypes.byref(h)))
+        return Basis(self, h)
+
+    def basis_prolongator(self, block, nv, k, null_xi=1e-2, null_maxit=200, **opts):
+        h = ctypes.c_void_p()
+        o = _opts(**opts)
+        b = (ctypes.c_int * 4)(*block)
+        self._check(lib().lqt_basis_prolongator(self._h, b, int(nv), int(k), float(null_xi), int(null_maxit),
+                                                ctypes.byref(o), ctypes.byref(h)))
+        return Basis(self, h, nv=nv)
+
+    def basis_prolongator_from(self, block, nv, W):
+        h = ctypes.c_void_p()
+        b = (ctypes.c_int * 4)(*block)
+        W = W.contiguous()
+        self._check(lib().lqt_basis_prolongator_from(self._h, b, int(nv), _ptr(W), ctypes.byref(h)))
+        return Basis(self, h, nv=nv)
+
+    def basis_from_vectors(self, X):
+        h = ctypes.c_void_p()
+        X = X.contiguous()
+        self._check(lib().lqt_basis_from_vectors(self._h, _ptr(X), int(X.shape[0]), ctypes.byref(h)))
+        return Basis(self, h)
+
+    # -- learned preconditioner
+    def precond_set(self, weights):
+        w = torch.as_tensor(weights, dtype=torch.complex64).contiguous().cpu()
+        return self._check(lib().lqt_precond_set(self._h, _ptr(w), w.numel() * 8))
+
+    def precond_get(self):
+        w = torch.empty(1728, dtype=torch.complex64)
+        self._check(lib().lqt_precond_get(self._h, _ptr(w), w.numel() * 8))
+        return w
+
+    def precond_apply(self, x):
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        self._check(lib().lqt_precond_apply(self._h, _ptr(x), _ptr(out), x.numel() // self.N))
+        return out
+
+    def precond_train(self, npairs, seed, epochs=4, lr=1e-3, pair_iters=64):
+        o = TrainOpts(epochs, lr, pair_iters)
+        loss = ctypes.c_double(0)
+        self._check(lib().lqt_precond_train(self._h, int(npairs), ctypes.c_uint64(seed), ctypes.byref(o),
+                                            ctypes.byref(loss)))
+        return loss.value
+
+    # -- trace
+    def trace(self, nprobes, seed, xi, basis=None, projector=OBLIQUE_G5, rank_curve=False, samples=False,
+              raise_on_fail=True, **opts):
+        res = TraceResult()
+        o = _opts(**opts)
+        k = basis.k if basis is not None else 0
+        curve = torch.zeros((k + 1, 3), dtype=torch.float64) if rank_curve else None
+        samp = torch.zeros(nprobes, dtype=torch.complex128) if samples else None
+        rc = lib().lqt_trace(self._h, basis._h if basis is not None else None, int(projector), int(nprobes),
+                             ctypes.c_uint64(seed), float(xi), ctypes.byref(o), ctypes.byref(res), _ptr(curve),
+                             _ptr(samp))
+        self._check(rc, allow=() if raise_on_fail else (LQT_ENOTCONV,))
+        out = {f: getattr(res, f) for f, _ in TraceResult._fields_}
+        out["rc"] = rc
+        if rank_curve:
+            out["rank_curve"] = curve
+        if samples:
+            out["samples"] = samp
+        return out
+
+
+class Basis:
+    def __init__(self, ctx, handle, nv=0):
+        self.ctx = ctx
+        self._h = handle
+        self.nv = nv
+        k = ctypes.c_int(0)
+        ctx._check(lib().lqt_basis_eigenvalues(self._h, None, ctypes.byref(k)))
+        self.k = k.value
+
+    def eigenvalues(self):
+        lam = torch.empty(self.k, dtype=torch.complex128)
+        k = ctypes.c_int(0)
+        self.ctx._check(lib().lqt_basis_eigenvalues(self._h, _ptr(lam), ctypes.byref(k)))
+        return lam
+
+    def vectors(self):
+        out = torch.empty((self.k, self.ctx.N), dtype=torch.complex128, device="cuda")
+        self.ctx._check(lib().lqt_basis_vectors(self._h, _ptr(out)))
+        return out
+
+    def restrict(self, fine):
+        fine = fine.contiguous()
+        nrhs = fine.numel() // self.ctx.N
+        nc = ctypes.c_longlong(0)
+        self.ctx._check(lib().lqt_prolongator_get(self._h, None, ctypes.byref(nc)))
+        out = torch.empty((nrhs, nc.value), dtype=torch.complex128, device="cuda")
+        self.ctx._check(lib().lqt_restrict(self.ctx._h, self._h, _ptr(fine), _ptr(out), nrhs))
+        return out
+
+    def prolong(self, coarse):
+        coarse = coarse.contiguous()
+        nrhs = coarse.shape[0]
+        out = torch.empty((nrhs, self.ctx.N), dtype=torch.complex128, device="cuda")
+        self.ctx._check(lib().lqt_prolong(self.ctx._h, self._h, _ptr(coarse), _ptr(out), nrhs))
+        return out
+
+    def prolongator(self):
+        """W as a flat complex128 device tensor of nv*N entries (layout in the header)."""
+        nc = ctypes.c_longlong(0)
+        W = torch.empty(self.nv * self.ctx.N, dtype=torch.complex128, device="cuda")
+        self.ctx._check(lib().lqt_prolongator_get(self._h, _ptr(W), ctypes.byref(nc)))
+        return W
+
+    def close(self):
+        if self._h:
+            lib().lqt_basis_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
