@@ -1,0 +1,181 @@
+"""Benchmark: Rademacher probe solves/s at 1e-8 residual on 16^3x32, with dslash HBM GB/s.
+
+One step = one deflated Hutchinson estimate through the C-ABI (lqt_trace): 128 real
+Rademacher probes generated on the device, the deflation projections U^+ z and U^+ g5 z
+against a k = 64 basis of A g5 eigenvectors (FP64 MFMA), batched restarted GMRES(32)
+with BF16 links and Krylov vectors, FP32 arithmetic and FP64 defect correction at every
+restart until the FP64 true residual is <= 1e-8, the probe samples and the estimate.
+Gauge field, mass, basis and dslash tiling are set up before the timed region (the
+basis build is reported separately).  Inputs are synthetic (seeded random SU(3) links).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 exits with a message.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="wilson16x32_mixed")
+    ap.add_argument("--nprobes", type=int, default=None, help="override the probe count (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GMRES comparison")
+    return ap.parse_args()
+
+
+def cpu_baseline(U, dims, mass, iters_per_probe, budget_s=15.0):
+    """Oracle FP64 GMRES(32) timed on the host for a bounded number of iterations of one probe
+    solve, scaled to probe solves/s with the iteration count the identical FP64 algorithm
+    needs per probe (measured on the device)."""
+    import numpy as np
+
+    from oracle import core
+
+    N = 12 * int(np.prod(dims))
+    z = core.probes(1001, 1, N)[0].astype(np.complex128)
+    core.gmres(U, dims, mass, z, 1e-8, m=32, maxit=2)  # warm the library
+    its = 32
+    t0 = time.perf_counter()
+    core.gmres(U, dims, mass, z, 1e-8, m=32, maxit=its)
+    dt = time.perf_counter() - t0
+    if dt < budget_s / 3:  # whole restart cycles filling about budget_s
+        its = 32 * max(1, int(budget_s / dt))
+        t0 = time.perf_counter()
+        core.gmres(U, dims, mass, z, 1e-8, m=32, maxit=its)
+        dt = time.perf_counter() - t0
+    per_iter = dt / its
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": 1.0 / (per_iter * iters_per_probe),
+        "unit": "probe solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{its} Arnoldi steps of FP64 GMRES(32) on one probe ({dt:.1f} s, {per_iter*1e3:.1f} ms/step), "
+                  f"scaled by the {iters_per_probe:.0f} steps per probe the same algorithm takes on the device",
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); probes are independent, see the "
+              "sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1909_12234_amd as lq
+    import synth
+    from paper_1909_12234_amd.workloads import PREC, WORKLOADS
+
+    w = WORKLOADS[a.workload]
+    dims, mass, eps = w["dims"], w["mass"], w["eps"]
+    nprobes = a.nprobes or w["nprobes"]
+    prec = PREC[w["inner_prec"]]
+    V = int(np.prod(dims))
+    torch.cuda.set_device(0)
+
+    t_setup = time.perf_counter()
+    U = synth.su3_links(dims, eps, w["seed"])
+    ctx = lq.Context(dims, mass)
+    ctx.set_gauge(U)
+    ctx.tune(prec, nprobes)
+    ctx.tune(0, 1)
+    t_basis = time.perf_counter()
+    basis = ctx.basis_eig(w["k"], xi=1e-2, prec=lq.F32) if w.get("k") else None
+    torch.cuda.synchronize()
+    t_basis = time.perf_counter() - t_basis
+    lam = basis.eigenvalues().numpy().real if basis is not None else np.array([1.0])
+    t_setup = time.perf_counter() - t_setup
+
+    def step():
+        return ctx.trace(nprobes, w["probe_seed"], w["xi"], basis=basis, prec=prec)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.kernel_times(mode=2)  # zero and start the kernel timers
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(a.steps):
+        results.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = ctx.kernel_times(mode=3)
+    ok = sum(r["nsolves"] - r["nfailed"] for r in results)
+    value = ok / elapsed
+    iters_mixed = sum(r["iters_total"] for r in results) / max(1, sum(r["nsolves"] for r in results))
+
+    # roofline of the dominant kernel family (by device time), from live HIP events
+    fam = max((f for f in kt if kt[f][2] > 0), key=lambda f: kt[f][0])
+    ms, calls, byt = kt[fam]
+    achieved = byt / (ms * 1e-3) / 1e9
+    roof = {"kernel": fam, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "launches": calls,
+            "avg_launch_us": round(ms * 1e3 / max(calls, 1), 2)}
+    d_ms, d_calls, d_b = kt["dslash"]
+    dslash_gbs = d_b / (d_ms * 1e-3) / 1e9 if d_ms > 0 else None
+
+    out = {
+        "metric": "Rademacher probe solves/s at 1e-8 residual (16^3x32) + dslash HBM GB/s",
+        "value": round(value, 3),
+        "unit": "probe solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(elapsed / a.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w["inner_prec"],
+        "dtype_detail": f"{w['inner_prec']} links and Krylov vectors, fp32 accumulate, fp64 defect correction",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: Wilson-Dirac {dims[0]}^3x{dims[3]}, eps={eps}, m={mass}, "
+                               f"{nprobes} Rademacher probes, xi={w['xi']}, oblique g5 deflation k={w.get('k', 0)}",
+                   "lattice": list(dims), "probes": nprobes, "restart": 32, "deflation_rank": w.get("k", 0)},
+        "dslash_hbm_gbps": round(dslash_gbs, 1) if dslash_gbs else None,
+        "dslash_frac_of_peak": round(dslash_gbs / HBM_PEAK_GBS, 4) if dslash_gbs else None,
+        "roofline": roof,
+        "kernel_ms": {f: round(kt[f][0], 2) for f in kt},
+        "iters_per_probe_mixed": round(iters_mixed, 1),
+        "estimate": {"trace": results[-1]["trace_re"], "var_sample": results[-1]["var_sample"],
+                     "jackknife_err": results[-1]["jackknife_err"], "nfailed": results[-1]["nfailed"]},
+        "setup_s": round(t_setup, 2),
+        "basis_s": round(t_basis, 2),
+        "basis_min_abs_lambda": float(np.min(np.abs(lam))),
+    }
+
+    if not a.no_fp64:
+        # plain FP64 GMRES(32), one right-hand side at a time, same probes (a sample of 4)
+        zs = ctx.probes(w["probe_seed"], 4)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its = []
+        for j in range(zs.shape[0]):
+            _, st, _ = ctx.solve(zs[j:j + 1], w["xi"], prec=lq.F64)
+            its.append(st[0][1])
+        torch.cuda.synchronize()
+        fp64_rate = zs.shape[0] / (time.perf_counter() - t1)
+        out["fp64_plain_gmres_solves_per_s"] = round(fp64_rate, 3)
+        out["fp64_plain_iters_per_probe"] = float(np.mean(its))
+        out["speedup_vs_fp64_plain"] = round(value / fp64_rate, 2)
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(U, dims, mass, out.get("fp64_plain_iters_per_probe", iters_mixed))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

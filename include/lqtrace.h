@@ -260,11 +260,14 @@ int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const d
 int lqt_tune(lqt_ctx *ctx, int prec, int nrhs, double *ms);
 
 /* Kernel timers: HIP event pairs recorded around the library's launches on the context
- * stream, summed per kernel family (0 Wilson operator, 1 Arnoldi orthogonalisation,
- * 2 other field BLAS, 3 deflation projections).  h_ms4 / h_calls4 (may be NULL) receive
- * the totals so far.  mode 0: read; 1: read, then zero; 2: zero and start timing;
- * 3: stop timing.  Timing is off by default. */
-int lqt_kernel_times(lqt_ctx *ctx, double *h_ms4, long long *h_calls4, int mode);
+ * stream, summed per kernel family: 0 Wilson operator of the inner cycles, 1 CGS dot
+ * pass, 2 CGS update pass, 3 FP64 residual (defect correction), 4 other Krylov kernels,
+ * 5 deflation projections, 6 prolongator restrict/prolong, 7 transport network.  h_ms,
+ * h_calls and h_bytes (each 8 entries, may be NULL) receive the device milliseconds, the
+ * launch counts and the algorithmic HBM bytes of the timed launches.  mode 0: read;
+ * 1: read, then zero; 2: zero and start timing; 3: stop timing.  Timing is off by default
+ * and costs two event records per launch when on. */
+int lqt_kernel_times(lqt_ctx *ctx, double *h_ms, long long *h_calls, double *h_bytes, int mode);
 
 const char *lqt_last_error(const lqt_ctx *ctx);
 void lqt_destroy(lqt_ctx *ctx);

@@ -179,13 +179,14 @@ int lqt_tune(lqt_ctx* c, int prec, int nrhs, double* ms) {
     });
 }
 
-int lqt_kernel_times(lqt_ctx* c, double* ms4, long long* calls4, int mode) {
+int lqt_kernel_times(lqt_ctx* c, double* ms, long long* calls, double* bytes, int mode) {
     if (!c) return LQT_EINVAL;
     return guard(c, [&] {
         c->timer.flush();
-        for (int i = 0; i < 4; i++) {
-            if (ms4) ms4[i] = c->timer.ms[i];
-            if (calls4) calls4[i] = c->timer.calls[i];
+        for (int i = 0; i < lqt::KT_N; i++) {
+            if (ms) ms[i] = c->timer.ms[i];
+            if (calls) calls[i] = c->timer.calls[i];
+            if (bytes) bytes[i] = c->timer.bytes[i];
         }
         if (mode == 1) c->timer.reset();
         if (mode == 2) {

@@ -12,3 +12,10 @@ void gamma5_fields(lqt_ctx* c, double2* x, int nf);
 bool has_nonfinite(lqt_ctx* c, const double* p, size_t n);
 
 }  // namespace lqt
+
+namespace lqt {
+void gaussian_fields(lqt_ctx* c, uint64_t seed, long long n, int nf, double2* out);
+// out[f] = |W_f - theta_f Q_f|^2 for nf vectors of length n
+void eig_residual_norms(lqt_ctx* c, const double2* W, const double2* Q, const double* theta_dev, long long n, int nf,
+                        double* out_dev);
+}  // namespace lqt

@@ -214,3 +214,59 @@ bool has_nonfinite(lqt_ctx* c, const double* p, size_t n) {
 }
 
 }  // namespace lqt
+
+namespace lqt {
+
+// Complex Gaussian fields (unit variance per real part) from a counter hash and Box-Muller:
+// entry (f, i) uses h(seed ^ h(f ^ h(2i))) and h(seed ^ h(f ^ h(2i+1))) as uniforms.
+__global__ void k_gauss(uint64_t seed, long long n, int nf, double2* __restrict__ out) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nf) return;
+    long long f = e / n, i = e - f * n;
+    uint64_t h1 = sm64(seed ^ sm64((uint64_t)f ^ sm64((uint64_t)(2 * i))));
+    uint64_t h2 = sm64(seed ^ sm64((uint64_t)f ^ sm64((uint64_t)(2 * i + 1))));
+    double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740992.0);  // (0, 1]
+    double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+    double r = sqrt(-2.0 * log(u1));
+    out[e] = make_double2(r * cos(6.283185307179586 * u2), r * sin(6.283185307179586 * u2));
+}
+
+void gaussian_fields(lqt_ctx* c, uint64_t seed, long long n, int nf, double2* out) {
+    long long tot = n * nf;
+    if (tot <= 0) return;
+    hipLaunchKernelGGL(k_gauss, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, seed, n, nf, out);
+    LQT_HIP(hipGetLastError());
+}
+
+// partial |w_f - theta_f q_f|^2 over generic vectors of length n (grid: chunks x fields)
+__global__ __launch_bounds__(256) void k_eigres_part(const double2* __restrict__ W, const double2* __restrict__ Q,
+                                                     const double* __restrict__ theta, long long n,
+                                                     double* __restrict__ part) {
+    __shared__ double red[4];
+    const int f = blockIdx.y;
+    const double th = theta[f];
+    double a = 0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        double2 w = W[f * n + i], q = Q[f * n + i];
+        double x = w.x - th * q.x, y = w.y - th * q.y;
+        a += x * x + y * y;
+    }
+    a = wsum(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(long long)f * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+void eig_residual_norms(lqt_ctx* c, const double2* W, const double2* Q, const double* theta_dev, long long n, int nf,
+                        double* out_dev) {
+    if (nf <= 0) return;
+    const int nb = 256;
+    c->scratch[6].ensure(sizeof(double) * (size_t)nb * nf);
+    hipLaunchKernelGGL(k_eigres_part, dim3(nb, nf), dim3(256), 0, c->stream, W, Q, theta_dev, n,
+                       c->scratch[6].as<double>());
+    LQT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows, dim3(nf), dim3(64), 0, c->stream, c->scratch[6].as<double>(), nb, out_dev);
+    LQT_HIP(hipGetLastError());
+}
+
+}  // namespace lqt

@@ -335,7 +335,8 @@ void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, l
     t = (it != c->tuned.end()) ? it->second : default_tile(prec, nrhs);
     c->timer.begin(c->stream, KT_DSLASH);
     dslash_cfg(c, prec, op, in, out, nrhs, in_stride, out_stride, t);
-    c->timer.end(c->stream);
+    const double b = (double)storage_bytes(prec) / 2;  // bytes per real
+    c->timer.end(c->stream, (double)c->g.V * (72.0 * b + 48.0 * b * nrhs));
 }
 
 // Autotuner: time every (rhs per thread, block size) candidate on scratch fields and keep
@@ -403,14 +404,15 @@ void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, doub
     const long long n = 12LL * g.V;
     c->scratch[7].ensure(sizeof(double) * (size_t)nsb * nrhs);
     double* part = c->scratch[7].as<double>();
-    c->timer.begin(c->stream, KT_DSLASH);
+    c->timer.begin(c->stream, KT_RESID);
     hipLaunchKernelGGL((k_dslash<double2, 1, false, 1>), dim3(xcd_grid(nsb * nrhs)), dim3(bs), 0, c->stream,
                        c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.L[0], g.L[1], g.L[2], g.L[3],
                        4.0 + c->mass, nrhs, n, n, 0, 0);
     LQT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, c->stream, part, nsb, nrhs, rnorm2);
     LQT_HIP(hipGetLastError());
-    c->timer.end(c->stream);
+    // links once; x, b read and r written per right-hand side (FP64)
+    c->timer.end(c->stream, (double)g.V * (72.0 * 8 + 72.0 * 8 * nrhs));
 }
 
 }  // namespace lqt

@@ -196,25 +196,39 @@ struct HBuf {
     }
 };
 
-// Kernel-family timers (HIP events on the context stream).
-enum { KT_DSLASH = 0, KT_ORTH = 1, KT_BLAS = 2, KT_PROJ = 3 };
+// Kernel families timed by KTimer.
+enum {
+    KT_DSLASH = 0,  // Wilson operator of the inner cycles (any storage precision)
+    KT_DOTS = 1,    // CGS dot pass
+    KT_UPDATE = 2,  // CGS update pass
+    KT_RESID = 3,   // FP64 residual b - A x with norms (defect correction)
+    KT_KRYLOV = 4,  // other Krylov kernels (cycle start, solution update, small reductions)
+    KT_PROJ = 5,    // deflation projections (FP64 MFMA)
+    KT_PR = 6,      // prolongator restrict / prolong
+    KT_NET = 7,     // transport-network preconditioner
+    KT_N = 8
+};
 
 // Non-blocking kernel timer: event pairs recorded around launches on the context stream,
-// folded into per-family totals only when the pool fills or the totals are read.
+// folded into per-family totals (time, launches, algorithmic bytes) only when the pool
+// fills or the totals are read.
 struct KTimer {
-    static constexpr int POOL = 2048;
+    static constexpr int POOL = 4096;
     bool on = false;
     std::vector<hipEvent_t> e0, e1;
     std::vector<int> fam;
+    std::vector<double> byt;
     int used = 0;
     int open_fam = -1;
-    double ms[4] = {0, 0, 0, 0};
-    long long calls[4] = {0, 0, 0, 0};
+    double ms[KT_N] = {};
+    long long calls[KT_N] = {};
+    double bytes[KT_N] = {};
     void init() {
         if (!e0.empty()) return;
         e0.resize(POOL);
         e1.resize(POOL);
         fam.resize(POOL);
+        byt.resize(POOL);
         for (int i = 0; i < POOL; i++) {
             (void)hipEventCreate(&e0[i]);
             (void)hipEventCreate(&e1[i]);
@@ -236,6 +250,7 @@ struct KTimer {
             if (hipEventElapsedTime(&t, e0[i], e1[i]) == hipSuccess) {
                 ms[fam[i]] += t;
                 calls[fam[i]] += 1;
+                bytes[fam[i]] += byt[i];
             }
         }
         used = 0;
@@ -247,15 +262,17 @@ struct KTimer {
         fam[used] = f;
         open_fam = f;
     }
-    void end(hipStream_t s) {
+    // bytes: algorithmic HBM bytes of the launches between begin and end
+    void end(hipStream_t s, double bytes_moved = 0) {
         if (!on || open_fam < 0) return;
         (void)hipEventRecord(e1[used], s);
+        byt[used] = bytes_moved;
         used++;
         open_fam = -1;
     }
     void reset() {
         flush();
-        for (int i = 0; i < 4; i++) ms[i] = 0, calls[i] = 0;
+        for (int i = 0; i < KT_N; i++) ms[i] = 0, calls[i] = 0, bytes[i] = 0;
     }
 };
 
@@ -284,7 +301,10 @@ struct lqt_ctx {
     std::string err;
     bool have_gauge = false;
     lqt::DBuf U[4];  // gauge per precision (LQT_F64 .. LQT_BF16)
-    lqt::DBuf scratch[8];
+    // work buffers, grown on demand: 0 Krylov basis, 1 residuals, 2 Krylov state,
+    // 3-4 Krylov partial sums, 5-6 apply / BLAS partials, 7 residual partials,
+    // 8 GEMM partials, 9 small matrices, 10-11 estimator fields
+    lqt::DBuf scratch[12];
     lqt::HBuf pinned;
     std::map<long long, lqt::Tuned> tuned;
     lqt::KTimer timer;
@@ -299,7 +319,10 @@ struct lqt_basis {
     lqt::DBuf U;                // k fine vectors, device layout FP64 [k][12][V]
     std::vector<double> lambda; // 2k (complex) eigenvalues of U^+ g5 A U, ascending |.|
     std::vector<double> ug5u;   // 2k: u_i^+ g5 u_i
-    bool orthonormal = false;
+    bool orthonormal = false;   // Q holds an orthonormal basis (Algorithm 1 projector)
+    lqt::DBuf Q;                // k orthonormal Ritz vectors of A g5 (eigensolver bases)
+    std::vector<double> theta;  // Ritz values of A g5
+    std::vector<double> resid;  // ||A g5 q - theta q||
     // prolongator data
     int block[4] = {0, 0, 0, 0};
     int nv = 0;

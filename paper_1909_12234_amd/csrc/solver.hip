@@ -54,18 +54,25 @@ struct StateBuf {
     }
 };
 
+// One Arnoldi orthogonalisation: CGS (or CGS2) dot and update passes.  Algorithmic bytes:
+// the dot pass reads j+2 vectors, the update pass reads j+2 and writes one (per slot).
 template <typename S>
 void kry_step_orth(lqt_ctx* c, void* basis, long long vstride, int j, int na, const KryState& st, bool cgs2,
                    double2* part, double* partn) {
-    c->timer.begin(c->stream, KT_ORTH);
-    kry_dots<S>(c, basis, vstride, j, na, part);
-    kry_finish(c, part, j, na, st, 0);
-    if (cgs2) {
-        kry_update<S>(c, basis, vstride, j, na, st, 0, partn);
+    const double vb = 24.0 * c->g.V * (sizeof(S) / 2) * na;  // bytes of one vector per slot set
+    for (int pass = 0; pass < (cgs2 ? 2 : 1); pass++) {
+        c->timer.begin(c->stream, KT_DOTS);
         kry_dots<S>(c, basis, vstride, j, na, part);
-        kry_finish(c, part, j, na, st, 1);
+        c->timer.end(c->stream, vb * (j + 2));
+        c->timer.begin(c->stream, KT_KRYLOV);
+        kry_finish(c, part, j, na, st, pass);
+        c->timer.end(c->stream);
+        const int last = (pass == (cgs2 ? 1 : 0));
+        c->timer.begin(c->stream, KT_UPDATE);
+        kry_update<S>(c, basis, vstride, j, na, st, last, partn);
+        c->timer.end(c->stream, vb * (j + 3));
     }
-    kry_update<S>(c, basis, vstride, j, na, st, 1, partn);
+    c->timer.begin(c->stream, KT_KRYLOV);
     kry_norm_givens(c, partn, j, na, st);
     c->timer.end(c->stream);
 }
@@ -108,7 +115,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     int* h_flags = (int*)(h_rn2 + nb);
 
     std::vector<double> bnorm(nb);
-    c->timer.begin(c->stream, KT_BLAS);
+    c->timer.begin(c->stream, KT_KRYLOV);
     norm2_fields(c, b, nb, bn2);
     LQT_HIP(hipMemsetAsync(x, 0, sizeof(double2) * (size_t)nb * n, c->stream));
     c->timer.end(c->stream);
@@ -161,7 +168,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         LQT_HIP(hipMemcpyAsync(src_d, src.data(), sizeof(int) * nn, hipMemcpyHostToDevice, c->stream));
         LQT_HIP(hipMemcpyAsync(tgt_d, tgt.data(), sizeof(double) * nn, hipMemcpyHostToDevice, c->stream));
         const long long vstride = (long long)nn * n;
-        c->timer.begin(c->stream, KT_BLAS);
+        c->timer.begin(c->stream, KT_KRYLOV);
         kry_start_state(c, sb.st, src_d, rn2, tgt_d, nn);
         kry_start<S>(c, basis, r, src_d, rn2, nn);
         c->timer.end(c->stream);
@@ -178,7 +185,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
                 if (all) break;
             }
         }
-        c->timer.begin(c->stream, KT_BLAS);
+        c->timer.begin(c->stream, KT_KRYLOV);
         kry_backsolve(c, nn, sb.st);
         kry_xupdate<S>(c, x, act_d, basis, vstride, nn, sb.st);
         c->timer.end(c->stream);

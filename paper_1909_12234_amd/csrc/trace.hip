@@ -1,0 +1,522 @@
+// Deflated Hutchinson estimation of trace(A^{-1}) and the deflation bases.
+//
+// Estimator (Eq. 1 with the split of Section 2; real Rademacher probes z_j):
+//   oblique, K = g5 (Section 2.1, Algorithm 2 form):
+//     t_j = z_j^T y_j - (z_j^T U) Lambda^{-1} (U^+ g5 z_j),  y_j = A^{-1}_xi z_j
+//     t0  = sum_i lambda_i^{-1} u_i^+ g5 u_i,  U = X U_hat,  U_hat Lambda U_hat^+ = X^+ g5 A X
+//   orthogonal (Algorithm 1):
+//     t_j = z_j^T A^{-1}_xi (z_j - U U^+ z_j),  t0 = sum_i u_i^+ A^{-1}_xi u_i
+// Only the k x s products U^+ z and U^+ g5 z are kept, which is what lets the estimate be
+// recomputed for every deflation rank after the solves (Section 2.2).
+//
+// Bases: from caller vectors, or from block subspace iteration on (A g5)^{-1}_xi =
+// g5 A^{-1}_xi with FP64 Rayleigh-Ritz (Algorithm 1, first step; the eigenvectors of A g5
+// are left singular vectors of A).  For the oblique projector an A g5 eigenbasis Q enters
+// as X = g5 Q, for which the oblique projector is Q Q^+ when Q is exact.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <new>
+
+#include "blas.h"
+#include "gemm.h"
+#include "hostla.h"
+#include "lqt_internal.h"
+#include "prolong.h"
+#include "solver.h"
+
+using lqt::DBuf;
+using lqt::Error;
+using lqt::zd;
+
+namespace lqt {
+
+static void h2d(lqt_ctx* c, void* d, const void* h, size_t bytes) {
+    LQT_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream));
+}
+static void d2h(lqt_ctx* c, void* h, const void* d, size_t bytes) {
+    LQT_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, c->stream));
+    LQT_HIP(hipStreamSynchronize(c->stream));
+}
+
+// C = X^+ Y on the device, copied to a host vector (ka x kb row-major)
+static std::vector<zd> gram_host(lqt_ctx* c, const double2* X, int ka, const double2* Y, int kb, long long n = -1) {
+    c->scratch[9].ensure(sizeof(double2) * (size_t)ka * kb);
+    gemm_gram(c, X, ka, Y, kb, c->scratch[9].as<double2>(), n);
+    std::vector<zd> h((size_t)ka * kb);
+    d2h(c, h.data(), c->scratch[9].p, sizeof(double2) * h.size());
+    return h;
+}
+
+// Y = X C with a host matrix C (ka x kb row-major)
+static void combine_host(lqt_ctx* c, const double2* X, int ka, const std::vector<zd>& C, int kb, double beta,
+                         double alpha, double2* Y, long long n = -1) {
+    c->scratch[9].ensure(sizeof(double2) * (size_t)ka * kb);
+    h2d(c, c->scratch[9].p, C.data(), sizeof(double2) * (size_t)ka * kb);
+    gemm_combine(c, X, ka, c->scratch[9].as<double2>(), kb, beta, alpha, Y, n);
+}
+
+// In place: X (k vectors) <- an orthonormal basis of span X (r <= k vectors). tmp: k vectors.
+static int orthonormalize(lqt_ctx* c, double2* X, int k, double2* tmp, long long n = -1) {
+    if (n < 0) n = 12LL * c->g.V;
+    int r = k;
+    for (int pass = 0; pass < 2; pass++) {
+        std::vector<zd> G = gram_host(c, X, r, X, r, n);
+        std::vector<zd> T;
+        int r2 = orthonormalizer(r, G, T, 1e-13);
+        combine_host(c, X, r, T, r2, 0.0, 1.0, tmp, n);
+        LQT_HIP(hipMemcpyAsync(X, tmp, sizeof(double2) * (size_t)r2 * n, hipMemcpyDeviceToDevice, c->stream));
+        r = r2;
+    }
+    return r;
+}
+
+// Oblique-projector data for fine vectors X: M = X^+ g5 A X, eigh, U = X U_hat.
+void fine_oblique_setup(lqt_ctx* c, lqt_basis* B, const double2* X, int k) {
+    const long long n = 12LL * c->g.V;
+    DBuf AX;
+    AX.ensure(sizeof(double2) * (size_t)k * n);
+    dslash(c, LQT_F64, LQT_A, X, AX.p, k, n, n);
+    gamma5_fields(c, AX.as<double2>(), k);
+    std::vector<zd> M = gram_host(c, X, k, AX.as<double2>(), k);
+    std::vector<double> lam;
+    std::vector<zd> Uh;
+    heev(k, M, lam, Uh, true);
+    B->U.ensure(sizeof(double2) * (size_t)k * n);
+    combine_host(c, X, k, Uh, k, 0.0, 1.0, B->U.as<double2>());
+    LQT_HIP(hipMemcpyAsync(AX.p, B->U.p, sizeof(double2) * (size_t)k * n, hipMemcpyDeviceToDevice, c->stream));
+    gamma5_fields(c, AX.as<double2>(), k);
+    c->scratch[9].ensure(sizeof(double2) * (size_t)k);
+    dot_fields(c, B->U.as<double2>(), AX.as<double2>(), k, c->scratch[9].as<double2>());
+    std::vector<zd> d(k);
+    d2h(c, d.data(), c->scratch[9].p, sizeof(double2) * k);
+    B->k = k;
+    B->lambda.assign(2 * k, 0.0);
+    B->ug5u.assign(2 * k, 0.0);
+    for (int i = 0; i < k; i++) {
+        B->lambda[2 * i] = lam[i];
+        B->ug5u[2 * i] = d[i].real();
+        B->ug5u[2 * i + 1] = d[i].imag();
+    }
+}
+
+// Largest singular value of A (= largest |eigenvalue| of the Hermitian A g5), power iteration.
+double sigma_max(lqt_ctx* c) {
+    if (c->sigma_max > 0) return c->sigma_max;
+    const long long n = 12LL * c->g.V;
+    DBuf v, w;
+    v.ensure(sizeof(double2) * n);
+    w.ensure(sizeof(double2) * n);
+    gaussian_fields(c, 0x5151, n, 1, v.as<double2>());
+    c->scratch[9].ensure(64);
+    double nv = 0, nw = 0, est = 0;
+    for (int it = 0; it < 40; it++) {
+        dslash(c, LQT_F64, LQT_A_G5, v.p, w.p, 1, n, n);
+        norm2_fields(c, v.as<double2>(), 1, c->scratch[9].as<double>());
+        norm2_fields(c, w.as<double2>(), 1, c->scratch[9].as<double>() + 1);
+        double h[2];
+        d2h(c, h, c->scratch[9].p, 16);
+        nv = std::sqrt(h[0]);
+        nw = std::sqrt(h[1]);
+        est = nw / nv;
+        std::swap(v.p, w.p);
+    }
+    c->sigma_max = est;
+    return est;
+}
+
+}  // namespace lqt
+
+namespace {
+
+template <typename F>
+int guard(lqt_ctx* c, F&& f) {
+    try {
+        f();
+        return LQT_OK;
+    } catch (const Error& e) {
+        if (c) c->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        return LQT_ENOMEM;
+    } catch (...) {
+        if (c) c->err = "unexpected exception";
+        return LQT_EINVAL;
+    }
+}
+
+void need_gauge(lqt_ctx* c) { LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)"); }
+
+struct Stats {
+    zd mean;
+    double var = 0, var_re = 0, jk = 0;
+};
+
+Stats summarize(const std::vector<zd>& t) {
+    Stats s;
+    const int m = (int)t.size();
+    zd sum = 0;
+    for (auto& x : t) sum += x;
+    s.mean = m ? sum / (double)m : zd(0);
+    if (m > 1) {
+        double v = 0, vr = 0;
+        for (auto& x : t) {
+            v += std::norm(x - s.mean);
+            vr += (x.real() - s.mean.real()) * (x.real() - s.mean.real());
+        }
+        s.var = v / (m - 1);
+        s.var_re = vr / (m - 1);
+        std::vector<zd> loo(m);
+        zd lm = 0;
+        for (int j = 0; j < m; j++) {
+            loo[j] = (sum - t[j]) / (double)(m - 1);
+            lm += loo[j];
+        }
+        lm /= (double)m;
+        double a = 0;
+        for (auto& x : loo) a += std::norm(x - lm);
+        s.jk = std::sqrt((m - 1.0) / m * a);
+    }
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lqt_basis_from_vectors(lqt_ctx* c, const double* vectors, int k, lqt_basis** out) {
+    if (!c || !out) return LQT_EINVAL;
+    *out = nullptr;
+    return guard(c, [&] {
+        LQT_CHECK(vectors && k >= 1, LQT_EINVAL, "need k >= 1 vectors");
+        need_gauge(c);
+        const long long n = 12LL * c->g.V;
+        LQT_CHECK(!lqt::has_nonfinite(c, vectors, (size_t)(2 * n * k)), LQT_ENAN, "basis vectors hold NaN or Inf");
+        lqt_basis* B = new lqt_basis();
+        B->ctx = c;
+        try {
+            DBuf X;
+            X.ensure(sizeof(double2) * (size_t)k * n);
+            lqt::to_device_layout(c, (const double2*)vectors, X.as<double2>(), k);
+            lqt::fine_oblique_setup(c, B, X.as<double2>(), k);
+            LQT_HIP(hipStreamSynchronize(c->stream));
+        } catch (...) {
+            delete B;
+            throw;
+        }
+        *out = B;
+    });
+}
+
+int lqt_basis_eig(lqt_ctx* c, int k, double xi, double tau, const lqt_solver_opts* opts, lqt_basis** out) {
+    if (!c || !out) return LQT_EINVAL;
+    *out = nullptr;
+    return guard(c, [&] {
+        LQT_CHECK(k >= 1, LQT_EINVAL, "k must be >= 1");
+        LQT_CHECK(xi > 0 && xi < 1, LQT_EINVAL, "xi must be in (0, 1)");
+        LQT_CHECK(tau == 0.0, LQT_EINVAL, "the shifted (tau != 0) eigensolver is not implemented");
+        need_gauge(c);
+        const long long n = 12LL * c->g.V;
+        LQT_CHECK(k <= n / 2, LQT_EINVAL, "k too large for the lattice");
+        lqt::SolveOpts o = lqt::make_opts(opts);
+        const int kk = (int)std::min<long long>(n / 2, k + std::max(8, k / 4));
+        const double smax = lqt::sigma_max(c);
+        DBuf Qb, Yb, Wb, Tb;
+        Qb.ensure(sizeof(double2) * (size_t)kk * n);
+        Yb.ensure(sizeof(double2) * (size_t)kk * n);
+        Wb.ensure(sizeof(double2) * (size_t)kk * n);
+        Tb.ensure(sizeof(double2) * (size_t)kk * n);
+        double2 *Q = Qb.as<double2>(), *Y = Yb.as<double2>(), *W = Wb.as<double2>(), *T = Tb.as<double2>();
+        lqt::gaussian_fields(c, 0xE16E5EEDull, n, kk, Q);
+        int r = lqt::orthonormalize(c, Q, kk, T);
+        std::vector<double> theta;
+        std::vector<double> res(kk, 0.0);
+        const int maxit = 40;
+        int conv = 0;
+        for (int it = 0; it < maxit; it++) {
+            // Y = (A g5)^{-1}_xi Q = g5 A^{-1}_xi Q
+            std::vector<lqt_solve_stats> st(r);
+            lqt::solve_fields(c, Q, Y, r, xi, o, st.data());
+            lqt::gamma5_fields(c, Y, r);
+            std::swap(Q, Y);
+            r = lqt::orthonormalize(c, Q, r, T);
+            // Rayleigh-Ritz with A g5 in FP64
+            lqt::dslash(c, LQT_F64, LQT_A_G5, Q, W, r, n, n);
+            std::vector<zd> M = lqt::gram_host(c, Q, r, W, r);
+            std::vector<zd> S;
+            lqt::heev(r, M, theta, S, true);
+            lqt::combine_host(c, Q, r, S, r, 0.0, 1.0, T);
+            std::swap(Q, T);
+            lqt::combine_host(c, W, r, S, r, 0.0, 1.0, T);
+            std::swap(W, T);
+            c->scratch[9].ensure(sizeof(double) * 2 * r);
+            double* th = c->scratch[9].as<double>();
+            LQT_HIP(hipMemcpyAsync(th, theta.data(), sizeof(double) * r, hipMemcpyHostToDevice, c->stream));
+            lqt::eig_residual_norms(c, W, Q, th, n, r, th + r);
+            lqt::d2h(c, res.data(), th + r, sizeof(double) * r);
+            conv = 0;
+            for (int i = 0; i < std::min(k, r); i++)
+                if (std::sqrt(res[i]) <= xi * smax) conv++;
+            if (conv >= std::min(k, r)) break;
+        }
+        LQT_CHECK(r >= k, LQT_ENOTCONV, "eigensolver lost rank");
+        lqt_basis* B = new lqt_basis();
+        B->ctx = c;
+        try {
+            // orthonormal Ritz vectors Q (Algorithm 1) and X = g5 Q for the oblique form
+            B->Q.ensure(sizeof(double2) * (size_t)k * n);
+            LQT_HIP(hipMemcpyAsync(B->Q.p, Q, sizeof(double2) * (size_t)k * n, hipMemcpyDeviceToDevice, c->stream));
+            B->orthonormal = true;
+            B->theta.assign(theta.begin(), theta.begin() + k);
+            B->resid.resize(k);
+            for (int i = 0; i < k; i++) B->resid[i] = std::sqrt(res[i]);
+            LQT_HIP(hipMemcpyAsync(T, Q, sizeof(double2) * (size_t)k * n, hipMemcpyDeviceToDevice, c->stream));
+            lqt::gamma5_fields(c, T, k);
+            lqt::fine_oblique_setup(c, B, T, k);
+            LQT_HIP(hipStreamSynchronize(c->stream));
+        } catch (...) {
+            delete B;
+            throw;
+        }
+        *out = B;
+        if (conv < k) {
+            c->err = "eigensolver: " + std::to_string(conv) + " of " + std::to_string(k) + " pairs converged";
+            throw Error{LQT_ENOTCONV, c->err};
+        }
+    });
+}
+
+int lqt_basis_eigenvalues(const lqt_basis* B, double* lambda, int* k) {
+    if (!B || !k) return LQT_EINVAL;
+    *k = B->k;
+    if (lambda)
+        for (int i = 0; i < 2 * B->k; i++) lambda[i] = B->lambda[i];
+    return LQT_OK;
+}
+
+int lqt_basis_vectors(const lqt_basis* B, double* out) {
+    if (!B || !out) return LQT_EINVAL;
+    lqt_ctx* c = B->ctx;
+    return guard(c, [&] {
+        LQT_CHECK(B->kind == 0, LQT_EINVAL, "a prolongator basis holds coarse vectors");
+        lqt::from_device_layout(c, B->U.as<double2>(), (double2*)out, B->k);
+        LQT_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+void lqt_basis_free(lqt_basis* B) {
+    if (!B) return;
+    if (B->ctx) (void)hipStreamSynchronize(B->ctx->stream);
+    delete B;
+}
+
+int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64_t seed, double xi,
+              const lqt_solver_opts* opts, lqt_trace_result* res, double* rank_curve, double* samples) {
+    if (!c) return LQT_EINVAL;
+    int nfail_total = 0;
+    int rc = guard(c, [&] {
+        LQT_CHECK(res, LQT_EINVAL, "null result");
+        LQT_CHECK(nprobes >= 1, LQT_EINVAL, "nprobes must be >= 1");
+        LQT_CHECK(xi > 0 && xi < 1, LQT_EINVAL, "xi must be in (0, 1)");
+        LQT_CHECK(projector == LQT_OBLIQUE_G5 || projector == LQT_ORTH, LQT_EINVAL, "bad projector");
+        LQT_CHECK(!B || B->ctx == c, LQT_EINVAL, "basis belongs to another context");
+        LQT_CHECK(!(B && projector == LQT_ORTH && (!B->orthonormal || B->kind != 0)), LQT_EINVAL,
+                  "the orthogonal projector needs an orthonormal fine basis (lqt_basis_eig)");
+        need_gauge(c);
+        lqt::SolveOpts o = lqt::make_opts(opts);
+        LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net without preconditioner weights");
+        const long long n = 12LL * c->g.V;
+        const int k = B ? B->k : 0;
+        const int s = nprobes;
+        // probe chunk: the caller's batch, else what fits (Z and Y FP64 + the Krylov basis)
+        size_t fr = 0, tot = 0;
+        LQT_HIP(hipMemGetInfo(&fr, &tot));
+        size_t per = (size_t)n * 16 * 2 + (size_t)(o.restart + 1) * n * lqt::storage_bytes(o.prec) + (size_t)n * 32;
+        if (o.use_net) per += (size_t)o.restart * n * lqt::storage_bytes(o.prec);
+        int fit = (int)std::max<size_t>(1, (size_t)(0.6 * (double)(fr + c->scratch[0].n + c->scratch[10].n +
+                                                                     c->scratch[11].n)) / per);
+        int chunk = std::min(s, o.max_batch > 0 ? o.max_batch : s);
+        chunk = std::max(1, std::min(chunk, fit));
+        c->scratch[10].ensure(sizeof(double2) * (size_t)chunk * n);
+        c->scratch[11].ensure(sizeof(double2) * (size_t)chunk * n);
+        double2* Z = c->scratch[10].as<double2>();
+        double2* Y = c->scratch[11].as<double2>();
+        std::vector<zd> t(s), Cm((size_t)k * s), Cg((size_t)k * s);
+        std::vector<lqt_solve_stats> st(s);
+        hipEvent_t e0, e1, e2;
+        LQT_HIP(hipEventCreate(&e0));
+        LQT_HIP(hipEventCreate(&e1));
+        LQT_HIP(hipEventCreate(&e2));
+        double t_setup = 0, t_solve = 0;
+        DBuf small;
+        for (int j0 = 0; j0 < s; j0 += chunk) {
+            const int cs = std::min(chunk, s - j0);
+            LQT_HIP(hipEventRecord(e0, c->stream));
+            if (B) {
+                small.ensure(sizeof(double2) * (size_t)k * cs * 2);
+                double2* cup = small.as<double2>();
+                double2* cdn = cup + (size_t)k * cs;
+                if (B->kind == 0) {
+                    const double2* U = (projector == LQT_ORTH) ? B->Q.as<double2>() : B->U.as<double2>();
+                    lqt::gemm_probes(c, U, k, seed, j0, cs, cup, cdn);
+                } else {
+                    lqt::prolong_project_probes(c, B, seed, j0, cs, cup, cdn);
+                }
+                std::vector<zd> hu((size_t)k * cs), hd((size_t)k * cs);
+                lqt::d2h(c, hu.data(), cup, sizeof(double2) * hu.size());
+                lqt::d2h(c, hd.data(), cdn, sizeof(double2) * hd.size());
+                for (int i = 0; i < k; i++)
+                    for (int j = 0; j < cs; j++) {
+                        zd a = hu[(size_t)i * cs + j], b = hd[(size_t)i * cs + j];
+                        Cm[(size_t)i * s + j0 + j] = a + b;  // u_i^+ z_j
+                        Cg[(size_t)i * s + j0 + j] = a - b;  // u_i^+ g5 z_j
+                    }
+            }
+            lqt::probes_gen(c, seed, j0, cs, Z);
+            if (B && projector == LQT_ORTH) {  // z <- z - Q (Q^+ z)
+                std::vector<zd> C((size_t)k * cs);
+                for (int i = 0; i < k; i++)
+                    for (int j = 0; j < cs; j++) C[(size_t)i * cs + j] = Cm[(size_t)i * s + j0 + j];
+                lqt::combine_host(c, B->Q.as<double2>(), k, C, cs, 1.0, -1.0, Z);
+            }
+            LQT_HIP(hipEventRecord(e1, c->stream));
+            nfail_total += lqt::solve_fields(c, Z, Y, cs, xi, o, st.data() + j0);
+            LQT_HIP(hipEventRecord(e2, c->stream));
+            c->scratch[9].ensure(sizeof(double2) * (size_t)cs);
+            lqt::probe_dots(c, seed, j0, Y, cs, c->scratch[9].as<double2>());
+            lqt::d2h(c, t.data() + j0, c->scratch[9].p, sizeof(double2) * cs);
+            float a = 0, b = 0;
+            LQT_HIP(hipEventElapsedTime(&a, e0, e1));
+            LQT_HIP(hipEventElapsedTime(&b, e1, e2));
+            t_setup += a * 1e-3;
+            t_solve += b * 1e-3;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipEventDestroy(e2);
+        // deterministic part
+        zd t0 = 0;
+        if (B && projector == LQT_OBLIQUE_G5) {
+            for (int i = 0; i < k; i++) t0 += zd(B->ug5u[2 * i], B->ug5u[2 * i + 1]) / B->lambda[2 * i];
+        } else if (B) {  // Algorithm 1: t0 = sum_i u_i^+ A^{-1}_xi u_i (k extra solves)
+            DBuf Yu;
+            Yu.ensure(sizeof(double2) * (size_t)k * n);
+            std::vector<lqt_solve_stats> su(k);
+            nfail_total += lqt::solve_fields(c, B->Q.as<double2>(), Yu.as<double2>(), k, xi, o, su.data());
+            c->scratch[9].ensure(sizeof(double2) * (size_t)k);
+            lqt::dot_fields(c, B->Q.as<double2>(), Yu.as<double2>(), k, c->scratch[9].as<double2>());
+            std::vector<zd> d(k);
+            lqt::d2h(c, d.data(), c->scratch[9].p, sizeof(double2) * k);
+            for (auto& x : d) t0 += x;
+        }
+        // samples
+        std::vector<zd> base = t, ts = t;
+        if (B && projector == LQT_OBLIQUE_G5)
+            for (int j = 0; j < s; j++) {
+                zd corr = 0;
+                for (int i = 0; i < k; i++)
+                    corr += std::conj(Cm[(size_t)i * s + j]) * Cg[(size_t)i * s + j] / B->lambda[2 * i];
+                ts[j] = t[j] - corr;
+            }
+        Stats S = summarize(ts);
+        res->trace_re = (t0 + S.mean).real();
+        res->trace_im = (t0 + S.mean).imag();
+        res->t0_re = t0.real();
+        res->t0_im = t0.imag();
+        res->var_sample = S.var;
+        res->var_mean = S.var / s;
+        res->jackknife_err = S.jk;
+        res->var_re_only = S.var_re;
+        res->nsolves = s;
+        res->nfailed = 0;
+        res->iters_total = 0;
+        for (auto& x : st) {
+            res->iters_total += x.iters;
+            res->nfailed += x.converged ? 0 : 1;
+        }
+        res->seconds_solve = t_solve;
+        res->seconds_setup = t_setup;
+        if (samples)
+            for (int j = 0; j < s; j++) {
+                samples[2 * j] = ts[j].real();
+                samples[2 * j + 1] = ts[j].imag();
+            }
+        if (rank_curve) {
+            for (int kp = 0; kp <= k; kp++) {
+                double* row = rank_curve + 3 * kp;
+                if (!(B && projector == LQT_OBLIQUE_G5)) {
+                    row[0] = row[1] = row[2] = 0;
+                    continue;
+                }
+                std::vector<zd> tk(s);
+                zd t0k = 0;
+                for (int i = 0; i < kp; i++) t0k += zd(B->ug5u[2 * i], B->ug5u[2 * i + 1]) / B->lambda[2 * i];
+                for (int j = 0; j < s; j++) {
+                    zd corr = 0;
+                    for (int i = 0; i < kp; i++)
+                        corr += std::conj(Cm[(size_t)i * s + j]) * Cg[(size_t)i * s + j] / B->lambda[2 * i];
+                    tk[j] = base[j] - corr;
+                }
+                Stats Sk = summarize(tk);
+                row[0] = (t0k + Sk.mean).real();
+                row[1] = Sk.var;
+                row[2] = Sk.jk;
+            }
+        }
+    });
+    if (rc == LQT_OK && nfail_total) return LQT_ENOTCONV;
+    return rc;
+}
+
+int lqt_gram(lqt_ctx* c, const double* x, int ka, const double* y, int kb, double* h_c) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(ka >= 1 && kb >= 1 && x && y && h_c, LQT_EINVAL, "bad gram arguments");
+        const long long n = 12LL * c->g.V;
+        DBuf X, Yd;
+        X.ensure(sizeof(double2) * (size_t)ka * n);
+        Yd.ensure(sizeof(double2) * (size_t)kb * n);
+        lqt::to_device_layout(c, (const double2*)x, X.as<double2>(), ka);
+        lqt::to_device_layout(c, (const double2*)y, Yd.as<double2>(), kb);
+        std::vector<zd> C = lqt::gram_host(c, X.as<double2>(), ka, Yd.as<double2>(), kb);
+        std::copy((double*)C.data(), (double*)C.data() + 2 * C.size(), h_c);
+    });
+}
+
+int lqt_project_probes(lqt_ctx* c, const double* x, int ka, uint64_t seed, long long j0, int s, double* h_cup,
+                       double* h_cdn) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(ka >= 1 && s >= 1 && j0 >= 0 && x && h_cup && h_cdn, LQT_EINVAL, "bad projection arguments");
+        const long long n = 12LL * c->g.V;
+        DBuf X, out;
+        X.ensure(sizeof(double2) * (size_t)ka * n);
+        out.ensure(sizeof(double2) * (size_t)ka * s * 2);
+        lqt::to_device_layout(c, (const double2*)x, X.as<double2>(), ka);
+        lqt::gemm_probes(c, X.as<double2>(), ka, seed, j0, s, out.as<double2>(), out.as<double2>() + (size_t)ka * s);
+        lqt::d2h(c, h_cup, out.p, sizeof(double2) * (size_t)ka * s);
+        lqt::d2h(c, h_cdn, out.as<double2>() + (size_t)ka * s, sizeof(double2) * (size_t)ka * s);
+    });
+}
+
+int lqt_combine(lqt_ctx* c, const double* x, int ka, const double* h_c, int kb, double beta, double alpha,
+                double* y) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(ka >= 1 && kb >= 1 && x && h_c && y, LQT_EINVAL, "bad combine arguments");
+        const long long n = 12LL * c->g.V;
+        DBuf X, Yd;
+        X.ensure(sizeof(double2) * (size_t)ka * n);
+        Yd.ensure(sizeof(double2) * (size_t)kb * n);
+        lqt::to_device_layout(c, (const double2*)x, X.as<double2>(), ka);
+        lqt::to_device_layout(c, (const double2*)y, Yd.as<double2>(), kb);
+        std::vector<zd> C((size_t)ka * kb);
+        std::copy(h_c, h_c + 2 * C.size(), (double*)C.data());
+        lqt::combine_host(c, X.as<double2>(), ka, C, kb, beta, alpha, Yd.as<double2>());
+        lqt::from_device_layout(c, Yd.as<double2>(), (double2*)y, kb);
+        LQT_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+}  // extern "C"

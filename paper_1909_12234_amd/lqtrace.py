@@ -82,7 +82,7 @@ _SIGS = {
     "lqt_prolongator_get": ([_P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
     "lqt_basis_prolongator_from": ([_P, _P, _I, _P, ctypes.POINTER(_P)], _I),
     "lqt_tune": ([_P, _I, _I, ctypes.POINTER(_D)], _I),
-    "lqt_kernel_times": ([_P, _P, _P, _I], _I),
+    "lqt_kernel_times": ([_P, _P, _P, _P, _I], _I),
     "lqt_last_error": ([_P], ctypes.c_char_p),
     "lqt_destroy": ([_P], None),
 }
@@ -190,11 +190,16 @@ class Context:
         self._check(lib().lqt_tune(self._h, int(prec), int(nrhs), ctypes.byref(ms)))
         return ms.value
 
+    KERNEL_FAMILIES = ["dslash", "cgs_dots", "cgs_update", "residual_fp64", "krylov_other", "projections",
+                       "prolongator", "net"]
+
     def kernel_times(self, mode=0):
-        ms = (ctypes.c_double * 4)()
-        calls = (ctypes.c_longlong * 4)()
-        self._check(lib().lqt_kernel_times(self._h, ms, calls, int(mode)))
-        return list(ms), list(calls)
+        """{family: (ms, launches, algorithmic bytes)}; mode 2 starts timing, 3 stops it."""
+        ms = (ctypes.c_double * 8)()
+        calls = (ctypes.c_longlong * 8)()
+        byt = (ctypes.c_double * 8)()
+        self._check(lib().lqt_kernel_times(self._h, ms, calls, byt, int(mode)))
+        return {f: (ms[i], calls[i], byt[i]) for i, f in enumerate(self.KERNEL_FAMILIES)}
 
     # -- dense building blocks
     def gram(self, X, Y):
@@ -223,11 +228,18 @@ class Context:
         return Y
 
     # -- deflation bases
-    def basis_eig(self, k, xi=1e-2, tau=0.0, **opts):
+    def basis_eig(self, k, xi=1e-2, tau=0.0, require_converged=False, **opts):
+        """k smallest-|lambda| eigenpairs of A g5.  A basis whose pairs did not all meet the
+        residual criterion is still returned (basis.converged = False) unless required."""
         h = ctypes.c_void_p()
         o = _opts(**opts)
-        self._check(lib().lqt_basis_eig(self._h, int(k), float(xi), float(tau), ctypes.byref(o), ctypes.byref(h)))
-        return Basis(self, h)
+        rc = lib().lqt_basis_eig(self._h, int(k), float(xi), float(tau), ctypes.byref(o), ctypes.byref(h))
+        self._check(rc, allow=() if require_converged else (LQT_ENOTCONV,))
+        if not h:
+            raise LqtError(rc, lib().lqt_last_error(self._h).decode())
+        b = Basis(self, h)
+        b.converged = rc == 0
+        return b
 
     def basis_prolongator(self, block, nv, k, null_xi=1e-2, null_maxit=200, **opts):
         h = ctypes.c_void_p()

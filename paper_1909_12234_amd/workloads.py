@@ -1,0 +1,28 @@
+"""Named synthetic workloads (lattice, gauge recipe, mass, probes, tolerances).
+
+Gauge fields are seeded random SU(3) links U = exp(i eps H), H = sum_a w_a lambda_a with
+standard-normal w_a (the `synth` package).  Probes are the real Rademacher probes of the
+library (SplitMix64 counter hash) with the seeds below.
+"""
+
+WORKLOADS = {
+    # 4^4, the small workload: exact trace by dense LU
+    "wilson4x4_plain": dict(dims=(4, 4, 4, 4), eps=0.3, seed=1, mass=0.1, nprobes=64, probe_seed=1000,
+                            xi=1e-10, k=16, inner_prec="f64"),
+    # 16^3x32 mixed precision: BF16 inner cycles, FP64 defect correction to 1e-8, k = 64 basis.
+    # The mass sits just inside the left edge of the spectrum of A(0) (complex pairs near
+    # Re lambda = 1.96 for these fields): moving past it makes restarted GMRES stagnate.
+    "wilson16x32_mixed": dict(dims=(16, 16, 16, 32), eps=0.5, seed=1, mass=-1.90, nprobes=128, probe_seed=1001,
+                              xi=1e-8, k=64, inner_prec="bf16"),
+    # three lattices solved one after the other in a batch of 192 probes, FP32 storage
+    "wilson_batched3": dict(lattices=[((8, 8, 8, 8), 1), ((12, 12, 12, 24), 2), ((16, 16, 16, 32), 3)], eps=0.4,
+                            mass=0.1, nprobes=192, probe_seed=1002, xi=1e-8, inner_prec="f32"),
+    # 16^3x32 with the learned preconditioner, 256 probes
+    "wilson16x32_net": dict(dims=(16, 16, 16, 32), eps=0.5, seed=1, mass=-1.90, nprobes=256, probe_seed=1003,
+                            xi=1e-8, inner_prec="bf16"),
+    # 32^3x64 prolongator deflation, 4^4 aggregates, 24 null vectors per chirality, k = 256
+    "wilson32x64_mg": dict(dims=(32, 32, 32, 64), eps=0.5, seed=1, mass=-1.90, nprobes=256, probe_seed=1004,
+                           xi=1e-8, block=(4, 4, 4, 4), nv=24, k=256, inner_prec="bf16"),
+}
+
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
