@@ -95,7 +95,7 @@ def main():
     ctx.tune(prec, nprobes)
     ctx.tune(0, 1)
     t_basis = time.perf_counter()
-    basis = ctx.basis_eig(w["k"], xi=1e-2, prec=lq.F32) if w.get("k") else None
+    basis = ctx.basis_eig(w["k"], xi=1e-2, prec=lq.F32, verbose=1) if w.get("k") else None
     torch.cuda.synchronize()
     t_basis = time.perf_counter() - t_basis
     lam = basis.eigenvalues().numpy().real if basis is not None else np.array([1.0])

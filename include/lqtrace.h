@@ -76,6 +76,9 @@ typedef struct {
     int max_batch;   /* right-hand sides solved together, 0 = all [0]                    */
     int cgs2;        /* 1: re-orthogonalise each Arnoldi step (CGS2) [0: single CGS]     */
     double inner_tol;/* relative reduction asked of one inner cycle [0: one full cycle]  */
+    int verbose;     /* 1: progress lines on stderr from long calls (eigensolver, setup) */
+    int outer_maxit; /* cap on eigensolver iterations (lqt_basis_eig / the coarse
+                        eigensolve of lqt_basis_prolongator) [60]                       */
 } lqt_solver_opts;
 
 /* Per right-hand side solve statistics. */
@@ -147,8 +150,11 @@ int lqt_solve(lqt_ctx *ctx, const double *d_b, double *d_x, int nrhs, double xi,
 
 /* Algorithm 1, first step: the k eigenpairs of the Hermitian operator A g5 with the
  * smallest |lambda| (its eigenvectors are left singular vectors of A), from block
- * subspace iteration with inexact solves (A g5)^{-1}_xi = g5 A^{-1}_xi and FP64
- * Rayleigh-Ritz.  A pair is accepted when ||A g5 u - theta u|| <= xi * sigma_max(A).
+ * inexact inverse iteration with solves (A g5)^{-1} = g5 A^{-1} to xi/10 and FP64
+ * Rayleigh-Ritz over the previous iterate and its image.  A pair is accepted when
+ * ||A g5 u - theta u|| <= xi |theta|, which implies the convergence test of the paper's
+ * Table 1 (||g5 A^{-1} u - u/theta|| <= xi ||A^{-1}||).  Returns LQT_ENOTCONV (with the
+ * basis in *out) if not all k pairs pass within 60 iterations.
  * tau must be 0 (the i*tau*g5 shift of Section 3.2 is not implemented; LQT_EINVAL).
  * *out receives a basis owned by the caller (free with lqt_basis_free); the context
  * must outlive it. */
@@ -156,11 +162,16 @@ int lqt_basis_eig(lqt_ctx *ctx, int k, double xi, double tau, const lqt_solver_o
                   lqt_basis **out);
 
 /* Algorithm 2, first three steps: the multigrid prolongator W built from nv near-null
- * vectors (Gaussian starts, inverse iteration with solves to null_xi or null_maxit Arnoldi
- * steps), blocked on block[0..3]-site aggregates and split by chirality (spins {0,1} and
- * {2,3}), orthonormalised per (aggregate, chirality); then the k eigenvectors of the
- * Hermitian coarse operator g5^W W^+ A W with the smallest |lambda|, rotated so that
- * U^+ g5 A U is diagonal.  Block extents must divide the lattice. */
+ * vectors (approximate solutions of A y = 0 from Gaussian starts y0, Section 2: y = y0 - e
+ * with A e = A y0 solved to null_xi or null_maxit Arnoldi steps), blocked on
+ * block[0..3]-site aggregates and split by chirality (spins {0,1} and {2,3}), orthonormalised
+ * per (aggregate, chirality) by two passes of modified Gram-Schmidt; then the k eigenvectors
+ * of the Hermitian coarse operator g5^W W^+ A W with the smallest |lambda| (subspace
+ * iteration on its inverse, MINRES inner solves, accepted at null_xi as in lqt_basis_eig),
+ * rotated so that U^+ g5^W W^+ A W U is diagonal.  The coarse vectors U_c are kept; the
+ * fine basis is U = W U_c.  Block extents must divide the lattice; 1 <= nv <= 64; k may be
+ * 0 (prolongator only).  Returns LQT_ENOTCONV (with the basis in *out) if the coarse
+ * eigenpairs did not all pass. */
 int lqt_basis_prolongator(lqt_ctx *ctx, const int block[4], int nv, int k, double null_xi,
                           int null_maxit, const lqt_solver_opts *opts, lqt_basis **out);
 
@@ -174,7 +185,8 @@ int lqt_basis_from_vectors(lqt_ctx *ctx, const double *d_vectors, int k, lqt_bas
  * NULL to query k; otherwise it must hold 2*k doubles (complex). */
 int lqt_basis_eigenvalues(const lqt_basis *basis, double *h_lambda, int *k);
 
-/* Copy the k basis vectors U (canonical complex128 layout) to device memory d_out. */
+/* Copy the k fine basis vectors U (canonical complex128 layout) to device memory d_out;
+ * for a prolongator basis U = W U_c is formed on the fly. */
 int lqt_basis_vectors(const lqt_basis *basis, double *d_out);
 
 void lqt_basis_free(lqt_basis *basis);
@@ -251,9 +263,13 @@ int lqt_prolong(lqt_ctx *ctx, const lqt_basis *basis, const double *d_coarse, do
  * site_in_block with x fastest, spin2 = spin - 2*chirality) to device memory.  Returns the
  * coarse dimension in *nc. */
 int lqt_prolongator_get(const lqt_basis *basis, double *d_w, long long *nc);
-/* Install a prolongator from caller-supplied W in the layout above (device). */
+/* Install a prolongator from caller-supplied W in the layout above (device), and optionally
+ * k coarse vectors U_bar (device, k x nc, may be NULL when k = 0): the library then forms
+ * M = U_bar^+ g5^W W^+ A W U_bar, diagonalises it and keeps U_c = U_bar U_hat (Algorithm 2,
+ * third step), giving a basis usable by lqt_trace.  W is used as given (its blocks are
+ * expected orthonormal). */
 int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const double *d_w,
-                               lqt_basis **out);
+                               const double *d_coarse, int k, lqt_basis **out);
 
 /* Autotuner: time the candidate dslash tilings for (prec, nrhs) now and cache the choice
  * in the context; *ms receives the best time (may be NULL). */

@@ -17,4 +17,9 @@ void heev(int n, const std::vector<zd>& A, std::vector<double>& w, std::vector<z
 // row-major) with X T orthonormal, r = numerical rank (eigenvalues above rtol * max).
 int orthonormalizer(int n, const std::vector<zd>& G, std::vector<zd>& T, double rtol);
 
+// Cholesky G = R^+ R of a Hermitian positive definite n x n matrix; on success T = R^{-1}
+// (upper triangular, row-major) so that X R^{-1} is orthonormal when G = X^+ X.  Returns
+// false when a pivot is not positive (G numerically singular).
+bool chol_inverse(int n, const std::vector<zd>& G, std::vector<zd>& T);
+
 }  // namespace lqt

@@ -87,4 +87,33 @@ int orthonormalizer(int n, const std::vector<zd>& G, std::vector<zd>& T, double 
     return r;
 }
 
+bool chol_inverse(int n, const std::vector<zd>& G, std::vector<zd>& T) {
+    std::vector<zd> R((size_t)n * n, zd(0, 0));
+    double dmax = 0;
+    for (int i = 0; i < n; i++) dmax = std::max(dmax, G[i * n + i].real());
+    for (int i = 0; i < n; i++) {
+        zd s = G[i * n + i];
+        for (int k = 0; k < i; k++) s -= std::conj(R[k * n + i]) * R[k * n + i];
+        if (!(s.real() > 1e-14 * dmax)) return false;
+        double d = std::sqrt(s.real());
+        R[i * n + i] = d;
+        for (int j = i + 1; j < n; j++) {
+            zd t = G[i * n + j];
+            for (int k = 0; k < i; k++) t -= std::conj(R[k * n + i]) * R[k * n + j];
+            R[i * n + j] = t / d;
+        }
+    }
+    // T = R^{-1} by back substitution, column by column
+    T.assign((size_t)n * n, zd(0, 0));
+    for (int j = 0; j < n; j++) {
+        T[j * n + j] = 1.0 / R[j * n + j];
+        for (int i = j - 1; i >= 0; i--) {
+            zd s = 0;
+            for (int k = i + 1; k <= j; k++) s += R[i * n + k] * T[k * n + j];
+            T[i * n + j] = -s / R[i * n + i];
+        }
+    }
+    return true;
+}
+
 }  // namespace lqt

@@ -1,0 +1,555 @@
+// Multigrid prolongator W and the coarse-space deflation of Algorithm 2.
+//
+// Aggregates are disjoint blocks of b0 x b1 x b2 x b3 sites.  For aggregate a and chirality
+// c (c = 0: spins {0,1}, c = 1: spins {2,3}; g5 = +1 / -1) the block W_{a,c} holds nv
+// orthonormal columns of length d = 6 * (sites per block), the restrictions of nv near-null
+// vectors to that block and chirality (Section 2: blocking; g5 W = W g5^W by construction).
+//   W layout     [a][c][v][bs][s2][colour] complex128, bs = site inside the block, x fastest
+//   coarse       [rhs][a][c][v]            complex128, length nc = 2 * nagg * nv
+// Near-null vectors follow the paper's adaptive setup: approximate solutions of A y = 0 from
+// random starts y0, i.e. y = y0 - e with A e = A y0 solved to null_xi or null_maxit steps.
+// The coarse operator g5^W W^+ A W is applied implicitly (prolong, Wilson operator, restrict).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <new>
+
+#include "blas.h"
+#include "gemm.h"
+#include "hostla.h"
+#include "lqt_internal.h"
+#include "minres.h"
+#include "prolong.h"
+#include "solver.h"
+
+using lqt::DBuf;
+using lqt::Error;
+using lqt::zd;
+
+namespace lqt {
+
+struct PG {
+    int L0, L1, L2, L3;  // lattice
+    int b0, b1, b2, b3;  // block
+    int n0, n1, n2;      // blocks per direction (x, y, z)
+    int nagg, bsites, d, nv;
+    int V;
+};
+
+static PG make_pg(const lqt_ctx* c, const int* b, int nv) {
+    PG p;
+    p.L0 = c->g.L[0], p.L1 = c->g.L[1], p.L2 = c->g.L[2], p.L3 = c->g.L[3];
+    p.b0 = b[0], p.b1 = b[1], p.b2 = b[2], p.b3 = b[3];
+    p.n0 = p.L0 / p.b0, p.n1 = p.L1 / p.b1, p.n2 = p.L2 / p.b2;
+    p.bsites = p.b0 * p.b1 * p.b2 * p.b3;
+    p.nagg = c->g.V / p.bsites;
+    p.d = 6 * p.bsites;
+    p.nv = nv;
+    p.V = c->g.V;
+    return p;
+}
+
+static PG pg_of(const lqt_basis* B) {
+    PG p = make_pg(B->ctx, B->block, B->nv);
+    return p;
+}
+
+__device__ __forceinline__ int site_of(const PG& p, int agg, int bs) {
+    const int ax = agg % p.n0, ay = (agg / p.n0) % p.n1, az = (agg / (p.n0 * p.n1)) % p.n2,
+              at = agg / (p.n0 * p.n1 * p.n2);
+    const int bx = bs % p.b0, by = (bs / p.b0) % p.b1, bz = (bs / (p.b0 * p.b1)) % p.b2,
+              bt = bs / (p.b0 * p.b1 * p.b2);
+    const int x = ax * p.b0 + bx, y = ay * p.b1 + by, z = az * p.b2 + bz, t = at * p.b3 + bt;
+    return x + p.L0 * (y + p.L1 * (z + p.L2 * t));
+}
+
+__device__ __forceinline__ double pwsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t psm64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------- W from near-null vectors
+// W[a][c][v][e] = y_v(comp, site) with e = bs*6 + s2*3 + col, comp = (2c + s2)*3 + col
+__global__ void k_gather_null(const double2* __restrict__ Y, PG p, double2* __restrict__ W) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)p.nagg * 2 * p.nv * p.d;
+    if (i >= tot) return;
+    const int e = (int)(i % p.d);
+    long long r = i / p.d;
+    const int v = (int)(r % p.nv);
+    r /= p.nv;
+    const int ch = (int)(r % 2), agg = (int)(r / 2);
+    const int bs = e / 6, s2 = (e % 6) / 3, col = e % 3;
+    const int comp = (2 * ch + s2) * 3 + col;
+    W[i] = Y[(long long)v * 12 * p.V + (long long)comp * p.V + site_of(p, agg, bs)];
+}
+
+// Modified Gram-Schmidt (two passes) on the nv columns of each block W_{a,c}; one workgroup
+// per block.  A column that vanishes stays zero.
+__global__ __launch_bounds__(256) void k_block_mgs(double2* __restrict__ W, PG p) {
+    __shared__ double red[4][2];
+    __shared__ double bc[2];
+    double2* Wb = W + (long long)blockIdx.x * p.nv * p.d;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int pass = 0; pass < 2; pass++)
+        for (int v = 0; v < p.nv; v++) {
+            double2* wv = Wb + (long long)v * p.d;
+            for (int u = 0; u < v; u++) {
+                const double2* wu = Wb + (long long)u * p.d;
+                double a = 0, b = 0;
+                for (int e = threadIdx.x; e < p.d; e += 256) {
+                    double2 x = wu[e], y = wv[e];
+                    a += x.x * y.x + x.y * y.y;
+                    b += x.x * y.y - x.y * y.x;
+                }
+                a = pwsum(a);
+                b = pwsum(b);
+                if (lane == 0) red[wave][0] = a, red[wave][1] = b;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    bc[0] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+                    bc[1] = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+                }
+                __syncthreads();
+                const double hr = bc[0], hi = bc[1];
+                for (int e = threadIdx.x; e < p.d; e += 256) {
+                    double2 x = wu[e], y = wv[e];
+                    wv[e] = make_double2(y.x - (hr * x.x - hi * x.y), y.y - (hr * x.y + hi * x.x));
+                }
+                __syncthreads();
+            }
+            double a = 0;
+            for (int e = threadIdx.x; e < p.d; e += 256) {
+                double2 y = wv[e];
+                a += y.x * y.x + y.y * y.y;
+            }
+            a = pwsum(a);
+            if (lane == 0) red[wave][0] = a;
+            __syncthreads();
+            if (threadIdx.x == 0) bc[0] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+            __syncthreads();
+            const double nrm = sqrt(bc[0]);
+            const double s = nrm > 1e-300 ? 1.0 / nrm : 0.0;
+            for (int e = threadIdx.x; e < p.d; e += 256) {
+                double2 y = wv[e];
+                wv[e] = make_double2(s * y.x, s * y.y);
+            }
+            __syncthreads();
+        }
+}
+
+// ---------------------------------------------------------------- restrict / prolong
+constexpr int RB = 8;  // right-hand sides per workgroup: each W entry is read once per RB
+
+// coarse[r][(a*2 + c)*nv + v] = sum_e conj(W[a][c][v][e]) y_r(e); grid (nagg*2, ceil(nrhs/RB)).
+// PROBES: y_r is the Rademacher probe j0 + r, and the result goes to out_up (c = 0) or
+// out_dn (c = 1) with zeros in the other.
+template <bool PROBES>
+__global__ __launch_bounds__(256) void k_restrict(const double2* __restrict__ W, PG p, const double2* __restrict__ y,
+                                                  int nrhs, uint64_t seed, long long j0, double2* __restrict__ out,
+                                                  double2* __restrict__ out_dn) {
+    extern __shared__ double lds[];  // [nv][RB][4 waves][2]
+    const int blk = blockIdx.x, agg = blk >> 1, ch = blk & 1;
+    const int r0 = blockIdx.y * RB;
+    const int nr = min(RB, nrhs - r0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double2* Wb = W + (long long)blk * p.nv * p.d;
+    const long long n = 12LL * p.V;
+    for (int v = 0; v < p.nv; v++) {
+        double ar[RB], ai[RB];
+#pragma unroll
+        for (int r = 0; r < RB; r++) ar[r] = ai[r] = 0;
+        for (int e = threadIdx.x; e < p.d; e += 256) {
+            const double2 w = Wb[(long long)v * p.d + e];
+            const int bs = e / 6, s2 = (e % 6) / 3, col = e % 3;
+            const int comp = (2 * ch + s2) * 3 + col;
+            const int site = site_of(p, agg, bs);
+            uint64_t hi = 0;
+            if (PROBES) hi = psm64((uint64_t)(12LL * site + comp));
+#pragma unroll
+            for (int r = 0; r < RB; r++) {
+                if (r < nr) {
+                    double2 yv;
+                    if (PROBES) {
+                        double z = (psm64(seed ^ psm64((uint64_t)(j0 + r0 + r) ^ hi)) >> 63) ? -1.0 : 1.0;
+                        yv = make_double2(z, 0.0);
+                    } else {
+                        yv = y[(long long)(r0 + r) * n + (long long)comp * p.V + site];
+                    }
+                    ar[r] += w.x * yv.x + w.y * yv.y;
+                    ai[r] += w.x * yv.y - w.y * yv.x;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; r++) {
+            double a = pwsum(ar[r]), b = pwsum(ai[r]);
+            if (lane == 0) {
+                lds[((v * RB + r) * 4 + wave) * 2] = a;
+                lds[((v * RB + r) * 4 + wave) * 2 + 1] = b;
+            }
+        }
+    }
+    __syncthreads();
+    const long long nc = 2LL * p.nagg * p.nv;
+    for (int t = threadIdx.x; t < p.nv * RB; t += 256) {
+        const int v = t / RB, r = t % RB;
+        if (r >= nr) continue;
+        double a = 0, b = 0;
+        for (int w = 0; w < 4; w++) {
+            a += lds[((v * RB + r) * 4 + w) * 2];
+            b += lds[((v * RB + r) * 4 + w) * 2 + 1];
+        }
+        const long long o = (long long)(r0 + r) * nc + (long long)blk * p.nv + v;
+        if (PROBES) {
+            out[o] = ch == 0 ? make_double2(a, b) : make_double2(0, 0);
+            out_dn[o] = ch == 1 ? make_double2(a, b) : make_double2(0, 0);
+        } else {
+            out[o] = make_double2(a, b);
+        }
+    }
+}
+
+// y_r(e) = sum_v W[a][c][v][e] coarse[r][(a*2 + c)*nv + v]; grid (nagg*2, ceil(nrhs/RB))
+__global__ __launch_bounds__(256) void k_prolong(const double2* __restrict__ W, PG p, const double2* __restrict__ cin,
+                                                 int nrhs, double2* __restrict__ y) {
+    extern __shared__ double2 cv[];  // [RB][nv]
+    const int blk = blockIdx.x, agg = blk >> 1, ch = blk & 1;
+    const int r0 = blockIdx.y * RB;
+    const int nr = min(RB, nrhs - r0);
+    const long long nc = 2LL * p.nagg * p.nv;
+    const long long n = 12LL * p.V;
+    for (int t = threadIdx.x; t < RB * p.nv; t += 256) {
+        const int r = t / p.nv, v = t % p.nv;
+        cv[t] = r < nr ? cin[(long long)(r0 + r) * nc + (long long)blk * p.nv + v] : make_double2(0, 0);
+    }
+    __syncthreads();
+    const double2* Wb = W + (long long)blk * p.nv * p.d;
+    for (int e = threadIdx.x; e < p.d; e += 256) {
+        double ar[RB], ai[RB];
+#pragma unroll
+        for (int r = 0; r < RB; r++) ar[r] = ai[r] = 0;
+        for (int v = 0; v < p.nv; v++) {
+            const double2 w = Wb[(long long)v * p.d + e];
+#pragma unroll
+            for (int r = 0; r < RB; r++) {
+                const double2 cc = cv[r * p.nv + v];
+                ar[r] += w.x * cc.x - w.y * cc.y;
+                ai[r] += w.x * cc.y + w.y * cc.x;
+            }
+        }
+        const int bs = e / 6, s2 = (e % 6) / 3, col = e % 3;
+        const int comp = (2 * ch + s2) * 3 + col;
+        const int site = site_of(p, agg, bs);
+#pragma unroll
+        for (int r = 0; r < RB; r++)
+            if (r < nr) y[(long long)(r0 + r) * n + (long long)comp * p.V + site] = make_double2(ar[r], ai[r]);
+    }
+}
+
+// coarse g5^W: negate the chirality-1 entries
+__global__ void k_g5c(double2* __restrict__ x, long long nc, int nv, long long total) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    long long e = i % nc;
+    if ((e / nv) & 1) {
+        double2 v = x[i];
+        x[i] = make_double2(-v.x, -v.y);
+    }
+}
+
+// y = y0 - e (near-null vectors from A e = A y0)
+__global__ void k_sub(const double2* __restrict__ a, double2* __restrict__ b, long long total) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    double2 x = a[i], y = b[i];
+    b[i] = make_double2(x.x - y.x, x.y - y.y);
+}
+
+static dim3 g1(long long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+void restrict_fields(lqt_ctx* c, const lqt_basis* B, const double2* fine, double2* coarse, int nrhs) {
+    if (nrhs <= 0) return;
+    PG p = pg_of(B);
+    dim3 grid(p.nagg * 2, (nrhs + RB - 1) / RB);
+    size_t lds = sizeof(double) * p.nv * RB * 4 * 2;
+    c->timer.begin(c->stream, KT_PR);
+    hipLaunchKernelGGL((k_restrict<false>), grid, dim3(256), lds, c->stream, B->W.as<double2>(), p, fine, nrhs, 0ull,
+                       0ll, coarse, (double2*)nullptr);
+    LQT_HIP(hipGetLastError());
+    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V * grid.y + (double)nrhs * 12 * p.V +
+                                    (double)nrhs * 2 * p.nagg * p.nv));
+}
+
+void prolong_fields(lqt_ctx* c, const lqt_basis* B, const double2* coarse, double2* fine, int nrhs) {
+    if (nrhs <= 0) return;
+    PG p = pg_of(B);
+    dim3 grid(p.nagg * 2, (nrhs + RB - 1) / RB);
+    size_t lds = sizeof(double2) * RB * p.nv;
+    c->timer.begin(c->stream, KT_PR);
+    hipLaunchKernelGGL(k_prolong, grid, dim3(256), lds, c->stream, B->W.as<double2>(), p, coarse, nrhs, fine);
+    LQT_HIP(hipGetLastError());
+    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V * grid.y + (double)nrhs * 12 * p.V +
+                                    (double)nrhs * 2 * p.nagg * p.nv));
+}
+
+// out_f = g5^W W^+ A W in_f (FP64), nf coarse vectors, in chunks that bound the fine memory
+static void coarse_herm(lqt_ctx* c, const lqt_basis* B, const double2* in, double2* out, int nf) {
+    const long long n = 12LL * c->g.V;
+    const long long nc = 2LL * B->nagg * B->nv;
+    const int chunk = (int)std::max<long long>(1, std::min<long long>(nf, (8LL << 30) / (2 * n * 16)));
+    c->scratch[10].ensure(sizeof(double2) * (size_t)chunk * n);
+    c->scratch[11].ensure(sizeof(double2) * (size_t)chunk * n);
+    for (int f0 = 0; f0 < nf; f0 += chunk) {
+        const int cs = std::min(chunk, nf - f0);
+        prolong_fields(c, B, in + (size_t)f0 * nc, c->scratch[10].as<double2>(), cs);
+        dslash(c, LQT_F64, LQT_A, c->scratch[10].p, c->scratch[11].p, cs, n, n);
+        restrict_fields(c, B, c->scratch[11].as<double2>(), out + (size_t)f0 * nc, cs);
+    }
+    long long tot = nc * nf;
+    hipLaunchKernelGGL(k_g5c, g1(tot), dim3(256), 0, c->stream, out, nc, B->nv, tot);
+    LQT_HIP(hipGetLastError());
+}
+
+void prolong_project_probes(lqt_ctx* c, const lqt_basis* B, uint64_t seed, long long j0, int s, double2* cup,
+                            double2* cdn) {
+    PG p = pg_of(B);
+    const long long nc = 2LL * p.nagg * p.nv;
+    DBuf rz;
+    rz.ensure(sizeof(double2) * (size_t)s * nc * 2);
+    double2* up = rz.as<double2>();
+    double2* dn = up + (size_t)s * nc;
+    dim3 grid(p.nagg * 2, (s + RB - 1) / RB);
+    size_t lds = sizeof(double) * p.nv * RB * 4 * 2;
+    c->timer.begin(c->stream, KT_PR);
+    hipLaunchKernelGGL((k_restrict<true>), grid, dim3(256), lds, c->stream, B->W.as<double2>(), p,
+                       (const double2*)nullptr, s, seed, j0, up, dn);
+    LQT_HIP(hipGetLastError());
+    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V * grid.y + 2.0 * s * nc));
+    gemm_gram(c, B->Uc.as<double2>(), B->k, up, s, cup, nc);
+    gemm_gram(c, B->Uc.as<double2>(), B->k, dn, s, cdn, nc);
+}
+
+// Coarse oblique data from coarse vectors Ubar (k, device): M = Ubar^+ g5^W W^+ A W Ubar,
+// eigh, Uc = Ubar U_hat, u_i^+ g5 u_i = Uc_i^+ g5^W Uc_i.
+static void coarse_oblique_setup(lqt_ctx* c, lqt_basis* B, const double2* Ubar, int k) {
+    const long long nc = 2LL * B->nagg * B->nv;
+    DBuf HU, G5U, Md;
+    HU.ensure(sizeof(double2) * (size_t)k * nc);
+    coarse_herm(c, B, Ubar, HU.as<double2>(), k);
+    Md.ensure(sizeof(double2) * (size_t)k * k);
+    gemm_gram(c, Ubar, k, HU.as<double2>(), k, Md.as<double2>(), nc);
+    std::vector<zd> M((size_t)k * k);
+    LQT_HIP(hipMemcpyAsync(M.data(), Md.p, sizeof(double2) * M.size(), hipMemcpyDeviceToHost, c->stream));
+    LQT_HIP(hipStreamSynchronize(c->stream));
+    std::vector<double> lam;
+    std::vector<zd> Uh;
+    heev(k, M, lam, Uh, true);
+    LQT_HIP(hipMemcpyAsync(Md.p, Uh.data(), sizeof(double2) * Uh.size(), hipMemcpyHostToDevice, c->stream));
+    B->Uc.ensure(sizeof(double2) * (size_t)k * nc);
+    gemm_combine(c, Ubar, k, Md.as<double2>(), k, 0.0, 1.0, B->Uc.as<double2>(), nc);
+    G5U.ensure(sizeof(double2) * (size_t)k * nc);
+    LQT_HIP(hipMemcpyAsync(G5U.p, B->Uc.p, sizeof(double2) * (size_t)k * nc, hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_g5c, g1(nc * k), dim3(256), 0, c->stream, G5U.as<double2>(), nc, B->nv, nc * k);
+    LQT_HIP(hipGetLastError());
+    gemm_gram(c, B->Uc.as<double2>(), k, G5U.as<double2>(), k, Md.as<double2>(), nc);
+    std::vector<zd> D((size_t)k * k);
+    LQT_HIP(hipMemcpyAsync(D.data(), Md.p, sizeof(double2) * D.size(), hipMemcpyDeviceToHost, c->stream));
+    LQT_HIP(hipStreamSynchronize(c->stream));
+    B->k = k;
+    B->lambda.assign(2 * k, 0.0);
+    B->ug5u.assign(2 * k, 0.0);
+    for (int i = 0; i < k; i++) {
+        B->lambda[2 * i] = lam[i];
+        B->ug5u[2 * i] = D[(size_t)i * k + i].real();
+        B->ug5u[2 * i + 1] = D[(size_t)i * k + i].imag();
+    }
+}
+
+static void check_block(const lqt_ctx* c, const int* block, int nv) {
+    LQT_CHECK(block, LQT_EINVAL, "null block");
+    for (int i = 0; i < 4; i++)
+        LQT_CHECK(block[i] >= 1 && c->g.L[i] % block[i] == 0, LQT_EINVAL, "block extents must divide the lattice");
+    const int bs = block[0] * block[1] * block[2] * block[3];
+    LQT_CHECK(nv >= 1 && nv <= 64 && nv <= 6 * bs, LQT_EINVAL, "nv must be in 1..min(64, 6 * block sites)");
+}
+
+}  // namespace lqt
+
+namespace {
+
+template <typename F>
+int guard(lqt_ctx* c, F&& f) {
+    try {
+        f();
+        return LQT_OK;
+    } catch (const Error& e) {
+        if (c) c->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        return LQT_ENOMEM;
+    } catch (...) {
+        if (c) c->err = "unexpected exception";
+        return LQT_EINVAL;
+    }
+}
+
+lqt_basis* new_prolongator(lqt_ctx* c, const int* block, int nv) {
+    lqt_basis* B = new lqt_basis();
+    B->ctx = c;
+    B->kind = 1;
+    for (int i = 0; i < 4; i++) B->block[i] = block[i];
+    B->nv = nv;
+    lqt::PG p = lqt::make_pg(c, block, nv);
+    B->nagg = p.nagg;
+    B->W.ensure(sizeof(double2) * (size_t)nv * 12 * c->g.V);
+    return B;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lqt_basis_prolongator(lqt_ctx* c, const int block[4], int nv, int k, double null_xi, int null_maxit,
+                          const lqt_solver_opts* opts, lqt_basis** out) {
+    if (!c || !out) return LQT_EINVAL;
+    *out = nullptr;
+    return guard(c, [&] {
+        LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
+        lqt::check_block(c, block, nv);
+        LQT_CHECK(null_xi > 0 && null_xi < 1 && null_maxit >= 1, LQT_EINVAL, "bad null-vector tolerance");
+        const long long n = 12LL * c->g.V;
+        lqt_basis* B = new_prolongator(c, block, nv);
+        const long long nc = 2LL * B->nagg * nv;
+        LQT_CHECK(k >= 0 && k <= nc / 8, LQT_EINVAL, "k must be in 0..nc/8");
+        try {
+            lqt::SolveOpts o = lqt::make_opts(opts);
+            // near-null vectors: y = y0 - e, A e = A y0 to null_xi or null_maxit steps
+            lqt::SolveOpts on = o;
+            on.maxit = null_maxit;
+            DBuf Y0, AY, E;
+            Y0.ensure(sizeof(double2) * (size_t)nv * n);
+            AY.ensure(sizeof(double2) * (size_t)nv * n);
+            E.ensure(sizeof(double2) * (size_t)nv * n);
+            lqt::gaussian_fields(c, 0x4E554C4Cull, n, nv, Y0.as<double2>());
+            lqt::dslash(c, LQT_F64, LQT_A, Y0.p, AY.p, nv, n, n);
+            std::vector<lqt_solve_stats> st(nv);
+            lqt::solve_fields(c, AY.as<double2>(), E.as<double2>(), nv, null_xi, on, st.data());
+            hipLaunchKernelGGL(lqt::k_sub, lqt::g1((long long)nv * n), dim3(256), 0, c->stream, Y0.as<double2>(),
+                               E.as<double2>(), (long long)nv * n);
+            LQT_HIP(hipGetLastError());
+            if (o.verbose) {
+                fprintf(stderr, "[lqtrace] prolongator: %d near-null vectors, %d steps each\n", nv, st[0].iters);
+                fflush(stderr);
+            }
+            // block, split by chirality, orthonormalise
+            lqt::PG p = lqt::make_pg(c, block, nv);
+            long long tot = (long long)p.nagg * 2 * nv * p.d;
+            hipLaunchKernelGGL(lqt::k_gather_null, lqt::g1(tot), dim3(256), 0, c->stream, E.as<double2>(), p,
+                               B->W.as<double2>());
+            hipLaunchKernelGGL(lqt::k_block_mgs, dim3(p.nagg * 2), dim3(256), 0, c->stream, B->W.as<double2>(), p);
+            LQT_HIP(hipGetLastError());
+            if (k > 0) {
+                // Algorithm 2, second step: k eigenpairs of g5^W W^+ A W with smallest |lambda|
+                lqt::HermOp H = [c, B](const double2* in, double2* o2, int nf) { lqt::coarse_herm(c, B, in, o2, nf); };
+                DBuf Qb;
+                std::vector<double> theta, resT;
+                int conv = lqt::eig_subspace(c, nc, H, k, null_xi, o.outer_maxit, std::min(o.maxit, 4000), o.verbose,
+                                             Qb, theta, resT);
+                // third step: rotate so that U^+ g5^W W^+ A W U is diagonal
+                lqt::coarse_oblique_setup(c, B, Qb.as<double2>(), k);
+                B->theta.assign(theta.begin(), theta.begin() + k);
+                B->resid.assign(resT.begin(), resT.begin() + k);
+                LQT_HIP(hipStreamSynchronize(c->stream));
+                *out = B;
+                if (conv < k) {
+                    c->err = "coarse eigensolver: " + std::to_string(conv) + " of " + std::to_string(k) +
+                             " pairs converged";
+                    throw Error{LQT_ENOTCONV, c->err};
+                }
+                return;
+            }
+            LQT_HIP(hipStreamSynchronize(c->stream));
+        } catch (const Error& e) {
+            if (*out == nullptr) delete B;
+            throw;
+        }
+        *out = B;
+    });
+}
+
+int lqt_basis_prolongator_from(lqt_ctx* c, const int block[4], int nv, const double* d_w, const double* d_coarse,
+                               int k, lqt_basis** out) {
+    if (!c || !out) return LQT_EINVAL;
+    *out = nullptr;
+    return guard(c, [&] {
+        LQT_CHECK(c->have_gauge || k == 0, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
+        lqt::check_block(c, block, nv);
+        LQT_CHECK(d_w, LQT_EINVAL, "null prolongator");
+        LQT_CHECK(k >= 0 && (k == 0 || d_coarse), LQT_EINVAL, "coarse vectors missing");
+        lqt_basis* B = new_prolongator(c, block, nv);
+        try {
+            LQT_HIP(hipMemcpyAsync(B->W.p, d_w, sizeof(double2) * (size_t)nv * 12 * c->g.V, hipMemcpyDeviceToDevice,
+                                   c->stream));
+            if (k > 0) lqt::coarse_oblique_setup(c, B, (const double2*)d_coarse, k);
+            LQT_HIP(hipStreamSynchronize(c->stream));
+        } catch (...) {
+            delete B;
+            throw;
+        }
+        *out = B;
+    });
+}
+
+int lqt_restrict(lqt_ctx* c, const lqt_basis* B, const double* fine, double* coarse, int nrhs) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(B && B->kind == 1 && B->ctx == c, LQT_EINVAL, "not a prolongator basis of this context");
+        LQT_CHECK(nrhs >= 0 && (nrhs == 0 || (fine && coarse)), LQT_EINVAL, "bad fields");
+        if (nrhs == 0) return;
+        const long long n = 12LL * c->g.V;
+        DBuf f;
+        f.ensure(sizeof(double2) * (size_t)nrhs * n);
+        lqt::to_device_layout(c, (const double2*)fine, f.as<double2>(), nrhs);
+        lqt::restrict_fields(c, B, f.as<double2>(), (double2*)coarse, nrhs);
+        LQT_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+int lqt_prolong(lqt_ctx* c, const lqt_basis* B, const double* coarse, double* fine, int nrhs) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(B && B->kind == 1 && B->ctx == c, LQT_EINVAL, "not a prolongator basis of this context");
+        LQT_CHECK(nrhs >= 0 && (nrhs == 0 || (fine && coarse)), LQT_EINVAL, "bad fields");
+        if (nrhs == 0) return;
+        const long long n = 12LL * c->g.V;
+        DBuf f;
+        f.ensure(sizeof(double2) * (size_t)nrhs * n);
+        lqt::prolong_fields(c, B, (const double2*)coarse, f.as<double2>(), nrhs);
+        lqt::from_device_layout(c, f.as<double2>(), (double2*)fine, nrhs);
+        LQT_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+int lqt_prolongator_get(const lqt_basis* B, double* d_w, long long* nc) {
+    if (!B || B->kind != 1) return LQT_EINVAL;
+    if (nc) *nc = 2LL * B->nagg * B->nv;
+    if (d_w) {
+        if (hipMemcpyAsync(d_w, B->W.p, sizeof(double2) * (size_t)B->nv * 12 * B->ctx->g.V, hipMemcpyDeviceToDevice,
+                           B->ctx->stream) != hipSuccess)
+            return LQT_EHIP;
+        if (hipStreamSynchronize(B->ctx->stream) != hipSuccess) return LQT_EHIP;
+    }
+    return LQT_OK;
+}
+
+}  // extern "C"

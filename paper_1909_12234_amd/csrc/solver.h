@@ -12,6 +12,8 @@ struct SolveOpts {
     int max_batch = 0;
     int cgs2 = 0;
     double inner_tol = 0.0;
+    int verbose = 0;
+    int outer_maxit = 60;
 };
 
 SolveOpts make_opts(const lqt_solver_opts* u);

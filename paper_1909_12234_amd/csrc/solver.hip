@@ -9,6 +9,7 @@
 // batch at the next restart, so the remaining ones stay contiguous.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 
 #include "blas.h"
 #include "krylov.h"
@@ -163,6 +164,13 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         }
         if (nact.empty()) break;
         const int nn = (int)nact.size();
+        if (o.verbose && (cyc[nact[0]] % 16) == 0) {
+            double mx = 0;
+            for (int i : nact) mx = std::max(mx, rel[i]);
+            fprintf(stderr, "[lqtrace] solve: %d of %d systems active, cycle %d, max relres %.3e\n", nn, nb,
+                    cyc[nact[0]], mx);
+            fflush(stderr);
+        }
         // new active list; src maps new slot -> slot of r
         LQT_HIP(hipMemcpyAsync(act_d, nact.data(), sizeof(int) * nn, hipMemcpyHostToDevice, c->stream));
         LQT_HIP(hipMemcpyAsync(src_d, src.data(), sizeof(int) * nn, hipMemcpyHostToDevice, c->stream));
@@ -216,6 +224,8 @@ SolveOpts make_opts(const lqt_solver_opts* u) {
         o.max_batch = u->max_batch;
         o.cgs2 = u->cgs2;
         o.inner_tol = u->inner_tol > 0 ? u->inner_tol : 0.0;
+        o.verbose = u->verbose;
+        o.outer_maxit = u->outer_maxit > 0 ? u->outer_maxit : 60;
     }
     return o;
 }

@@ -16,12 +16,15 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <chrono>
+#include <cstdio>
 #include <new>
 
 #include "blas.h"
 #include "gemm.h"
 #include "hostla.h"
 #include "lqt_internal.h"
+#include "minres.h"
 #include "prolong.h"
 #include "solver.h"
 
@@ -31,8 +34,10 @@ using lqt::zd;
 
 namespace lqt {
 
+// Host -> device from pageable memory; waits, so the host buffer may be released at once.
 static void h2d(lqt_ctx* c, void* d, const void* h, size_t bytes) {
     LQT_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream));
+    LQT_HIP(hipStreamSynchronize(c->stream));
 }
 static void d2h(lqt_ctx* c, void* h, const void* d, size_t bytes) {
     LQT_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, c->stream));
@@ -123,6 +128,72 @@ double sigma_max(lqt_ctx* c) {
     }
     c->sigma_max = est;
     return est;
+}
+
+
+int eig_subspace(lqt_ctx* c, long long n, const HermOp& H, int k, double xi, int maxit, int inner_maxit,
+                 int verbose, DBuf& Qout, std::vector<double>& theta, std::vector<double>& resT) {
+    // Subspace iteration with Rayleigh-Ritz on T = H^{-1}_xi (exterior eigenvalues of T, so
+    // no spurious interior Ritz values): V orthonormal (kk = k + guard vectors), Y = T V by
+    // batched MINRES (solves to xi/10), K = V^+ Y = E diag(mu) E^+ with |mu| descending.
+    // Ritz pair i, (V E_i, theta_i = 1/mu_i), passes the test of the paper's Table 1 when
+    // ||Y E_i - mu_i V E_i|| <= xi ||T||, ||T|| ~ max |mu|; otherwise V <- orth(Y E).  Each
+    // step solves Y = T V afresh, so the inexactness of the solves cannot accumulate.
+    const int kk = (int)std::min<long long>(n / 4, k + std::max(8, k / 2));
+    DBuf Vb, Yb;
+    Vb.ensure(sizeof(double2) * (size_t)kk * n);
+    Yb.ensure(sizeof(double2) * (size_t)kk * n);
+    Qout.ensure(sizeof(double2) * (size_t)kk * n);
+    double2 *Vv = Vb.as<double2>(), *Y = Yb.as<double2>(), *T = Qout.as<double2>();
+    gaussian_fields(c, 0xE16E5EEDull, n, kk, Vv);
+    int r = orthonormalize(c, Vv, kk, T, n);
+    LQT_CHECK(r >= k, LQT_ENOTCONV, "eigensolver start block lost rank");
+    theta.assign(kk, 0.0);
+    resT.assign(kk, 0.0);
+    std::vector<double> mu(kk, 0.0), res(kk, 0.0);
+    int conv = 0;
+    auto t_start = std::chrono::steady_clock::now();
+    for (int it = 0; it < maxit; it++) {
+        std::vector<int> its;
+        minres(c, n, H, Vv, Y, r, 0.1 * xi, inner_maxit, &its);
+        std::vector<zd> K = gram_host(c, Vv, r, Y, r, n);
+        std::vector<double> w;
+        std::vector<zd> E;
+        heev(r, K, w, E, true);  // ascending |mu|: reverse to descending
+        std::vector<zd> Ed((size_t)r * r);
+        for (int j = 0; j < r; j++) {
+            mu[j] = w[r - 1 - j];
+            for (int i = 0; i < r; i++) Ed[(size_t)i * r + j] = E[(size_t)i * r + (r - 1 - j)];
+        }
+        combine_host(c, Vv, r, Ed, r, 0.0, 1.0, T, n);  // Ritz vectors of T
+        combine_host(c, Y, r, Ed, r, 0.0, 1.0, Vv, n);  // T times them
+        c->scratch[9].ensure(sizeof(double) * 2 * r);
+        double* th = c->scratch[9].as<double>();
+        h2d(c, th, mu.data(), sizeof(double) * r);
+        eig_residual_norms(c, Vv, T, th, n, r, th + r);
+        d2h(c, res.data(), th + r, sizeof(double) * r);
+        const double tnorm = std::fabs(mu[0]);
+        conv = 0;
+        for (int i = 0; i < k; i++)
+            if (std::sqrt(res[i]) <= xi * tnorm) conv++;
+        for (int i = 0; i < r; i++) {
+            theta[i] = mu[i] != 0 ? 1.0 / mu[i] : 0.0;
+            resT[i] = std::sqrt(res[i]);
+        }
+        if (verbose) {
+            long long tot = 0;
+            for (int x : its) tot += x;
+            double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+            fprintf(stderr, "[lqtrace] eig it %d: %d/%d pass, |theta| %.3e..%.3e, %lld MINRES steps per solve, %.1f s\n",
+                    it, conv, k, std::fabs(theta[0]), std::fabs(theta[k - 1]), tot / std::max(r, 1), el);
+            fflush(stderr);
+        }
+        if (conv >= k || it + 1 == maxit) break;
+        int r2 = orthonormalize(c, Vv, r, Y, n);  // next block: orth(T V E)
+        LQT_CHECK(r2 >= k, LQT_ENOTCONV, "eigensolver lost rank");
+        r = r2;
+    }
+    return conv;
 }
 
 }  // namespace lqt
@@ -218,49 +289,30 @@ int lqt_basis_eig(lqt_ctx* c, int k, double xi, double tau, const lqt_solver_opt
         LQT_CHECK(tau == 0.0, LQT_EINVAL, "the shifted (tau != 0) eigensolver is not implemented");
         need_gauge(c);
         const long long n = 12LL * c->g.V;
-        LQT_CHECK(k <= n / 2, LQT_EINVAL, "k too large for the lattice");
+        LQT_CHECK(k <= n / 8, LQT_EINVAL, "k too large for the lattice");
         lqt::SolveOpts o = lqt::make_opts(opts);
-        const int kk = (int)std::min<long long>(n / 2, k + std::max(8, k / 4));
-        const double smax = lqt::sigma_max(c);
-        DBuf Qb, Yb, Wb, Tb;
-        Qb.ensure(sizeof(double2) * (size_t)kk * n);
-        Yb.ensure(sizeof(double2) * (size_t)kk * n);
-        Wb.ensure(sizeof(double2) * (size_t)kk * n);
-        Tb.ensure(sizeof(double2) * (size_t)kk * n);
-        double2 *Q = Qb.as<double2>(), *Y = Yb.as<double2>(), *W = Wb.as<double2>(), *T = Tb.as<double2>();
-        lqt::gaussian_fields(c, 0xE16E5EEDull, n, kk, Q);
-        int r = lqt::orthonormalize(c, Q, kk, T);
-        std::vector<double> theta;
-        std::vector<double> res(kk, 0.0);
-        const int maxit = 40;
-        int conv = 0;
-        for (int it = 0; it < maxit; it++) {
-            // Y = (A g5)^{-1}_xi Q = g5 A^{-1}_xi Q
-            std::vector<lqt_solve_stats> st(r);
-            lqt::solve_fields(c, Q, Y, r, xi, o, st.data());
-            lqt::gamma5_fields(c, Y, r);
-            std::swap(Q, Y);
-            r = lqt::orthonormalize(c, Q, r, T);
-            // Rayleigh-Ritz with A g5 in FP64
-            lqt::dslash(c, LQT_F64, LQT_A_G5, Q, W, r, n, n);
-            std::vector<zd> M = lqt::gram_host(c, Q, r, W, r);
-            std::vector<zd> S;
-            lqt::heev(r, M, theta, S, true);
-            lqt::combine_host(c, Q, r, S, r, 0.0, 1.0, T);
-            std::swap(Q, T);
-            lqt::combine_host(c, W, r, S, r, 0.0, 1.0, T);
-            std::swap(W, T);
-            c->scratch[9].ensure(sizeof(double) * 2 * r);
+        // Algorithm 1, first step: eigenpairs of g5 A^{-1}_xi = (A g5)^{-1}_xi of largest
+        // magnitude, i.e. the smallest |lambda| of the Hermitian A g5.
+        lqt::HermOp H = [c, n](const double2* in, double2* outv, int nf) {
+            lqt::dslash(c, LQT_F64, LQT_A_G5, in, outv, nf, n, n);
+        };
+        DBuf Qb;
+        std::vector<double> theta, resT;
+        const int conv = lqt::eig_subspace(c, n, H, k, xi, o.outer_maxit, std::min(o.maxit, 4000), o.verbose, Qb,
+                                           theta, resT);
+        double2* Q = Qb.as<double2>();
+        // eigen-residuals ||A g5 q - theta q|| of the returned Ritz vectors
+        std::vector<double> eres(k, 0.0);
+        {
+            DBuf Wq;
+            Wq.ensure(sizeof(double2) * (size_t)k * n);
+            lqt::dslash(c, LQT_F64, LQT_A_G5, Q, Wq.p, k, n, n);
+            c->scratch[9].ensure(sizeof(double) * 2 * k);
             double* th = c->scratch[9].as<double>();
-            LQT_HIP(hipMemcpyAsync(th, theta.data(), sizeof(double) * r, hipMemcpyHostToDevice, c->stream));
-            lqt::eig_residual_norms(c, W, Q, th, n, r, th + r);
-            lqt::d2h(c, res.data(), th + r, sizeof(double) * r);
-            conv = 0;
-            for (int i = 0; i < std::min(k, r); i++)
-                if (std::sqrt(res[i]) <= xi * smax) conv++;
-            if (conv >= std::min(k, r)) break;
+            lqt::h2d(c, th, theta.data(), sizeof(double) * k);
+            lqt::eig_residual_norms(c, Wq.as<double2>(), Q, th, n, k, th + k);
+            lqt::d2h(c, eres.data(), th + k, sizeof(double) * k);
         }
-        LQT_CHECK(r >= k, LQT_ENOTCONV, "eigensolver lost rank");
         lqt_basis* B = new lqt_basis();
         B->ctx = c;
         try {
@@ -270,10 +322,9 @@ int lqt_basis_eig(lqt_ctx* c, int k, double xi, double tau, const lqt_solver_opt
             B->orthonormal = true;
             B->theta.assign(theta.begin(), theta.begin() + k);
             B->resid.resize(k);
-            for (int i = 0; i < k; i++) B->resid[i] = std::sqrt(res[i]);
-            LQT_HIP(hipMemcpyAsync(T, Q, sizeof(double2) * (size_t)k * n, hipMemcpyDeviceToDevice, c->stream));
-            lqt::gamma5_fields(c, T, k);
-            lqt::fine_oblique_setup(c, B, T, k);
+            for (int i = 0; i < k; i++) B->resid[i] = std::sqrt(eres[i]);
+            lqt::gamma5_fields(c, Q, k);  // X = g5 Q (B->Q keeps Q)
+            lqt::fine_oblique_setup(c, B, Q, k);
             LQT_HIP(hipStreamSynchronize(c->stream));
         } catch (...) {
             delete B;
@@ -299,8 +350,14 @@ int lqt_basis_vectors(const lqt_basis* B, double* out) {
     if (!B || !out) return LQT_EINVAL;
     lqt_ctx* c = B->ctx;
     return guard(c, [&] {
-        LQT_CHECK(B->kind == 0, LQT_EINVAL, "a prolongator basis holds coarse vectors");
-        lqt::from_device_layout(c, B->U.as<double2>(), (double2*)out, B->k);
+        if (B->kind == 0) {
+            lqt::from_device_layout(c, B->U.as<double2>(), (double2*)out, B->k);
+        } else {  // U = W U_c
+            DBuf f;
+            f.ensure(sizeof(double2) * (size_t)B->k * 12 * c->g.V);
+            lqt::prolong_fields(c, B, B->Uc.as<double2>(), f.as<double2>(), B->k);
+            lqt::from_device_layout(c, f.as<double2>(), (double2*)out, B->k);
+        }
         LQT_HIP(hipStreamSynchronize(c->stream));
     });
 }

@@ -25,7 +25,7 @@ ERROR_NAMES = {0: "LQT_OK", -1: "LQT_EINVAL", -2: "LQT_ENOMEM", -3: "LQT_EHIP", 
 class SolverOpts(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("use_net", ctypes.c_int), ("max_batch", ctypes.c_int), ("cgs2", ctypes.c_int),
-                ("inner_tol", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("verbose", ctypes.c_int), ("outer_maxit", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -80,7 +80,7 @@ _SIGS = {
     "lqt_restrict": ([_P, _P, _P, _P, _I], _I),
     "lqt_prolong": ([_P, _P, _P, _P, _I], _I),
     "lqt_prolongator_get": ([_P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
-    "lqt_basis_prolongator_from": ([_P, _P, _I, _P, ctypes.POINTER(_P)], _I),
+    "lqt_basis_prolongator_from": ([_P, _P, _I, _P, _P, _I, ctypes.POINTER(_P)], _I),
     "lqt_tune": ([_P, _I, _I, ctypes.POINTER(_D)], _I),
     "lqt_kernel_times": ([_P, _P, _P, _P, _I], _I),
     "lqt_last_error": ([_P], ctypes.c_char_p),
@@ -111,8 +111,9 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0):
-    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol)
+def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0, verbose=0,
+          outer_maxit=0):
+    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit)
 
 
 class Context:
@@ -249,11 +250,14 @@ class Context:
                                                 ctypes.byref(o), ctypes.byref(h)))
         return Basis(self, h, nv=nv)
 
-    def basis_prolongator_from(self, block, nv, W):
+    def basis_prolongator_from(self, block, nv, W, coarse=None):
         h = ctypes.c_void_p()
         b = (ctypes.c_int * 4)(*block)
         W = W.contiguous()
-        self._check(lib().lqt_basis_prolongator_from(self._h, b, int(nv), _ptr(W), ctypes.byref(h)))
+        k = 0 if coarse is None else coarse.shape[0]
+        cv = None if coarse is None else coarse.contiguous()
+        self._check(lib().lqt_basis_prolongator_from(self._h, b, int(nv), _ptr(W), _ptr(cv), int(k),
+                                                     ctypes.byref(h)))
         return Basis(self, h, nv=nv)
 
     def basis_from_vectors(self, X):

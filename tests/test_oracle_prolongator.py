@@ -1,0 +1,91 @@
+"""CPU pins of the oracle prolongator (Algorithm 2 blocking) and its coarse operator."""
+import numpy as np
+
+import synth
+from oracle import core, dense, estimator, prolongator as pr
+
+
+def test_table2_dimension_arithmetic():
+    """Coarse dimensions of Table 2: nagg * 2 * nv per level (32^3x64, 4^4 blocks)."""
+    dims = (32, 32, 32, 64)
+    nagg = int(np.prod(dims)) // 4 ** 4
+    assert nagg * 2 * 24 == 393216 and nagg * 2 * 48 == 786432
+    assert (nagg // 2 ** 4) * 2 * 32 == 32768 and (nagg // 2 ** 4) * 2 * 64 == 65536
+    assert 12 * int(np.prod(dims)) == 25165824
+
+
+def _wil(dims, block, nv, seed=3):
+    rng = np.random.default_rng(seed)
+    N = 12 * int(np.prod(dims))
+    Y = rng.standard_normal((nv, N)) + 1j * rng.standard_normal((nv, N))
+    return pr.block_orthonormalize(Y, dims, block)
+
+
+def test_blocks_orthonormal_and_projector_algebra():
+    dims, block, nv = (4, 2, 2, 4), (2, 2, 2, 2), 5
+    W = _wil(dims, block, nv)
+    for a in range(W.shape[0]):
+        for c in range(2):
+            assert np.allclose(W[a, c].conj() @ W[a, c].T, np.eye(nv), atol=1e-13)
+    P = pr.dense_prolongator(W, dims, block)
+    assert np.allclose(P.conj().T @ P, np.eye(P.shape[1]), atol=1e-13)  # R P = I
+    PR = P @ P.conj().T
+    assert np.allclose(PR @ PR, PR, atol=1e-12)  # P R idempotent
+    g5 = estimator.g5_vec(P.shape[0])
+    g5c = pr.coarse_g5(W.shape[0], nv)
+    assert np.allclose(g5[:, None] * P, P * g5c[None, :], atol=1e-14)  # g5 W = W g5^W
+    # restrict / prolong agree with the dense matrix
+    rng = np.random.default_rng(0)
+    y = rng.standard_normal((3, P.shape[0])) + 1j * rng.standard_normal((3, P.shape[0]))
+    assert np.allclose(pr.restrict(W, y, dims, block), (P.conj().T @ y.T).T, atol=1e-12)
+    cv = rng.standard_normal((2, P.shape[1])) + 0j
+    assert np.allclose(pr.prolong(W, cv, dims, block), (P @ cv.T).T, atol=1e-12)
+
+
+def test_single_site_aggregates_preserve_the_spectrum():
+    """Blocks of one site with nv = 6 make W unitary, so W^+ A W has the spectrum of A."""
+    dims, m = (2, 2, 2, 2), 0.1
+    U = synth.su3_links(dims, 0.4, 5)
+    A = dense.dense_operator(U, dims, m)
+    W = _wil(dims, (1, 1, 1, 1), 6)
+    P = pr.dense_prolongator(W, dims, (1, 1, 1, 1))
+    Ac = P.conj().T @ A @ P
+    ev = np.sort_complex(np.linalg.eigvals(A))
+    evc = np.sort_complex(np.linalg.eigvals(Ac))
+    assert np.allclose(np.sort(ev.real), np.sort(evc.real), atol=1e-10)
+    assert np.allclose(np.sort(np.abs(ev)), np.sort(np.abs(evc)), atol=1e-10)
+
+
+def test_coarse_g5_operator_is_hermitian():
+    dims, block, nv, m = (4, 2, 2, 4), (2, 2, 2, 2), 4, -0.2
+    U = synth.su3_links(dims, 0.5, 2)
+    A = dense.dense_operator(U, dims, m)
+    W = _wil(dims, block, nv)
+    P = pr.dense_prolongator(W, dims, block)
+    Hc = pr.coarse_g5(W.shape[0], nv)[:, None] * (P.conj().T @ A @ P)
+    assert np.allclose(Hc, Hc.conj().T, atol=1e-12)
+
+
+def test_prolongator_deflation_identity():
+    """Algorithm 2 with X = W U_bar: t0 + trace(A^{-1}(I - P)) = trace(A^{-1}) exactly, and
+    the fine-space quantities equal their coarse counterparts (W^+ W = I)."""
+    dims, block, nv, m = (2, 2, 2, 4), (2, 2, 2, 2), 3, 0.1
+    U = synth.su3_links(dims, 0.3, 4)
+    A = dense.dense_operator(U, dims, m)
+    Ai = np.linalg.inv(A)
+    W = _wil(dims, block, nv)
+    P = pr.dense_prolongator(W, dims, block)
+    g5c = pr.coarse_g5(W.shape[0], nv)
+    Hc = g5c[:, None] * (P.conj().T @ A @ P)
+    w, Ub = np.linalg.eigh(Hc)
+    idx = np.argsort(np.abs(w))[:4]
+    X = (P @ Ub[:, idx]).T  # fine rows
+    Uo, lam, ug5u, t0 = estimator.oblique_setup(X, (A @ X.T).T)
+    assert np.allclose(np.sort(np.abs(lam)), np.sort(np.abs(w[idx])), rtol=1e-10)
+    Pobl = estimator.oblique_projector_dense(A, Uo, lam)
+    N = A.shape[0]
+    assert abs(t0 + np.trace(Ai @ (np.eye(N) - Pobl)) - np.trace(Ai)) < 1e-10 * abs(np.trace(Ai))
+    # u^+ g5 u computed on the coarse vectors equals the fine value
+    uc = Ub[:, idx]
+    assert np.allclose(np.sort(np.einsum("ni,n,ni->i", uc.conj(), g5c, uc).real),
+                       np.sort(np.einsum("in,n,in->i", X.conj(), estimator.g5_vec(N), X).real), atol=1e-12)
