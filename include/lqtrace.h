@@ -108,7 +108,10 @@ typedef struct {
 typedef struct {
     int epochs;        /* passes over the generated pairs [4]                            */
     double lr;         /* Adam learning rate [1e-3]                                      */
-    int pair_iters;    /* GMRES steps used to harvest each residual/error pair [64]       */
+    int batch;         /* pairs per optimiser step [4]                                   */
+    double pair_xi;    /* 0: errors e are Gaussian; in (0,1): e = A^{-1}_{pair_xi} g, the  */
+                       /* solver's output (FP32 inner GMRES) on a Gaussian g [0]          */
+    int verbose;       /* 1: one progress line per epoch on stderr [0]                   */
 } lqt_train_opts;
 
 /* ---- context ---------------------------------------------------------------------- */
@@ -148,13 +151,13 @@ int lqt_solve(lqt_ctx *ctx, const double *d_b, double *d_x, int nrhs, double xi,
 
 /* ---- deflation bases ---------------------------------------------------------------- */
 
-/* Algorithm 1, first step: the k eigenpairs of the Hermitian operator A g5 with the
- * smallest |lambda| (its eigenvectors are left singular vectors of A), from block
- * inexact inverse iteration with solves (A g5)^{-1} = g5 A^{-1} to xi/10 and FP64
- * Rayleigh-Ritz over the previous iterate and its image.  A pair is accepted when
- * ||A g5 u - theta u|| <= xi |theta|, which implies the convergence test of the paper's
- * Table 1 (||g5 A^{-1} u - u/theta|| <= xi ||A^{-1}||).  Returns LQT_ENOTCONV (with the
- * basis in *out) if not all k pairs pass within 60 iterations.
+/* Algorithm 1, first step: the k eigenpairs of the Hermitian operator H = A g5 with the
+ * smallest |lambda| (its eigenvectors are left singular vectors of A).  Subspace iteration
+ * on T = H^{-1} with k + max(8, k/2) vectors (FP64 Rayleigh-Ritz, MINRES inner solves of H
+ * to xi/10, at most min(opts->maxit, 4000) steps each), accepting a pair (mu, v) of T once
+ * ||T v - mu v|| <= xi max|mu| (the convergence test of the paper's Table 1); lambda =
+ * 1/mu.  Returns LQT_ENOTCONV (with the basis in *out) if not all k pairs pass within
+ * opts->outer_maxit iterations (default 60).
  * tau must be 0 (the i*tau*g5 shift of Section 3.2 is not implemented; LQT_EINVAL).
  * *out receives a basis owned by the caller (free with lqt_basis_free); the context
  * must outlive it. */
@@ -194,12 +197,15 @@ void lqt_basis_free(lqt_basis *basis);
 /* ---- learned preconditioner ------------------------------------------------------- */
 
 /* Set the weights of the 4-layer gauge-equivariant parallel-transport network used as a
- * right preconditioner (features 4 -> 8 -> 8 -> 4, each feature a colour 3-vector; the 4
- * input/output features are the 4 spin components of a spinor).  Layer l maps
+ * right preconditioner in FGMRES (features 4 -> 8 -> 8 -> 8 -> 4, i.e. 12 -> 24 -> 24 ->
+ * 24 -> 12 complex channels, each feature a colour 3-vector; the 4 input/output features
+ * are the 4 spin components of a spinor).  Layer l maps
  *   out_f(x) = sum_{p=0..8} sum_g W_l[p][f][g] (T_p v_g)(x),  T_0 = 1,
- *   T_{1+2mu} v(x) = U_mu(x) v(x+mu),  T_{2+2mu} v(x) = U_mu(x-mu)^+ v(x-mu),
- * weights concatenated layer by layer as complex FP32 (re, im): 2*9*(32+64+64+32) = 3456
- * floats (nbytes = 13824); stored on the device in BF16.  Host pointer. */
+ *   T_{1+2mu} v(x) = U_mu(x) v(x+mu),  T_{2+2mu} v(x) = U_mu(x-mu)^+ v(x-mu)
+ * (links with the antiperiodic sign), linear, no bias.  Weights concatenated layer by layer,
+ * W_l[p][f][g] row-major, as complex FP32 (re, im): 2*9*(32+64+64+32) = 3456 floats
+ * (nbytes = 13824); the kernels use them rounded to BF16, with FP32 arithmetic.  Host
+ * pointer. */
 int lqt_precond_set(lqt_ctx *ctx, const void *h_weights, size_t nbytes);
 
 /* Copy the current weights (complex FP32 in the order above) to the host. */
@@ -208,8 +214,24 @@ int lqt_precond_get(lqt_ctx *ctx, void *h_weights, size_t nbytes);
 /* Apply the network: out = M(in), canonical complex128 device arrays, nrhs fields. */
 int lqt_precond_apply(lqt_ctx *ctx, const double *d_in, double *d_out, int nrhs);
 
-/* Train the network on npairs residual/error pairs (r, e = A^{-1} r) generated on the
- * device from seeded Gaussian vectors, loss ||M r - e||^2 / ||e||^2, Adam. */
+/* Loss and gradient of the network on caller-supplied errors: for the npairs fields e_q
+ * (canonical complex128, device) the library forms r_q = A e_q and returns
+ *   *h_loss = (1/npairs) sum_q ||M r_q - e_q||^2 / ||e_q||^2
+ * and h_grad[2*i], h_grad[2*i+1] = re, im of dL/dconj(W_i) (2 * 1728 doubles, the weight
+ * order above; d/dRe W_i = 2 re, d/dIm W_i = 2 im), by back-propagation through the
+ * adjoint layers (the adjoint of T_{+mu} is T_{-mu}; weights conjugate-transposed).  Uses
+ * the FP32 master weights (not the BF16 copy), FP32 arithmetic and FP64-stored activations. */
+int lqt_precond_loss_grad(lqt_ctx *ctx, const double *d_e, int npairs, double *h_loss,
+                          double *h_grad);
+
+/* Train the network with Adam (on the real and imaginary parts of every weight) on npairs
+ * pairs (r, e) with A e = r: e are drawn on the device from seed, either Gaussian or the
+ * solver's own approximate solutions of Gaussian right-hand sides (opts->pair_xi), and kept
+ * resident (npairs * 12V complex128; LQT_ENOMEM beyond half the free device memory); r = A e;
+ * loss and gradient as in lqt_precond_loss_grad over opts->batch pairs per step, the same
+ * pairs every epoch.  Starts from the current weights, else from the identity scaled by
+ * |4+m|^{-1/4} per layer (M = 1/(4+m), point Jacobi).  *h_final_loss (may be NULL) receives
+ * the mean loss of the last epoch (accumulated over its steps). */
 int lqt_precond_train(lqt_ctx *ctx, int npairs, uint64_t seed, const lqt_train_opts *opts,
                       double *h_final_loss);
 

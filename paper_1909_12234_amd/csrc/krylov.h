@@ -33,8 +33,11 @@ void kry_xupdate(lqt_ctx* c, double2* x, const int* act, const void* Zb, long lo
                  const KryState& st);
 template <typename S>
 void kry_start(lqt_ctx* c, void* V0, const double2* r, const int* src, const double* rn2, int ns);
-void kry_finish(lqt_ctx* c, const double2* part, int j, int ns, const KryState& st, int pass);
-void kry_norm_givens(lqt_ctx* c, const double* part, int j, int ns, const KryState& st);
+// nsb = partial-sum blocks per slot of the preceding dot / update pass (kry_blocks<S>)
+template <typename S>
+int kry_blocks(const lqt_ctx* c);
+void kry_finish(lqt_ctx* c, const double2* part, int nsb, int j, int ns, const KryState& st, int pass);
+void kry_norm_givens(lqt_ctx* c, const double* part, int nsb, int j, int ns, const KryState& st);
 void kry_backsolve(lqt_ctx* c, int ns, const KryState& st);
 void kry_start_state(lqt_ctx* c, const KryState& st, const int* src, const double* rn2, const double* target_abs,
                      int ns);

@@ -51,6 +51,129 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// ---------------------------------------------------------------------------- 16-byte lanes
+// With SP = 16 / sizeof(S) consecutive sites per lane, every component of a vector is read
+// with one 16-byte load per lane (4 sites for BF16/FP16, 2 for FP32, 1 for FP64); used when
+// the volume is a multiple of SP (then every component row is 16-byte aligned).
+template <typename S>
+struct Lanes {
+    static constexpr int SP = 16 / (int)sizeof(S);
+};
+
+template <typename S, typename C, int SP>
+__device__ __forceinline__ void ld16(const S* p, cx<C> o[SP]) {
+    if constexpr (SP == 1) {
+        o[0] = ldk<S, C>(p);
+    } else {
+        const uint4 r = *reinterpret_cast<const uint4*>(p);
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+        if constexpr (sizeof(S) == 8) {  // float2 x 2
+            o[0] = {(C)__uint_as_float(w[0]), (C)__uint_as_float(w[1])};
+            o[1] = {(C)__uint_as_float(w[2]), (C)__uint_as_float(w[3])};
+        } else if constexpr (std::is_same<S, b2>::value) {
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                o[k] = {(C)__uint_as_float(w[k] << 16), (C)__uint_as_float(w[k] & 0xffff0000u)};
+        } else {  // two FP16
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                __half_raw lo, hi;
+                lo.x = (unsigned short)(w[k] & 0xffffu);
+                hi.x = (unsigned short)(w[k] >> 16);
+                o[k] = {(C)__half2float(__half(lo)), (C)__half2float(__half(hi))};
+            }
+        }
+    }
+}
+
+// store SP values, return (through o) what the storage type holds after rounding
+template <typename S, typename C, int SP>
+__device__ __forceinline__ void st16(S* p, cx<C> o[SP]) {
+    if constexpr (SP == 1) {
+        o[0] = stk<S, C>(p, o[0]);
+    } else {
+        uint32_t w[4];
+        if constexpr (sizeof(S) == 8) {
+            w[0] = __float_as_uint((float)o[0].x), w[1] = __float_as_uint((float)o[0].y);
+            w[2] = __float_as_uint((float)o[1].x), w[3] = __float_as_uint((float)o[1].y);
+        } else if constexpr (std::is_same<S, b2>::value) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint16_t a = f_to_bf16((float)o[k].x), b = f_to_bf16((float)o[k].y);
+                w[k] = (uint32_t)a | ((uint32_t)b << 16);
+                o[k] = {(C)bf16_to_f(a), (C)bf16_to_f(b)};
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                __half_raw a = __half(__float2half_rn((float)o[k].x)), b = __half(__float2half_rn((float)o[k].y));
+                w[k] = (uint32_t)a.x | ((uint32_t)b.x << 16);
+                o[k] = {(C)__half2float(__half(a)), (C)__half2float(__half(b))};
+            }
+        }
+        *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// dot pass with SP sites per lane (V % SP == 0): same output as k_cgs_dots
+template <typename S, int SP>
+__global__ __launch_bounds__(256) void k_cgs_dots_v(const S* __restrict__ Vb, long long vstride, int j, int V,
+                                                    double2* __restrict__ part) {
+    using C = typename acc_of<S>::type;
+    __shared__ double red[4][KRY_MAXM + 2][2];
+    const int q = blockIdx.y;
+    const int nsb = gridDim.x;
+    const int s0 = (blockIdx.x * 256 + threadIdx.x) * SP;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long n = 12LL * V;
+    const S* w = Vb + (long long)(j + 1) * vstride + q * n;
+    const bool ok = s0 < V;
+    cx<C> wv[12][SP];
+    double nw = 0;
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        if (ok)
+            ld16<S, C, SP>(w + (long long)c * V + s0, wv[c]);
+        else
+#pragma unroll
+            for (int k = 0; k < SP; k++) wv[c][k] = {0, 0};
+#pragma unroll
+        for (int k = 0; k < SP; k++) nw += (double)wv[c][k].x * wv[c][k].x + (double)wv[c][k].y * wv[c][k].y;
+    }
+    for (int i = 0; i <= j; i++) {
+        const S* vi = Vb + (long long)i * vstride + q * n;
+        C dr = 0, di = 0;
+        if (ok) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                cx<C> v[SP];
+                ld16<S, C, SP>(vi + (long long)c * V + s0, v);
+#pragma unroll
+                for (int k = 0; k < SP; k++) {
+                    dr += v[k].x * wv[c][k].x + v[k].y * wv[c][k].y;
+                    di += v[k].x * wv[c][k].y - v[k].y * wv[c][k].x;
+                }
+            }
+        }
+        double a = wave_sum((double)dr), b = wave_sum((double)di);
+        if (lane == 0) {
+            red[wave][i][0] = a;
+            red[wave][i][1] = b;
+        }
+    }
+    nw = wave_sum(nw);
+    if (lane == 0) {
+        red[wave][j + 1][0] = nw;
+        red[wave][j + 1][1] = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += 256) {
+        double a = red[0][i][0] + red[1][i][0] + red[2][i][0] + red[3][i][0];
+        double b = red[0][i][1] + red[1][i][1] + red[2][i][1] + red[3][i][1];
+        part[((long long)q * nsb + blockIdx.x) * (j + 2) + i] = make_double2(a, b);
+    }
+}
+
 // ---------------------------------------------------------------------------- dot pass
 // part[(q*nsb + blk)*(j+2) + i]: i <= j: d_i, i = j+1: (|what|^2, 0)
 template <typename S>
@@ -182,6 +305,54 @@ __global__ __launch_bounds__(256) void k_cgs_update(S* __restrict__ Vb, long lon
         for (int c = 0; c < 12; c++) {
             cx<C> o = stk<S, C>(w + (long long)c * V + s, cx<C>{wv[c].x * f, wv[c].y * f});
             nrm += (double)o.x * o.x + (double)o.y * o.y;
+        }
+    }
+    nrm = wave_sum(nrm);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(long long)q * nsb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// update pass with SP sites per lane (V % SP == 0): same output as k_cgs_update
+template <typename S, int SP>
+__global__ __launch_bounds__(256) void k_cgs_update_v(S* __restrict__ Vb, long long vstride, int j, int V,
+                                                      KryState st, int scale, double* __restrict__ part) {
+    using C = typename acc_of<S>::type;
+    __shared__ double red[4];
+    const int q = blockIdx.y;
+    const int nsb = gridDim.x;
+    const int s0 = (blockIdx.x * 256 + threadIdx.x) * SP;
+    const long long n = 12LL * V;
+    const int m = st.m;
+    S* w = Vb + (long long)(j + 1) * vstride + q * n;
+    double nrm = 0;
+    if (s0 < V) {
+        cx<C> wv[12][SP];
+#pragma unroll
+        for (int c = 0; c < 12; c++) ld16<S, C, SP>(w + (long long)c * V + s0, wv[c]);
+        for (int i = 0; i <= j; i++) {
+            const double2 a = st.alpha[(long long)q * (m + 1) + i];
+            const C ar = (C)a.x, ai = (C)a.y;
+            const S* vi = Vb + (long long)i * vstride + q * n;
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                cx<C> v[SP];
+                ld16<S, C, SP>(vi + (long long)c * V + s0, v);
+#pragma unroll
+                for (int k = 0; k < SP; k++) {
+                    wv[c][k].x -= ar * v[k].x - ai * v[k].y;
+                    wv[c][k].y -= ar * v[k].y + ai * v[k].x;
+                }
+            }
+        }
+        const C f = scale ? (C)st.fac[q] : (C)1;
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+#pragma unroll
+            for (int k = 0; k < SP; k++) wv[c][k] = {wv[c][k].x * f, wv[c][k].y * f};
+            st16<S, C, SP>(w + (long long)c * V + s0, wv[c]);
+#pragma unroll
+            for (int k = 0; k < SP; k++) nrm += (double)wv[c][k].x * wv[c][k].x + (double)wv[c][k].y * wv[c][k].y;
         }
     }
     nrm = wave_sum(nrm);
@@ -341,15 +512,36 @@ __global__ void k_start_state(KryState st, const int* __restrict__ src, const do
 
 // ---------------------------------------------------------------------------- host side
 template <typename S>
+static bool vec_ok(const lqt_ctx* c) {
+    return Lanes<S>::SP > 1 && c->g.V % Lanes<S>::SP == 0;
+}
+
+// partial-sum blocks per slot of the dot and update passes
+template <typename S>
+int kry_blocks(const lqt_ctx* c) {
+    const int sp = vec_ok<S>(c) ? Lanes<S>::SP : 1;
+    return (c->g.V / sp + 255) / 256 + ((c->g.V % sp) ? 1 : 0);
+}
+
+template <typename S>
 void kry_dots(lqt_ctx* c, const void* Vb, long long vstride, int j, int ns, double2* part) {
-    dim3 grid((c->g.V + 255) / 256, ns);
-    hipLaunchKernelGGL(k_cgs_dots<S>, grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, j, c->g.V, part);
+    dim3 grid(kry_blocks<S>(c), ns);
+    if (vec_ok<S>(c))
+        hipLaunchKernelGGL((k_cgs_dots_v<S, Lanes<S>::SP>), grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, j,
+                           c->g.V, part);
+    else
+        hipLaunchKernelGGL(k_cgs_dots<S>, grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, j, c->g.V, part);
     LQT_HIP(hipGetLastError());
 }
 template <typename S>
 void kry_update(lqt_ctx* c, void* Vb, long long vstride, int j, int ns, const KryState& st, int scale, double* part) {
-    dim3 grid((c->g.V + 255) / 256, ns);
-    hipLaunchKernelGGL(k_cgs_update<S>, grid, dim3(256), 0, c->stream, (S*)Vb, vstride, j, c->g.V, st, scale, part);
+    dim3 grid(kry_blocks<S>(c), ns);
+    if (vec_ok<S>(c))
+        hipLaunchKernelGGL((k_cgs_update_v<S, Lanes<S>::SP>), grid, dim3(256), 0, c->stream, (S*)Vb, vstride, j,
+                           c->g.V, st, scale, part);
+    else
+        hipLaunchKernelGGL(k_cgs_update<S>, grid, dim3(256), 0, c->stream, (S*)Vb, vstride, j, c->g.V, st, scale,
+                           part);
     LQT_HIP(hipGetLastError());
 }
 template <typename S>
@@ -367,13 +559,11 @@ void kry_start(lqt_ctx* c, void* V0, const double2* r, const int* src, const dou
     LQT_HIP(hipGetLastError());
 }
 
-void kry_finish(lqt_ctx* c, const double2* part, int j, int ns, const KryState& st, int pass) {
-    int nsb = (c->g.V + 255) / 256;
+void kry_finish(lqt_ctx* c, const double2* part, int nsb, int j, int ns, const KryState& st, int pass) {
     hipLaunchKernelGGL(k_cgs_finish, dim3(ns), dim3(64), 0, c->stream, part, nsb, j, st, pass, sqrt(12.0 * c->g.V));
     LQT_HIP(hipGetLastError());
 }
-void kry_norm_givens(lqt_ctx* c, const double* part, int j, int ns, const KryState& st) {
-    int nsb = (c->g.V + 255) / 256;
+void kry_norm_givens(lqt_ctx* c, const double* part, int nsb, int j, int ns, const KryState& st) {
     hipLaunchKernelGGL(k_norm_givens, dim3(ns), dim3(64), 0, c->stream, part, nsb, j, st, sqrt(12.0 * c->g.V));
     LQT_HIP(hipGetLastError());
 }
@@ -389,6 +579,7 @@ void kry_start_state(lqt_ctx* c, const KryState& st, const int* src, const doubl
 }
 
 #define INST(S)                                                                                          \
+    template int kry_blocks<S>(const lqt_ctx*);                                                          \
     template void kry_dots<S>(lqt_ctx*, const void*, long long, int, int, double2*);                     \
     template void kry_update<S>(lqt_ctx*, void*, long long, int, int, const KryState&, int, double*);    \
     template void kry_xupdate<S>(lqt_ctx*, double2*, const int*, const void*, long long, int,            \

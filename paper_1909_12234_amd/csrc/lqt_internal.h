@@ -283,10 +283,9 @@ struct Tuned {
 
 struct Net {
     bool set = false;
-    int feats[5] = {4, 8, 8, 4, 0};
-    std::vector<float> w;  // complex FP32 weights, host copy
-    DBuf wd;               // BF16 weights on device (complex pairs)
-    DBuf wf;               // FP32 weights on device
+    std::vector<float> w;  // FP32 master weights (complex pairs), host copy
+    DBuf wf;               // the weights the kernels use (BF16-rounded values held as FP32)
+    DBuf act;              // two FP32 activation fields for the hidden layers
 };
 
 }  // namespace lqt
@@ -303,8 +302,8 @@ struct lqt_ctx {
     lqt::DBuf U[4];  // gauge per precision (LQT_F64 .. LQT_BF16)
     // work buffers, grown on demand: 0 Krylov basis, 1 residuals, 2 Krylov state,
     // 3-4 Krylov partial sums, 5-6 apply / BLAS partials, 7 residual partials,
-    // 8 GEMM partials, 9 small matrices, 10-11 estimator fields
-    lqt::DBuf scratch[12];
+    // 8 GEMM partials, 9 small matrices, 10-11 estimator fields, 12 FGMRES preconditioned basis
+    lqt::DBuf scratch[13];
     lqt::HBuf pinned;
     std::map<long long, lqt::Tuned> tuned;
     lqt::KTimer timer;

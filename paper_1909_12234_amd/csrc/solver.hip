@@ -14,6 +14,7 @@
 #include "blas.h"
 #include "krylov.h"
 #include "lqt_internal.h"
+#include "ptc.h"
 #include "solver.h"
 
 namespace lqt {
@@ -61,12 +62,13 @@ template <typename S>
 void kry_step_orth(lqt_ctx* c, void* basis, long long vstride, int j, int na, const KryState& st, bool cgs2,
                    double2* part, double* partn) {
     const double vb = 24.0 * c->g.V * (sizeof(S) / 2) * na;  // bytes of one vector per slot set
+    const int nsb = kry_blocks<S>(c);
     for (int pass = 0; pass < (cgs2 ? 2 : 1); pass++) {
         c->timer.begin(c->stream, KT_DOTS);
         kry_dots<S>(c, basis, vstride, j, na, part);
         c->timer.end(c->stream, vb * (j + 2));
         c->timer.begin(c->stream, KT_KRYLOV);
-        kry_finish(c, part, j, na, st, pass);
+        kry_finish(c, part, nsb, j, na, st, pass);
         c->timer.end(c->stream);
         const int last = (pass == (cgs2 ? 1 : 0));
         c->timer.begin(c->stream, KT_UPDATE);
@@ -74,7 +76,7 @@ void kry_step_orth(lqt_ctx* c, void* basis, long long vstride, int j, int na, co
         c->timer.end(c->stream, vb * (j + 3));
     }
     c->timer.begin(c->stream, KT_KRYLOV);
-    kry_norm_givens(c, partn, j, na, st);
+    kry_norm_givens(c, partn, nsb, j, na, st);
     c->timer.end(c->stream);
 }
 
@@ -93,6 +95,9 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     DBuf& partb = c->scratch[3];
     DBuf& partnb = c->scratch[4];
     basisb.ensure((size_t)(m + 1) * nb * n * eb);
+    // flexible GMRES: z_j = M v_j is kept for the solution update (right preconditioning)
+    DBuf& zb = c->scratch[12];
+    if (o.use_net) zb.ensure((size_t)m * nb * n * eb);
     rb.ensure((size_t)nb * n * sizeof(double2) + 4 * 256 * (size_t)nb);
     StateBuf sb;
     sb.carve(stb, nb, m);
@@ -183,7 +188,13 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         for (int j = 0; j < m; j++) {
             const void* vj = (const char*)basis + (size_t)j * vstride * eb;
             void* vj1 = (char*)basis + (size_t)(j + 1) * vstride * eb;
-            dslash(c, prec, LQT_A, vj, vj1, nn, n, n);
+            const void* aj = vj;
+            if (o.use_net) {
+                void* zj = (char*)zb.p + (size_t)j * vstride * eb;
+                ptc_apply<S>(c, (const S*)vj, (S*)zj, nn);
+                aj = zj;
+            }
+            dslash(c, prec, LQT_A, aj, vj1, nn, n, n);
             kry_step_orth<S>(c, basis, vstride, j, nn, sb.st, o.cgs2 != 0, part, partn);
             if (j + 1 < m) {
                 LQT_HIP(hipMemcpyAsync(h_flags, sb.st.frozen, sizeof(int) * nn, hipMemcpyDeviceToHost, c->stream));
@@ -195,7 +206,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         }
         c->timer.begin(c->stream, KT_KRYLOV);
         kry_backsolve(c, nn, sb.st);
-        kry_xupdate<S>(c, x, act_d, basis, vstride, nn, sb.st);
+        kry_xupdate<S>(c, x, act_d, o.use_net ? zb.p : basis, vstride, nn, sb.st);
         c->timer.end(c->stream);
         LQT_HIP(hipMemcpyAsync(h_flags, sb.st.kdim, sizeof(int) * nn, hipMemcpyDeviceToHost, c->stream));
         LQT_HIP(hipStreamSynchronize(c->stream));
@@ -235,13 +246,16 @@ int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, 
     LQT_CHECK(o.restart >= 1 && o.restart <= KRY_MAXM, LQT_EINVAL, "restart must be in 1..64");
     LQT_CHECK(o.prec >= LQT_F64 && o.prec <= LQT_BF16, LQT_EINVAL, "bad inner precision");
     LQT_CHECK(xi > 0, LQT_EINVAL, "tolerance must be positive");
+    LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net requires preconditioner weights (lqt_precond_set/train)");
     const long long n = 12LL * c->g.V;
     // batch size: caller cap, else what fits in 70% of free device memory
     size_t fr = 0, tot = 0;
     LQT_HIP(hipMemGetInfo(&fr, &tot));
     size_t per = (size_t)(o.restart + 1) * n * storage_bytes(o.prec) + (size_t)n * 16 * 2 +
                  (size_t)((c->g.V + 255) / 256) * (o.restart + 2) * 16;
-    size_t have = (size_t)(0.7 * (double)(fr + c->scratch[0].n + c->scratch[1].n + c->scratch[3].n));
+    if (o.use_net) per += (size_t)o.restart * n * storage_bytes(o.prec) + (size_t)c->g.V * 24 * 8 * 2;
+    size_t have = (size_t)(0.7 * (double)(fr + c->scratch[0].n + c->scratch[1].n + c->scratch[3].n +
+                                          c->scratch[12].n + c->net.act.n));
     int fit = (int)std::max<size_t>(1, have / per);
     int batch = o.max_batch > 0 ? o.max_batch : nrhs;
     batch = std::min(batch, fit);

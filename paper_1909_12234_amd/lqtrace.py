@@ -17,6 +17,8 @@ LQT_OK, LQT_EINVAL, LQT_ENOMEM, LQT_EHIP, LQT_ENOTCONV, LQT_ENOTUNITARY, LQT_EST
 A, A_DAG, A_G5, G5_A = 0, 1, 2, 3
 F64, F32, F16, BF16 = 0, 1, 2, 3
 OBLIQUE_G5, ORTH = 0, 1
+NET_FEATURES = (4, 8, 8, 8, 4)  # parallel-transport network: features per layer boundary
+WEIGHT_COUNT = sum(9 * a * b for a, b in zip(NET_FEATURES[:-1], NET_FEATURES[1:]))  # complex weights
 
 ERROR_NAMES = {0: "LQT_OK", -1: "LQT_EINVAL", -2: "LQT_ENOMEM", -3: "LQT_EHIP", -4: "LQT_ENOTCONV",
                -5: "LQT_ENOTUNITARY", -6: "LQT_ESTATE", -7: "LQT_ENAN"}
@@ -42,7 +44,8 @@ class TraceResult(ctypes.Structure):
 
 
 class TrainOpts(ctypes.Structure):
-    _fields_ = [("epochs", ctypes.c_int), ("lr", ctypes.c_double), ("pair_iters", ctypes.c_int)]
+    _fields_ = [("epochs", ctypes.c_int), ("lr", ctypes.c_double), ("batch", ctypes.c_int),
+                ("pair_xi", ctypes.c_double), ("verbose", ctypes.c_int)]
 
 
 class LqtError(RuntimeError):
@@ -72,6 +75,7 @@ _SIGS = {
     "lqt_precond_get": ([_P, _P, ctypes.c_size_t], _I),
     "lqt_precond_apply": ([_P, _P, _P, _I], _I),
     "lqt_precond_train": ([_P, _I, ctypes.c_uint64, _P, _P], _I),
+    "lqt_precond_loss_grad": ([_P, _P, _I, _P, _P], _I),
     "lqt_trace": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _P, _P, _P, _P], _I),
     "lqt_probes": ([_P, ctypes.c_uint64, ctypes.c_longlong, _I, _P], _I),
     "lqt_gram": ([_P, _P, _I, _P, _I, _P], _I),
@@ -272,7 +276,7 @@ class Context:
         return self._check(lib().lqt_precond_set(self._h, _ptr(w), w.numel() * 8))
 
     def precond_get(self):
-        w = torch.empty(1728, dtype=torch.complex64)
+        w = torch.empty(WEIGHT_COUNT, dtype=torch.complex64)
         self._check(lib().lqt_precond_get(self._h, _ptr(w), w.numel() * 8))
         return w
 
@@ -282,8 +286,19 @@ class Context:
         self._check(lib().lqt_precond_apply(self._h, _ptr(x), _ptr(out), x.numel() // self.N))
         return out
 
-    def precond_train(self, npairs, seed, epochs=4, lr=1e-3, pair_iters=64):
-        o = TrainOpts(epochs, lr, pair_iters)
+    def precond_loss_grad(self, e):
+        """Mean loss ||M A e - e||^2/||e||^2 over the fields e and its gradient dL/dconj(W)
+        (complex128 array of the 1728 weights) at the current FP32 master weights."""
+        e = e.contiguous()
+        npairs = e.numel() // self.N
+        g = torch.empty(2 * WEIGHT_COUNT, dtype=torch.float64)
+        loss = ctypes.c_double(0)
+        self._check(lib().lqt_precond_loss_grad(self._h, _ptr(e), npairs, ctypes.byref(loss), _ptr(g)))
+        return loss.value, torch.view_as_complex(g.view(-1, 2))
+
+    def precond_train(self, npairs, seed, epochs=4, lr=1e-3, batch=4, pair_xi=0.0, verbose=0):
+        """Adam training on npairs pairs (r = A e, e); returns the last epoch's mean loss."""
+        o = TrainOpts(int(epochs), float(lr), int(batch), float(pair_xi), int(verbose))
         loss = ctypes.c_double(0)
         self._check(lib().lqt_precond_train(self._h, int(npairs), ctypes.c_uint64(seed), ctypes.byref(o),
                                             ctypes.byref(loss)))
