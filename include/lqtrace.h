@@ -293,9 +293,12 @@ int lqt_prolongator_get(const lqt_basis *basis, double *d_w, long long *nc);
 int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const double *d_w,
                                const double *d_coarse, int k, lqt_basis **out);
 
-/* Autotuner: time the candidate dslash tilings for (prec, nrhs) now and cache the choice
- * in the context; *ms receives the best time (may be NULL). */
-int lqt_tune(lqt_ctx *ctx, int prec, int nrhs, double *ms);
+/* Autotuner: time the candidate dslash tilings (right-hand sides per thread 1/2/4, block
+ * 64/128/256 sites, block order: site-block major or chunks of 16/64 site blocks swept per
+ * right-hand-side group) for (prec, nrhs) now and cache the choice in the context; *ms
+ * receives the best time and tile[0..2] the chosen (rhs per thread, block, chunk); either
+ * may be NULL. */
+int lqt_tune(lqt_ctx *ctx, int prec, int nrhs, double *ms, int *tile);
 
 /* Kernel timers: HIP event pairs recorded around the library's launches on the context
  * stream, summed per kernel family: 0 Wilson operator of the inner cycles, 1 CGS dot

@@ -169,13 +169,19 @@ int lqt_probes(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double* out
     });
 }
 
-int lqt_tune(lqt_ctx* c, int prec, int nrhs, double* ms) {
+int lqt_tune(lqt_ctx* c, int prec, int nrhs, double* ms, int* tile) {
     if (!c) return LQT_EINVAL;
     return guard(c, [&] {
         LQT_CHECK(prec >= LQT_F64 && prec <= LQT_BF16 && nrhs >= 1, LQT_EINVAL, "bad tuning request");
         need_gauge(c);
-        double t = lqt::dslash_tune(c, prec, nrhs);
-        if (ms) *ms = t;
+        lqt::Tuned t;
+        double best = lqt::dslash_tune(c, prec, nrhs, &t);
+        if (ms) *ms = best;
+        if (tile) {
+            tile[0] = t.rhs_per_thread;
+            tile[1] = t.block;
+            tile[2] = t.chunk;
+        }
     });
 }
 

@@ -168,14 +168,29 @@ template <typename S, int R, bool DAG, int EPI>
 __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S* __restrict__ in, S* __restrict__ out,
                                                 const S* __restrict__ bvec, double* __restrict__ part, const int* act,
                                                 int L0, int L1, int L2, int L3, typename acc_of<S>::type diag, int nrhs,
-                                                long long in_stride, long long out_stride, int g5in, int g5out) {
+                                                long long in_stride, long long out_stride, int g5in, int g5out,
+                                                int chunk) {
     using C = typename acc_of<S>::type;
     const int V = L0 * L1 * L2 * L3;
     const int nsb = (V + blockDim.x - 1) / blockDim.x;
     const int ngrp = (nrhs + R - 1) / R;
     const int lb = xcd_block(nsb * ngrp);
     if (lb < 0) return;
-    const int sblk = lb / ngrp, grp = lb - sblk * ngrp;
+    // Block order.  chunk = 0: site block major (a thread's R links serve every group in
+    // turn).  chunk > 0: the lattice is cut into chunks of `chunk` site blocks (whole time
+    // slices for the usual sizes); each chunk is swept once per right-hand-side group, so
+    // the +-t and +-z neighbours of a block are read while they are still in the XCD's L2.
+    int sblk, grp;
+    if (chunk <= 0) {
+        sblk = lb / ngrp;
+        grp = lb - sblk * ngrp;
+    } else {
+        const int ch = lb / (chunk * ngrp);
+        const int cs = min(chunk, nsb - ch * chunk);
+        const int rem = lb - ch * chunk * ngrp;
+        grp = rem / cs;
+        sblk = ch * chunk + (rem - grp * cs);
+    }
     const int s = sblk * blockDim.x + threadIdx.x;
     const int r0 = grp * R;
     const int nr = min(R, nrhs - r0);
@@ -256,7 +271,7 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
 
 template <typename S, int R>
 static void launch_R(lqt_ctx* c, int op, const S* U, const S* in, S* out, int nrhs, long long is, long long os,
-                     int bs) {
+                     int bs, int chunk) {
     const Geom& g = c->g;
     using C = typename acc_of<S>::type;
     int nsb = (g.V + bs - 1) / bs;
@@ -267,11 +282,11 @@ static void launch_R(lqt_ctx* c, int op, const S* U, const S* in, S* out, int nr
     if (op == LQT_A_DAG)
         hipLaunchKernelGGL((k_dslash<S, R, true, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,
                            (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.L[0], g.L[1], g.L[2], g.L[3],
-                           diag, nrhs, is, os, 0, 0);
+                           diag, nrhs, is, os, 0, 0, chunk);
     else
         hipLaunchKernelGGL((k_dslash<S, R, false, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,
                            (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.L[0], g.L[1], g.L[2], g.L[3],
-                           diag, nrhs, is, os, g5in, g5out);
+                           diag, nrhs, is, os, g5in, g5out, chunk);
     LQT_HIP(hipGetLastError());
 }
 
@@ -295,13 +310,13 @@ const b2* gauge_of<b2>(lqt_ctx* c) {
 }
 
 template <typename S>
-static void launch_prec(lqt_ctx* c, int op, const void* in, void* out, int nrhs, long long is, long long os, int R,
-                        int bs) {
+static void launch_prec(lqt_ctx* c, int op, const void* in, void* out, int nrhs, long long is, long long os,
+                        const Tuned& t) {
     const S* U = gauge_of<S>(c);
-    switch (R) {
-        case 1: launch_R<S, 1>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, bs); break;
-        case 2: launch_R<S, 2>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, bs); break;
-        default: launch_R<S, 4>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, bs); break;
+    switch (t.rhs_per_thread) {
+        case 1: launch_R<S, 1>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk); break;
+        case 2: launch_R<S, 2>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk); break;
+        default: launch_R<S, 4>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk); break;
     }
 }
 
@@ -310,6 +325,7 @@ static long long tune_key(int prec, int nrhs) { return ((long long)prec << 32) |
 static Tuned default_tile(int prec, int nrhs) {
     Tuned t;
     t.block = 256;
+    t.chunk = 0;
     if (prec == LQT_F64)
         t.rhs_per_thread = nrhs >= 2 ? 2 : 1;
     else
@@ -320,10 +336,10 @@ static Tuned default_tile(int prec, int nrhs) {
 static void dslash_cfg(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long is, long long os,
                        Tuned t) {
     switch (prec) {
-        case LQT_F64: launch_prec<double2>(c, op, in, out, nrhs, is, os, t.rhs_per_thread, t.block); break;
-        case LQT_F32: launch_prec<float2>(c, op, in, out, nrhs, is, os, t.rhs_per_thread, t.block); break;
-        case LQT_F16: launch_prec<h2>(c, op, in, out, nrhs, is, os, t.rhs_per_thread, t.block); break;
-        default: launch_prec<b2>(c, op, in, out, nrhs, is, os, t.rhs_per_thread, t.block); break;
+        case LQT_F64: launch_prec<double2>(c, op, in, out, nrhs, is, os, t); break;
+        case LQT_F32: launch_prec<float2>(c, op, in, out, nrhs, is, os, t); break;
+        case LQT_F16: launch_prec<h2>(c, op, in, out, nrhs, is, os, t); break;
+        default: launch_prec<b2>(c, op, in, out, nrhs, is, os, t); break;
     }
 }
 
@@ -339,9 +355,9 @@ void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, l
     c->timer.end(c->stream, (double)c->g.V * (72.0 * b + 48.0 * b * nrhs));
 }
 
-// Autotuner: time every (rhs per thread, block size) candidate on scratch fields and keep
+// Autotuner: time every (rhs per thread, block size, chunk) candidate on scratch fields and keep
 // the fastest for this (precision, nrhs).
-double dslash_tune(lqt_ctx* c, int prec, int nrhs) {
+double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen) {
     const size_t eb = storage_bytes(prec);
     const long long n = 12LL * c->g.V;
     DBuf a, b;
@@ -350,6 +366,7 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs) {
     LQT_HIP(hipMemsetAsync(a.p, 0, (size_t)n * nrhs * eb, c->stream));
     const int Rs[3] = {1, 2, 4};
     const int Bs[3] = {64, 128, 256};
+    const int Cs[3] = {0, 16, 64};
     hipEvent_t e0, e1;
     LQT_HIP(hipEventCreate(&e0));
     LQT_HIP(hipEventCreate(&e1));
@@ -358,8 +375,9 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs) {
     for (int ri = 0; ri < 3; ri++) {
         if (Rs[ri] > nrhs) continue;
         if (prec == LQT_F64 && Rs[ri] > 2) continue;
-        for (int bi = 0; bi < 3; bi++) {
-            Tuned t{Rs[ri], Bs[bi]};
+        for (int bi = 0; bi < 3; bi++)
+        for (int ci = 0; ci < 3; ci++) {
+            Tuned t{Rs[ri], Bs[bi], Cs[ci]};
             dslash_cfg(c, prec, LQT_A, a.p, b.p, nrhs, n, n, t);  // warm
             LQT_HIP(hipEventRecord(e0, c->stream));
             const int reps = 5;
@@ -377,6 +395,7 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->tuned[tune_key(prec, nrhs)] = bt;
+    if (chosen) *chosen = bt;
     return best;
 }
 
@@ -407,7 +426,7 @@ void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, doub
     c->timer.begin(c->stream, KT_RESID);
     hipLaunchKernelGGL((k_dslash<double2, 1, false, 1>), dim3(xcd_grid(nsb * nrhs)), dim3(bs), 0, c->stream,
                        c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.L[0], g.L[1], g.L[2], g.L[3],
-                       4.0 + c->mass, nrhs, n, n, 0, 0);
+                       4.0 + c->mass, nrhs, n, n, 0, 0, 0);
     LQT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, c->stream, part, nsb, nrhs, rnorm2);
     LQT_HIP(hipGetLastError());

@@ -1,7 +1,8 @@
 // Batched restarted GMRES building blocks (gfx950).
 //
 // A batch of `ns` systems ("slots") advances in lock step.  The Krylov basis of slot q is
-// stored as V[i][q][comp][site] in storage type S.  Stored vectors are not unit vectors:
+// stored as V[i][q][comp][site] in storage type S (the dot and update passes only need
+// every vector of a slot in the same layout).  Stored vectors are not unit vectors:
 // the true basis vector is v_i = sc[i] * vhat_i, and every stored vector is written with
 // norm ~ sqrt(N) so that 16-bit storage neither overflows nor underflows.  With w = A v_j
 // computed on stored vectors (true w = sc_j * what):
@@ -52,9 +53,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------- 16-byte lanes
-// With SP = 16 / sizeof(S) consecutive sites per lane, every component of a vector is read
-// with one 16-byte load per lane (4 sites for BF16/FP16, 2 for FP32, 1 for FP64); used when
-// the volume is a multiple of SP (then every component row is 16-byte aligned).
+// SP = 16 / sizeof(S) complex values per 16-byte load (4 for BF16/FP16, 2 for FP32, 1 for FP64).
 template <typename S>
 struct Lanes {
     static constexpr int SP = 16 / (int)sizeof(S);
@@ -115,100 +114,114 @@ __device__ __forceinline__ void st16(S* p, cx<C> o[SP]) {
     }
 }
 
-// dot pass with SP sites per lane (V % SP == 0): same output as k_cgs_dots
-template <typename S, int SP>
-__global__ __launch_bounds__(256) void k_cgs_dots_v(const S* __restrict__ Vb, long long vstride, int j, int V,
-                                                    double2* __restrict__ part) {
+// ---------------------------------------------------------------------------- flat passes
+// The dot and update passes see a slot vector as n * sizeof(S) / 16 chunks of 16 bytes (SP
+// complex values each; 12 V sizeof(S) is always a multiple of 16).  A block covers KTILE
+// consecutive chunks of every vector, KCH per thread (strided by 256 so that each load
+// instruction of a wave reads 1 KiB contiguously), and keeps its chunks of w in registers
+// across the loop over the basis.  Lane partial sums are reduced across the wave with DPP
+// (no LDS traffic per basis vector).
+constexpr int KCH = 4;
+constexpr int KTILE = 256 * KCH;
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+// sum over the 64 lanes (every lane active), returned in every lane
+__device__ __forceinline__ float wave_sum_f(float v) {
+    v += dpp_f<0xB1>(v);         // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);         // quad_perm [2,3,0,1]
+    v += dpp_f<0x141>(v);        // row_half_mirror: sums of 8
+    v += dpp_f<0x140>(v);        // row_mirror: sums of 16 (every lane of a row)
+    v += dpp_f<0x142, 0xA>(v);   // row_bcast15 into rows 1, 3
+    v += dpp_f<0x143, 0xC>(v);   // row_bcast31 into rows 2, 3: lane 63 holds the total
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+template <typename C>
+__device__ __forceinline__ double wsum(C v) {
+    if constexpr (sizeof(C) == 4)
+        return (double)wave_sum_f(v);
+    else
+        return wave_sum(v);
+}
+
+// dot pass: part[(q*nsb + blk)*(j+2) + i] = (vhat_i^+ what) over the block's chunks for
+// i <= j, and (|what|^2, 0) at i = j+1
+template <typename S>
+__global__ __launch_bounds__(256) void k_cgs_dots(const S* __restrict__ Vb, long long vstride, int j, long long nch,
+                                                  double2* __restrict__ part) {
     using C = typename acc_of<S>::type;
+    constexpr int SP = Lanes<S>::SP;
     __shared__ double red[4][KRY_MAXM + 2][2];
     const int q = blockIdx.y;
     const int nsb = gridDim.x;
-    const int s0 = (blockIdx.x * 256 + threadIdx.x) * SP;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long n = 12LL * V;
+    const long long n = nch * SP;
+    const long long k0 = (long long)blockIdx.x * KTILE + threadIdx.x;
     const S* w = Vb + (long long)(j + 1) * vstride + q * n;
-    const bool ok = s0 < V;
-    cx<C> wv[12][SP];
+    cx<C> wv[KCH][SP];
     double nw = 0;
 #pragma unroll
-    for (int c = 0; c < 12; c++) {
-        if (ok)
-            ld16<S, C, SP>(w + (long long)c * V + s0, wv[c]);
+    for (int c = 0; c < KCH; c++) {
+        const long long k = k0 + 256 * c;
+        if (k < nch)
+            ld16<S, C, SP>(w + k * SP, wv[c]);
         else
 #pragma unroll
-            for (int k = 0; k < SP; k++) wv[c][k] = {0, 0};
+            for (int t = 0; t < SP; t++) wv[c][t] = {0, 0};
 #pragma unroll
-        for (int k = 0; k < SP; k++) nw += (double)wv[c][k].x * wv[c][k].x + (double)wv[c][k].y * wv[c][k].y;
+        for (int t = 0; t < SP; t++) nw += (double)wv[c][t].x * wv[c][t].x + (double)wv[c][t].y * wv[c][t].y;
     }
-    for (int i = 0; i <= j; i++) {
-        const S* vi = Vb + (long long)i * vstride + q * n;
-        C dr = 0, di = 0;
-        if (ok) {
+    int i = 0;
+    for (; i + 1 <= j; i += 2) {  // two basis vectors per trip: twice the loads in flight
+        const S* v0 = Vb + (long long)i * vstride + q * n;
+        const S* v1 = v0 + vstride;
+        C r0 = 0, i0 = 0, r1 = 0, i1 = 0;
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                cx<C> v[SP];
-                ld16<S, C, SP>(vi + (long long)c * V + s0, v);
+        for (int c = 0; c < KCH; c++) {
+            const long long k = k0 + 256 * c;
+            if (k < nch) {
+                cx<C> a[SP], b[SP];
+                ld16<S, C, SP>(v0 + k * SP, a);
+                ld16<S, C, SP>(v1 + k * SP, b);
 #pragma unroll
-                for (int k = 0; k < SP; k++) {
-                    dr += v[k].x * wv[c][k].x + v[k].y * wv[c][k].y;
-                    di += v[k].x * wv[c][k].y - v[k].y * wv[c][k].x;
+                for (int t = 0; t < SP; t++) {
+                    r0 += a[t].x * wv[c][t].x + a[t].y * wv[c][t].y;
+                    i0 += a[t].x * wv[c][t].y - a[t].y * wv[c][t].x;
+                    r1 += b[t].x * wv[c][t].x + b[t].y * wv[c][t].y;
+                    i1 += b[t].x * wv[c][t].y - b[t].y * wv[c][t].x;
                 }
             }
         }
-        double a = wave_sum((double)dr), b = wave_sum((double)di);
+        const double s0 = wsum(r0), s1 = wsum(i0), s2 = wsum(r1), s3 = wsum(i1);
         if (lane == 0) {
-            red[wave][i][0] = a;
-            red[wave][i][1] = b;
+            red[wave][i][0] = s0;
+            red[wave][i][1] = s1;
+            red[wave][i + 1][0] = s2;
+            red[wave][i + 1][1] = s3;
         }
     }
-    nw = wave_sum(nw);
-    if (lane == 0) {
-        red[wave][j + 1][0] = nw;
-        red[wave][j + 1][1] = 0;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= j + 1; i += 256) {
-        double a = red[0][i][0] + red[1][i][0] + red[2][i][0] + red[3][i][0];
-        double b = red[0][i][1] + red[1][i][1] + red[2][i][1] + red[3][i][1];
-        part[((long long)q * nsb + blockIdx.x) * (j + 2) + i] = make_double2(a, b);
-    }
-}
-
-// ---------------------------------------------------------------------------- dot pass
-// part[(q*nsb + blk)*(j+2) + i]: i <= j: d_i, i = j+1: (|what|^2, 0)
-template <typename S>
-__global__ __launch_bounds__(256) void k_cgs_dots(const S* __restrict__ Vb, long long vstride, int j, int V,
-                                                  double2* __restrict__ part) {
-    using C = typename acc_of<S>::type;
-    __shared__ double red[4][KRY_MAXM + 2][2];
-    const int q = blockIdx.y;
-    const int nsb = gridDim.x;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long n = 12LL * V;
-    const S* w = Vb + (long long)(j + 1) * vstride + q * n;
-    cx<C> wv[12];
-    double nw = 0;
+    if (i <= j) {
+        const S* v0 = Vb + (long long)i * vstride + q * n;
+        C r0 = 0, i0 = 0;
 #pragma unroll
-    for (int c = 0; c < 12; c++) {
-        wv[c] = s < V ? ldk<S, C>(w + (long long)c * V + s) : cx<C>{0, 0};
-        nw += (double)wv[c].x * wv[c].x + (double)wv[c].y * wv[c].y;
-    }
-    for (int i = 0; i <= j; i++) {
-        const S* vi = Vb + (long long)i * vstride + q * n;
-        C dr = 0, di = 0;
-        if (s < V) {
+        for (int c = 0; c < KCH; c++) {
+            const long long k = k0 + 256 * c;
+            if (k < nch) {
+                cx<C> a[SP];
+                ld16<S, C, SP>(v0 + k * SP, a);
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                cx<C> v = ldk<S, C>(vi + (long long)c * V + s);
-                dr += v.x * wv[c].x + v.y * wv[c].y;
-                di += v.x * wv[c].y - v.y * wv[c].x;
+                for (int t = 0; t < SP; t++) {
+                    r0 += a[t].x * wv[c][t].x + a[t].y * wv[c][t].y;
+                    i0 += a[t].x * wv[c][t].y - a[t].y * wv[c][t].x;
+                }
             }
         }
-        double a = wave_sum((double)dr), b = wave_sum((double)di);
+        const double s0 = wsum(r0), s1 = wsum(i0);
         if (lane == 0) {
-            red[wave][i][0] = a;
-            red[wave][i][1] = b;
+            red[wave][i][0] = s0;
+            red[wave][i][1] = s1;
         }
     }
     nw = wave_sum(nw);
@@ -217,29 +230,31 @@ __global__ __launch_bounds__(256) void k_cgs_dots(const S* __restrict__ Vb, long
         red[wave][j + 1][1] = 0;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i <= j + 1; i += 256) {
-        double a = red[0][i][0] + red[1][i][0] + red[2][i][0] + red[3][i][0];
-        double b = red[0][i][1] + red[1][i][1] + red[2][i][1] + red[3][i][1];
-        part[((long long)q * nsb + blockIdx.x) * (j + 2) + i] = make_double2(a, b);
+    for (int t = threadIdx.x; t <= j + 1; t += 256) {
+        const double a = red[0][t][0] + red[1][t][0] + red[2][t][0] + red[3][t][0];
+        const double b = red[0][t][1] + red[1][t][1] + red[2][t][1] + red[3][t][1];
+        part[((long long)q * nsb + blockIdx.x) * (j + 2) + t] = make_double2(a, b);
     }
 }
 
-// One block (64 threads) per slot: finish the sums, fill column j of H, the update
+// One block (256 threads) per slot: finish the sums, fill column j of H, the update
 // coefficients alpha_i = sc_i^2 d_i and the write scale fac = sqrt(N)/nu.
 // pass 0 overwrites H[:, j], pass 1 (re-orthogonalisation) adds to it.
-__global__ void k_cgs_finish(const double2* __restrict__ part, int nsb, int j, KryState st, int pass, double sqrtN) {
+__global__ __launch_bounds__(256) void k_cgs_finish(const double2* __restrict__ part, int nsb, int j, KryState st,
+                                                    int pass, double sqrtN) {
     const int q = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ double2 d[KRY_MAXM + 2];
-    for (int i = 0; i <= j + 1; i++) {
+    for (int i = wave; i <= j + 1; i += 4) {  // one wave per basis index
         double a = 0, b = 0;
-        for (int k = threadIdx.x; k < nsb; k += 64) {
+        for (int k = lane; k < nsb; k += 64) {
             double2 p = part[((long long)q * nsb + k) * (j + 2) + i];
             a += p.x;
             b += p.y;
         }
         a = wave_sum(a);
         b = wave_sum(b);
-        if (threadIdx.x == 0) d[i] = make_double2(a, b);
+        if (lane == 0) d[i] = make_double2(a, b);
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -271,40 +286,81 @@ __global__ void k_cgs_finish(const double2* __restrict__ part, int nsb, int j, K
     st.nu[q] = sqrt(nu2);
 }
 
-// ---------------------------------------------------------------------------- update pass
-// what' = what - sum_i alpha_i vhat_i, optionally scaled by fac; partial |stored|^2.
+// update pass: what' = what - sum_i alpha_i vhat_i, optionally scaled by fac and stored;
+// part[q*nsb + blk] = |stored|^2 over the block's chunks (of the rounded stored values)
 template <typename S>
-__global__ __launch_bounds__(256) void k_cgs_update(S* __restrict__ Vb, long long vstride, int j, int V, KryState st,
-                                                    int scale, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_cgs_update(S* __restrict__ Vb, long long vstride, int j, long long nch,
+                                                    KryState st, int scale, double* __restrict__ part) {
     using C = typename acc_of<S>::type;
+    constexpr int SP = Lanes<S>::SP;
     __shared__ double red[4];
     const int q = blockIdx.y;
     const int nsb = gridDim.x;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    const long long n = 12LL * V;
     const int m = st.m;
+    const long long n = nch * SP;
+    const long long k0 = (long long)blockIdx.x * KTILE + threadIdx.x;
     S* w = Vb + (long long)(j + 1) * vstride + q * n;
-    double nrm = 0;
-    if (s < V) {
-        cx<C> wv[12];
+    const double2* alpha = st.alpha + (long long)q * (m + 1);
+    cx<C> wv[KCH][SP];
 #pragma unroll
-        for (int c = 0; c < 12; c++) wv[c] = ldk<S, C>(w + (long long)c * V + s);
-        for (int i = 0; i <= j; i++) {
-            double2 a = st.alpha[(long long)q * (m + 1) + i];
-            C ar = (C)a.x, ai = (C)a.y;
-            const S* vi = Vb + (long long)i * vstride + q * n;
+    for (int c = 0; c < KCH; c++) {
+        const long long k = k0 + 256 * c;
+        if (k < nch)
+            ld16<S, C, SP>(w + k * SP, wv[c]);
+        else
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                cx<C> v = ldk<S, C>(vi + (long long)c * V + s);
-                wv[c].x -= ar * v.x - ai * v.y;
-                wv[c].y -= ar * v.y + ai * v.x;
+            for (int t = 0; t < SP; t++) wv[c][t] = {0, 0};
+    }
+    int i = 0;
+    for (; i + 1 <= j; i += 2) {
+        const double2 a0 = alpha[i], a1 = alpha[i + 1];
+        const C ar = (C)a0.x, ai = (C)a0.y, br = (C)a1.x, bi = (C)a1.y;
+        const S* v0 = Vb + (long long)i * vstride + q * n;
+        const S* v1 = v0 + vstride;
+#pragma unroll
+        for (int c = 0; c < KCH; c++) {
+            const long long k = k0 + 256 * c;
+            if (k < nch) {
+                cx<C> a[SP], b[SP];
+                ld16<S, C, SP>(v0 + k * SP, a);
+                ld16<S, C, SP>(v1 + k * SP, b);
+#pragma unroll
+                for (int t = 0; t < SP; t++) {
+                    wv[c][t].x -= ar * a[t].x - ai * a[t].y + br * b[t].x - bi * b[t].y;
+                    wv[c][t].y -= ar * a[t].y + ai * a[t].x + br * b[t].y + bi * b[t].x;
+                }
             }
         }
-        C f = scale ? (C)st.fac[q] : (C)1;
+    }
+    if (i <= j) {
+        const double2 a0 = alpha[i];
+        const C ar = (C)a0.x, ai = (C)a0.y;
+        const S* v0 = Vb + (long long)i * vstride + q * n;
 #pragma unroll
-        for (int c = 0; c < 12; c++) {
-            cx<C> o = stk<S, C>(w + (long long)c * V + s, cx<C>{wv[c].x * f, wv[c].y * f});
-            nrm += (double)o.x * o.x + (double)o.y * o.y;
+        for (int c = 0; c < KCH; c++) {
+            const long long k = k0 + 256 * c;
+            if (k < nch) {
+                cx<C> a[SP];
+                ld16<S, C, SP>(v0 + k * SP, a);
+#pragma unroll
+                for (int t = 0; t < SP; t++) {
+                    wv[c][t].x -= ar * a[t].x - ai * a[t].y;
+                    wv[c][t].y -= ar * a[t].y + ai * a[t].x;
+                }
+            }
+        }
+    }
+    const C f = scale ? (C)st.fac[q] : (C)1;
+    double nrm = 0;
+#pragma unroll
+    for (int c = 0; c < KCH; c++) {
+        const long long k = k0 + 256 * c;
+        if (k < nch) {
+#pragma unroll
+            for (int t = 0; t < SP; t++) wv[c][t] = {wv[c][t].x * f, wv[c][t].y * f};
+            st16<S, C, SP>(w + k * SP, wv[c]);
+#pragma unroll
+            for (int t = 0; t < SP; t++) nrm += (double)wv[c][t].x * wv[c][t].x + (double)wv[c][t].y * wv[c][t].y;
         }
     }
     nrm = wave_sum(nrm);
@@ -313,53 +369,6 @@ __global__ __launch_bounds__(256) void k_cgs_update(S* __restrict__ Vb, long lon
     if (threadIdx.x == 0) part[(long long)q * nsb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// update pass with SP sites per lane (V % SP == 0): same output as k_cgs_update
-template <typename S, int SP>
-__global__ __launch_bounds__(256) void k_cgs_update_v(S* __restrict__ Vb, long long vstride, int j, int V,
-                                                      KryState st, int scale, double* __restrict__ part) {
-    using C = typename acc_of<S>::type;
-    __shared__ double red[4];
-    const int q = blockIdx.y;
-    const int nsb = gridDim.x;
-    const int s0 = (blockIdx.x * 256 + threadIdx.x) * SP;
-    const long long n = 12LL * V;
-    const int m = st.m;
-    S* w = Vb + (long long)(j + 1) * vstride + q * n;
-    double nrm = 0;
-    if (s0 < V) {
-        cx<C> wv[12][SP];
-#pragma unroll
-        for (int c = 0; c < 12; c++) ld16<S, C, SP>(w + (long long)c * V + s0, wv[c]);
-        for (int i = 0; i <= j; i++) {
-            const double2 a = st.alpha[(long long)q * (m + 1) + i];
-            const C ar = (C)a.x, ai = (C)a.y;
-            const S* vi = Vb + (long long)i * vstride + q * n;
-#pragma unroll
-            for (int c = 0; c < 12; c++) {
-                cx<C> v[SP];
-                ld16<S, C, SP>(vi + (long long)c * V + s0, v);
-#pragma unroll
-                for (int k = 0; k < SP; k++) {
-                    wv[c][k].x -= ar * v[k].x - ai * v[k].y;
-                    wv[c][k].y -= ar * v[k].y + ai * v[k].x;
-                }
-            }
-        }
-        const C f = scale ? (C)st.fac[q] : (C)1;
-#pragma unroll
-        for (int c = 0; c < 12; c++) {
-#pragma unroll
-            for (int k = 0; k < SP; k++) wv[c][k] = {wv[c][k].x * f, wv[c][k].y * f};
-            st16<S, C, SP>(w + (long long)c * V + s0, wv[c]);
-#pragma unroll
-            for (int k = 0; k < SP; k++) nrm += (double)wv[c][k].x * wv[c][k].x + (double)wv[c][k].y * wv[c][k].y;
-        }
-    }
-    nrm = wave_sum(nrm);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
-    __syncthreads();
-    if (threadIdx.x == 0) part[(long long)q * nsb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
 
 // One block (64 threads) per slot: mu, sc_{j+1}, H[j+1][j], then the Givens step.
 __global__ void k_norm_givens(const double* __restrict__ part, int nsb, int j, KryState st, double sqrtN) {
@@ -511,37 +520,29 @@ __global__ void k_start_state(KryState st, const int* __restrict__ src, const do
 }
 
 // ---------------------------------------------------------------------------- host side
+// chunks of 16 bytes in one slot vector (12 V complex values of S)
 template <typename S>
-static bool vec_ok(const lqt_ctx* c) {
-    return Lanes<S>::SP > 1 && c->g.V % Lanes<S>::SP == 0;
+static long long kry_chunks(const lqt_ctx* c) {
+    return 12LL * c->g.V * (long long)sizeof(S) / 16;
 }
 
 // partial-sum blocks per slot of the dot and update passes
 template <typename S>
 int kry_blocks(const lqt_ctx* c) {
-    const int sp = vec_ok<S>(c) ? Lanes<S>::SP : 1;
-    return (c->g.V / sp + 255) / 256 + ((c->g.V % sp) ? 1 : 0);
+    return (int)((kry_chunks<S>(c) + KTILE - 1) / KTILE);
 }
 
 template <typename S>
 void kry_dots(lqt_ctx* c, const void* Vb, long long vstride, int j, int ns, double2* part) {
     dim3 grid(kry_blocks<S>(c), ns);
-    if (vec_ok<S>(c))
-        hipLaunchKernelGGL((k_cgs_dots_v<S, Lanes<S>::SP>), grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, j,
-                           c->g.V, part);
-    else
-        hipLaunchKernelGGL(k_cgs_dots<S>, grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, j, c->g.V, part);
+    hipLaunchKernelGGL(k_cgs_dots<S>, grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, j, kry_chunks<S>(c), part);
     LQT_HIP(hipGetLastError());
 }
 template <typename S>
 void kry_update(lqt_ctx* c, void* Vb, long long vstride, int j, int ns, const KryState& st, int scale, double* part) {
     dim3 grid(kry_blocks<S>(c), ns);
-    if (vec_ok<S>(c))
-        hipLaunchKernelGGL((k_cgs_update_v<S, Lanes<S>::SP>), grid, dim3(256), 0, c->stream, (S*)Vb, vstride, j,
-                           c->g.V, st, scale, part);
-    else
-        hipLaunchKernelGGL(k_cgs_update<S>, grid, dim3(256), 0, c->stream, (S*)Vb, vstride, j, c->g.V, st, scale,
-                           part);
+    hipLaunchKernelGGL(k_cgs_update<S>, grid, dim3(256), 0, c->stream, (S*)Vb, vstride, j, kry_chunks<S>(c), st, scale,
+                       part);
     LQT_HIP(hipGetLastError());
 }
 template <typename S>
@@ -560,7 +561,7 @@ void kry_start(lqt_ctx* c, void* V0, const double2* r, const int* src, const dou
 }
 
 void kry_finish(lqt_ctx* c, const double2* part, int nsb, int j, int ns, const KryState& st, int pass) {
-    hipLaunchKernelGGL(k_cgs_finish, dim3(ns), dim3(64), 0, c->stream, part, nsb, j, st, pass, sqrt(12.0 * c->g.V));
+    hipLaunchKernelGGL(k_cgs_finish, dim3(ns), dim3(256), 0, c->stream, part, nsb, j, st, pass, sqrt(12.0 * c->g.V));
     LQT_HIP(hipGetLastError());
 }
 void kry_norm_givens(lqt_ctx* c, const double* part, int nsb, int j, int ns, const KryState& st) {

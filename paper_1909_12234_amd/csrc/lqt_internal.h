@@ -279,6 +279,7 @@ struct KTimer {
 struct Tuned {
     int rhs_per_thread;
     int block;
+    int chunk;  // site blocks per sweep (0: site-block-major order)
 };
 
 struct Net {
@@ -286,6 +287,7 @@ struct Net {
     std::vector<float> w;  // FP32 master weights (complex pairs), host copy
     DBuf wf;               // the weights the kernels use (BF16-rounded values held as FP32)
     DBuf act;              // two FP32 activation fields for the hidden layers
+    DBuf train[8];         // training workspace (weights, activations, deltas, Gram blocks)
 };
 
 }  // namespace lqt
@@ -345,7 +347,7 @@ void convert_out_c64(lqt_ctx* c, const S* dev, float2* canon, int nrhs);
 // ---- dslash (dslash.hip): out = op(in), device layout, nrhs fields
 void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long in_stride,
             long long out_stride);
-double dslash_tune(lqt_ctx* c, int prec, int nrhs);
+double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen = nullptr);
 // FP64 residual r = b - A x for nrhs fields and squared norms (device layout FP64).
 // act maps slot -> field index (nullptr = identity).
 // act (device, may be null) maps slot -> field index of b and x; r is slot-ordered.

@@ -120,20 +120,20 @@ __global__ __launch_bounds__(256) void k_ptc_layer(const float2* __restrict__ U,
         for (int a = 0; a < 3; a++) pst<SO>(vout + (long long)(3 * f + a) * V + s, acc[f][a]);
 }
 
-// Transport only: out[p][g] = T_p in_g for p = 0..8 (FP64 fields), used for weight gradients.
-__global__ __launch_bounds__(256) void k_transport64(const double2* __restrict__ U, const double2* __restrict__ in,
-                                                     double2* __restrict__ out, int F, int p, int L0, int L1, int L2,
-                                                     int L3) {
+// Transport only, all nine paths: out[p][g] = T_p in_g (FP64 fields [g][colour][V] in,
+// [p][g][colour][V] out; grid (site blocks, F, 9)), used for the weight gradients.
+__global__ __launch_bounds__(256) void k_transport9(const double2* __restrict__ U, const double2* __restrict__ in,
+                                                    double2* __restrict__ out, int F, int L0, int L1, int L2, int L3) {
     const int V = L0 * L1 * L2 * L3;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
-    const int g = blockIdx.y;
+    const int g = blockIdx.y, p = blockIdx.z;
     const int x = s % L0, y = (s / L0) % L1, z = (s / (L0 * L1)) % L2, t = s / (L0 * L1 * L2);
     const int st[4] = {1, L0, L0 * L1, L0 * L1 * L2};
     const int co[4] = {x, y, z, t};
     const int Ls[4] = {L0, L1, L2, L3};
     const double2* vin = in + (long long)3 * g * V;
-    double2* vo = out + (long long)3 * g * V;
+    double2* vo = out + ((long long)p * F + g) * 3 * V;
     if (p == 0) {
         for (int a = 0; a < 3; a++) vo[(long long)a * V + s] = vin[(long long)a * V + s];
         return;
@@ -158,6 +158,29 @@ __global__ __launch_bounds__(256) void k_transport64(const double2* __restrict__
         }
         vo[(long long)a * V + s] = make_double2(re, im);
     }
+}
+
+// delta = (a - e) * wq[q] for pair q (grid (256, np)); part[q*256 + b] = partial |a - e|^2
+__global__ __launch_bounds__(256) void k_ptc_delta(const double2* __restrict__ a, const double2* __restrict__ e,
+                                                   const double* __restrict__ wq, long long n,
+                                                   double2* __restrict__ del, double* __restrict__ part) {
+    __shared__ double red[256];
+    const int q = blockIdx.y;
+    const double w = wq[q];
+    double acc = 0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const double2 av = a[q * n + i], ev = e[q * n + i];
+        const double dx = av.x - ev.x, dy = av.y - ev.y;
+        acc += dx * dx + dy * dy;
+        del[q * n + i] = make_double2(dx * w, dy * w);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)q * gridDim.x + blockIdx.x] = red[0];
 }
 
 // ---------------------------------------------------------------- host side
@@ -258,93 +281,104 @@ static std::vector<float> adjoint_weights(const float* W, int fi, int fo) {
 }
 
 // Loss sum_pairs ||M r - e||^2 / ||e||^2 and its gradient with respect to conj(W) (FP64
-// fields r, e: npairs spinors in device layout).  grad receives 2 * ptc_weight_count() doubles.
+// fields r, e: np spinors in device layout).  grad receives 2 * ptc_weight_count() doubles.
+// Forward with stored activations a_1..a_4; delta_4 = (a_4 - e)/||e||^2; delta_{l-1} =
+// L_l^+ delta_l (the adjoint layer); G_l[p][f][g] = sum_x conj(T_p a_{l-1,g}) . delta_{l,f}
+// from one FP64 MFMA Gram product per (layer, pair); one device-to-host copy per call.
 double ptc_loss_grad(lqt_ctx* c, const double2* r, const double2* e, int np, const float* Wh, std::vector<double>& grad,
                      const std::vector<double>& enorm2) {
     const long long V = c->g.V;
+    const long long n = 12 * V;
     const int nw = ptc_weight_count();
     grad.assign(2 * nw, 0.0);
-    // device copies of this pass's weights and of the adjoint weights
-    DBuf Wd, Wa;
-    Wd.ensure(sizeof(float) * 2 * nw);
-    LQT_HIP(hipMemcpyAsync(Wd.p, Wh, sizeof(float) * 2 * nw, hipMemcpyHostToDevice, c->stream));
+    DBuf* tw = c->net.train;  // workspace kept across calls
+    // weights of this pass and their adjoints
     std::vector<float> adj;
+    int woff[NL];
     for (int l = 0, off = 0; l < NL; l++) {
+        woff[l] = off;
         std::vector<float> a = adjoint_weights(Wh + 2 * off, FEATS[l], FEATS[l + 1]);
         adj.insert(adj.end(), a.begin(), a.end());
         off += 9 * FEATS[l] * FEATS[l + 1];
     }
-    Wa.ensure(sizeof(float) * adj.size());
-    LQT_HIP(hipMemcpyAsync(Wa.p, adj.data(), sizeof(float) * adj.size(), hipMemcpyHostToDevice, c->stream));
-    // activations a_0 = r, a_1..a_4 (FP64, [pair][3F][V])
-    DBuf act[NL + 1], del[2], tp, G;
-    for (int l = 1; l <= NL; l++) act[l].ensure(sizeof(double2) * (size_t)np * 3 * FEATS[l] * V);
-    del[0].ensure(sizeof(double2) * (size_t)np * 24 * V);
-    del[1].ensure(sizeof(double2) * (size_t)np * 24 * V);
-    tp.ensure(sizeof(double2) * (size_t)8 * 3 * V);
-    G.ensure(sizeof(double2) * 64);
+    tw[0].ensure(sizeof(float) * 2 * nw);
+    tw[1].ensure(sizeof(float) * 2 * nw);
+    LQT_HIP(hipMemcpyAsync(tw[0].p, Wh, sizeof(float) * 2 * nw, hipMemcpyHostToDevice, c->stream));
+    LQT_HIP(hipMemcpyAsync(tw[1].p, adj.data(), sizeof(float) * 2 * nw, hipMemcpyHostToDevice, c->stream));
+    // activations a_1..a_4 (FP64, [pair][3F][V]) in one buffer, two delta buffers, the
+    // transported inputs of one pair, the Gram blocks of every (layer, pair), small vectors
+    size_t aoff[NL + 2];
+    aoff[1] = 0;
+    for (int l = 1; l <= NL; l++) aoff[l + 1] = aoff[l] + (size_t)np * 3 * FEATS[l] * V;
+    tw[2].ensure(sizeof(double2) * aoff[NL + 1]);
+    tw[3].ensure(sizeof(double2) * (size_t)np * 24 * V);
+    tw[4].ensure(sizeof(double2) * (size_t)np * 24 * V);
+    tw[5].ensure(sizeof(double2) * (size_t)9 * 8 * 3 * V);
+    tw[6].ensure(sizeof(double2) * (size_t)np * nw);
+    const int nbl = 256;
+    tw[7].ensure(sizeof(double) * ((size_t)np * nbl + np));
+    auto act = [&](int l) { return tw[2].as<double2>() + aoff[l]; };
+    double2* G = tw[6].as<double2>();
+    double* lpart = tw[7].as<double>();
+    double* wq = lpart + (size_t)np * nbl;
+    std::vector<double> hw(np);
+    for (int q = 0; q < np; q++) hw[q] = 1.0 / enorm2[q];
+    LQT_HIP(hipMemcpyAsync(wq, hw.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
+    const float2* Wd = tw[0].as<float2>();
+    const float2* Wa = tw[1].as<float2>();
     const double2* a_prev = r;
-    int woff[NL];
-    for (int l = 0, off = 0; l < NL; l++) {
-        woff[l] = off;
-        layer64_dyn(c, FEATS[l], FEATS[l + 1], Wd.as<float2>() + off, a_prev, act[l + 1].as<double2>(), np);
-        a_prev = act[l + 1].as<double2>();
-        off += 9 * FEATS[l] * FEATS[l + 1];
+    for (int l = 0; l < NL; l++) {
+        layer64_dyn(c, FEATS[l], FEATS[l + 1], Wd + woff[l], a_prev, act(l + 1), np);
+        a_prev = act(l + 1);
     }
-    // delta_4 = (a_4 - e) / ||e||^2 per pair, loss
-    std::vector<double2> h4((size_t)np * 12 * V), he((size_t)np * 12 * V);
-    LQT_HIP(hipMemcpyAsync(h4.data(), act[NL].p, sizeof(double2) * h4.size(), hipMemcpyDeviceToHost, c->stream));
-    LQT_HIP(hipMemcpyAsync(he.data(), e, sizeof(double2) * he.size(), hipMemcpyDeviceToHost, c->stream));
+    hipLaunchKernelGGL(k_ptc_delta, dim3(nbl, np), dim3(256), 0, c->stream, act(NL), e, wq, n,
+                       tw[3].as<double2>(), lpart);
+    LQT_HIP(hipGetLastError());
+    int cur = 3;
+    for (int l = NL; l >= 1; l--) {
+        const int fi = FEATS[l - 1], fo = FEATS[l];
+        const double2* ain = (l == 1) ? r : act(l - 1);
+        const double2* dl = tw[cur].as<double2>();
+        for (int q = 0; q < np; q++) {
+            dim3 grid((unsigned)((V + 255) / 256), fi, 9);
+            hipLaunchKernelGGL(k_transport9, grid, dim3(256), 0, c->stream, c->U[LQT_F64].as<double2>(),
+                               ain + (size_t)q * 3 * fi * V, tw[5].as<double2>(), fi, c->g.L[0], c->g.L[1],
+                               c->g.L[2], c->g.L[3]);
+            LQT_HIP(hipGetLastError());
+            // C[p*fi + g][f] = sum_x conj(T_p a_g) . delta_f   (vectors of length 3V)
+            gemm_gram(c, tw[5].as<double2>(), 9 * fi, dl + (size_t)q * 3 * fo * V, fo,
+                      G + (size_t)q * nw + woff[l - 1], 3LL * V);
+        }
+        if (l > 1) {  // delta_{l-1} = L_l^+ delta_l
+            const int nxt = (cur == 3) ? 4 : 3;
+            layer64_dyn(c, fo, fi, Wa + woff[l - 1], dl, tw[nxt].as<double2>(), np);
+            cur = nxt;
+        }
+    }
+    std::vector<double2> hG((size_t)np * nw);
+    std::vector<double> hl((size_t)np * nbl);
+    LQT_HIP(hipMemcpyAsync(hG.data(), G, sizeof(double2) * hG.size(), hipMemcpyDeviceToHost, c->stream));
+    LQT_HIP(hipMemcpyAsync(hl.data(), lpart, sizeof(double) * hl.size(), hipMemcpyDeviceToHost, c->stream));
     LQT_HIP(hipStreamSynchronize(c->stream));
     double loss = 0;
     for (int q = 0; q < np; q++) {
-        const double w = 1.0 / enorm2[q];
-        for (long long i = 0; i < 12 * V; i++) {
-            double2& d = h4[(size_t)q * 12 * V + i];
-            const double2 ee = he[(size_t)q * 12 * V + i];
-            d.x -= ee.x;
-            d.y -= ee.y;
-            loss += w * (d.x * d.x + d.y * d.y);
-            d.x *= w;
-            d.y *= w;
-        }
+        double lq = 0;
+        for (int b = 0; b < nbl; b++) lq += hl[(size_t)q * nbl + b];
+        loss += lq * hw[q];
     }
-    LQT_HIP(hipMemcpyAsync(del[0].p, h4.data(), sizeof(double2) * h4.size(), hipMemcpyHostToDevice, c->stream));
-    LQT_HIP(hipStreamSynchronize(c->stream));
-    // backward: layer l (1-based) has input a_{l-1} (F_l-1 features) and output delta_l
-    int cur = 0;
-    for (int l = NL; l >= 1; l--) {
-        const int fi = FEATS[l - 1], fo = FEATS[l];
-        const double2* ain = (l == 1) ? r : act[l - 1].as<double2>();
-        const double2* dl = del[cur].as<double2>();
-        for (int q = 0; q < np; q++) {
-            for (int p = 0; p < 9; p++) {
-                dim3 grid((c->g.V + 255) / 256, fi);
-                hipLaunchKernelGGL(k_transport64, grid, dim3(256), 0, c->stream, c->U[LQT_F64].as<double2>(),
-                                   ain + (size_t)q * 3 * fi * V, tp.as<double2>(), fi, p, c->g.L[0], c->g.L[1],
-                                   c->g.L[2], c->g.L[3]);
-                LQT_HIP(hipGetLastError());
-                // C[g][f] = sum_x conj(T_p a_g) . delta_f   (vectors of length 3V)
-                gemm_gram(c, tp.as<double2>(), fi, dl + (size_t)q * 3 * fo * V, fo, G.as<double2>(), 3LL * V);
-                double2 Ch[64];
-                LQT_HIP(hipMemcpyAsync(Ch, G.p, sizeof(double2) * fi * fo, hipMemcpyDeviceToHost, c->stream));
-                LQT_HIP(hipStreamSynchronize(c->stream));
-                for (int f = 0; f < fo; f++)
-                    for (int g = 0; g < fi; g++) {
-                        const double2 v = Ch[g * fo + f];
-                        // dL/dconj(W) = sum delta conj(T a): the gram gives conj(T a) . delta
-                        double* gw = grad.data() + 2 * (woff[l - 1] + (p * fo + f) * fi + g);
+    for (int q = 0; q < np; q++)
+        for (int l = 0; l < NL; l++) {
+            const int fi = FEATS[l], fo = FEATS[l + 1];
+            const double2* Gq = hG.data() + (size_t)q * nw + woff[l];
+            for (int p = 0; p < 9; p++)
+                for (int g = 0; g < fi; g++)
+                    for (int f = 0; f < fo; f++) {
+                        const double2 v = Gq[(p * fi + g) * fo + f];
+                        double* gw = grad.data() + 2 * (woff[l] + (p * fo + f) * fi + g);
                         gw[0] += v.x;
                         gw[1] += v.y;
                     }
-            }
         }
-        if (l > 1) {  // delta_{l-1} = L_l^+ delta_l
-            layer64_dyn(c, fo, fi, Wa.as<float2>() + woff[l - 1], dl, del[1 - cur].as<double2>(), np);
-            cur = 1 - cur;
-        }
-    }
-    LQT_HIP(hipStreamSynchronize(c->stream));
     return loss;
 }
 

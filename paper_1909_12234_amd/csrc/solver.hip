@@ -87,7 +87,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     const long long n = 12LL * c->g.V;
     const int m = o.restart;
     const size_t eb = sizeof(S);
-    const int nsb = (c->g.V + 255) / 256;
+    const int nsb = std::max(kry_blocks<S>(c), (c->g.V + 255) / 256);  // partial sums per slot
 
     DBuf& basisb = c->scratch[0];
     DBuf& rb = c->scratch[1];

@@ -85,7 +85,7 @@ _SIGS = {
     "lqt_prolong": ([_P, _P, _P, _P, _I], _I),
     "lqt_prolongator_get": ([_P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
     "lqt_basis_prolongator_from": ([_P, _P, _I, _P, _P, _I, ctypes.POINTER(_P)], _I),
-    "lqt_tune": ([_P, _I, _I, ctypes.POINTER(_D)], _I),
+    "lqt_tune": ([_P, _I, _I, ctypes.POINTER(_D), _P], _I),
     "lqt_kernel_times": ([_P, _P, _P, _P, _I], _I),
     "lqt_last_error": ([_P], ctypes.c_char_p),
     "lqt_destroy": ([_P], None),
@@ -190,10 +190,13 @@ class Context:
         self._check(lib().lqt_probes(self._h, ctypes.c_uint64(seed), int(j0), int(nprobes), _ptr(out)))
         return out
 
-    def tune(self, prec, nrhs):
+    def tune(self, prec, nrhs, return_tile=False):
+        """Autotune the dslash tiling for (prec, nrhs); the best time in ms (and the tile
+        (rhs per thread, block, chunk) with return_tile)."""
         ms = ctypes.c_double(0)
-        self._check(lib().lqt_tune(self._h, int(prec), int(nrhs), ctypes.byref(ms)))
-        return ms.value
+        tile = (ctypes.c_int * 3)()
+        self._check(lib().lqt_tune(self._h, int(prec), int(nrhs), ctypes.byref(ms), tile))
+        return (ms.value, tuple(tile)) if return_tile else ms.value
 
     KERNEL_FAMILIES = ["dslash", "cgs_dots", "cgs_update", "residual_fp64", "krylov_other", "projections",
                        "prolongator", "net"]
