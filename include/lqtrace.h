@@ -79,6 +79,11 @@ typedef struct {
     int verbose;     /* 1: progress lines on stderr from long calls (eigensolver, setup) */
     int outer_maxit; /* cap on eigensolver iterations (lqt_basis_eig / the coarse
                         eigensolve of lqt_basis_prolongator) [60]                       */
+    int graph;       /* 1: capture each inner cycle (all m Arnoldi steps, the small
+                        Hessenberg updates and the solution update) in a HIP graph once
+                        per batch size and replay it; cycles always run all m steps (the
+                        steps after a system has converged change nothing), so results
+                        are bit-identical to graph = 0 [0]                               */
 } lqt_solver_opts;
 
 /* Per right-hand side solve statistics. */
@@ -122,6 +127,18 @@ typedef struct {
  * header comment.  On failure *ctx is NULL and the code is returned. */
 int lqt_create(lqt_ctx **ctx, const int dims[4], double mass, int t_antiperiodic,
                void *hip_stream);
+
+/* Create a context for nlat (1..8) lattices solved together (dims[4k..4k+3] = Lx, Ly, Lz, Lt
+ * of lattice k, masses[k] its bare mass; all other arguments as lqt_create).  The operator
+ * is block diagonal over the lattices and every kernel launch covers all of them (a block
+ * of sites never straddles two lattices).  Fields and links in the canonical layout are the
+ * lattices' canonical arrays one after the other (per right-hand side for fields).  Probes
+ * restrict to each lattice as they would for a context of that lattice alone; a solve stops
+ * when every lattice block meets ||b_k - A_k x_k|| <= xi ||b_k||.  lqt_trace_lattices gives
+ * one estimate per lattice.  Deflation bases, the prolongator and the network preconditioner
+ * need a single-lattice context (LQT_EINVAL).  lqt_set_mass sets every lattice's mass. */
+int lqt_create_multi(lqt_ctx **ctx, int nlat, const int *dims, const double *masses,
+                     int t_antiperiodic, void *hip_stream);
 
 /* Upload the gauge field (canonical layout, V*4*9 complex128 = 144*V doubles), from host
  * memory (on_device = 0) or device memory (1).  The field is copied into the device
@@ -253,6 +270,14 @@ int lqt_trace(lqt_ctx *ctx, const lqt_basis *basis, int projector, int nprobes, 
               double xi, const lqt_solver_opts *opts, lqt_trace_result *out,
               double *h_rank_curve, double *h_samples);
 
+/* Undeflated Hutchinson estimates of trace(A_k^{-1}), one per lattice of the context (Eq. 1;
+ * the same probes and solves as lqt_trace, the samples split by lattice): res receives nlat
+ * results, samples (may be NULL) 2*nlat*nprobes doubles [lattice][probe] (re, im).  nsolves,
+ * nfailed and iters_total count the joint solves of all lattices.  Returns LQT_ENOTCONV as
+ * lqt_trace. */
+int lqt_trace_lattices(lqt_ctx *ctx, int nprobes, uint64_t seed, double xi,
+                       const lqt_solver_opts *opts, lqt_trace_result *res, double *h_samples);
+
 /* ---- building blocks (exposed for verification and measurement) ------------------- */
 
 /* Write the real Rademacher probes j0 .. j0+nprobes-1 as canonical complex128 fields. */
@@ -303,8 +328,9 @@ int lqt_tune(lqt_ctx *ctx, int prec, int nrhs, double *ms, int *tile);
 /* Kernel timers: HIP event pairs recorded around the library's launches on the context
  * stream, summed per kernel family: 0 Wilson operator of the inner cycles, 1 CGS dot
  * pass, 2 CGS update pass, 3 FP64 residual (defect correction), 4 other Krylov kernels,
- * 5 deflation projections, 6 prolongator restrict/prolong, 7 transport network.  h_ms,
- * h_calls and h_bytes (each 8 entries, may be NULL) receive the device milliseconds, the
+ * 5 deflation projections, 6 prolongator restrict/prolong, 7 transport network, 8 graph-
+ * captured inner cycles (opts->graph: a whole cycle is one launch).  h_ms, h_calls and
+ * h_bytes (each 9 entries, may be NULL) receive the device milliseconds, the
  * launch counts and the algorithmic HBM bytes of the timed launches.  mode 0: read;
  * 1: read, then zero; 2: zero and start timing; 3: stop timing.  Timing is off by default
  * and costs two event records per launch when on. */

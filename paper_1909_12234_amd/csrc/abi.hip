@@ -45,11 +45,20 @@ int lqt_create(lqt_ctx** ctx, const int dims[4], double mass, int t_antiperiodic
         if (dims[i] < 2) return LQT_EINVAL;
         V *= dims[i];
     }
-    if (V > (1LL << 30) / 12 || !std::isfinite(mass)) return LQT_EINVAL;
+    // every FP64 field of one right-hand side stays below 4 GiB (32-bit byte offsets in the kernels)
+    if (V > (1LL << 32) / (12 * 16) - 256 || !std::isfinite(mass)) return LQT_EINVAL;
     lqt_ctx* c = new (std::nothrow) lqt_ctx();
     if (!c) return LQT_ENOMEM;
     for (int i = 0; i < 4; i++) c->g.L[i] = dims[i];
     c->g.V = (int)V;
+    c->g.lat.nlat = 1;
+    for (int i = 0; i < 4; i++) c->g.lat.L[0][i] = dims[i];
+    c->g.lat.off[0] = 0;
+    c->g.lat.off[1] = (int)V;
+    c->g.lat.coff[0] = 0;
+    c->g.lat.coff[1] = (int)V;
+    c->g.lat.diag[0] = 4.0 + mass;
+    c->g.canon_sites = V;
     c->N = 12 * V;
     c->mass = mass;
     c->antiperiodic = t_antiperiodic ? 1 : 0;
@@ -63,9 +72,45 @@ int lqt_create(lqt_ctx** ctx, const int dims[4], double mass, int t_antiperiodic
     return LQT_OK;
 }
 
+int lqt_create_multi(lqt_ctx** ctx, int nlat, const int* dims, const double* masses, int t_antiperiodic,
+                     void* hip_stream) {
+    if (!ctx) return LQT_EINVAL;
+    *ctx = nullptr;
+    if (nlat < 1 || nlat > lqt::LQT_MAXLAT || !dims || !masses) return LQT_EINVAL;
+    lqt::LatTab t{};
+    t.nlat = nlat;
+    long long off = 0, coff = 0;
+    for (int k = 0; k < nlat; k++) {
+        long long Vk = 1;
+        for (int i = 0; i < 4; i++) {
+            if (dims[4 * k + i] < 2) return LQT_EINVAL;
+            t.L[k][i] = dims[4 * k + i];
+            Vk *= dims[4 * k + i];
+        }
+        if (!std::isfinite(masses[k])) return LQT_EINVAL;
+        t.off[k] = (int)off;
+        t.coff[k] = (int)coff;
+        t.diag[k] = 4.0 + masses[k];
+        off += (Vk + 255) / 256 * 256;  // each lattice starts on a 256-site boundary
+        coff += Vk;
+        if (off > (1LL << 32) / (12 * 16) - 256) return LQT_EINVAL;
+    }
+    t.off[nlat] = (int)off;
+    t.coff[nlat] = (int)coff;
+    int rc = lqt_create(ctx, dims, masses[0], t_antiperiodic, hip_stream);
+    if (rc != LQT_OK) return rc;
+    lqt_ctx* c = *ctx;
+    c->g.lat = t;
+    c->g.V = (int)off;
+    c->g.canon_sites = coff;
+    c->N = 12 * off;
+    return LQT_OK;
+}
+
 void lqt_destroy(lqt_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     c->timer.destroy();
     delete c;
 }
@@ -92,6 +137,7 @@ int lqt_set_mass(lqt_ctx* c, double mass) {
     if (!c) return LQT_EINVAL;
     if (!std::isfinite(mass)) return LQT_EINVAL;
     c->mass = mass;
+    for (int k = 0; k < c->g.lat.nlat; k++) c->g.lat.diag[k] = 4.0 + mass;
     c->sigma_max = 0;
     return LQT_OK;
 }
@@ -140,7 +186,8 @@ int lqt_solve(lqt_ctx* c, const double* b, double* x, int nrhs, double xi, const
         lqt::SolveOpts o = lqt::make_opts(opts);
         LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net without preconditioner weights");
         const long long n = 12LL * c->g.V;
-        LQT_CHECK(!lqt::has_nonfinite(c, b, (size_t)(2 * n * nrhs)), LQT_ENAN, "right-hand side holds NaN or Inf");
+        const long long ncanon = 12LL * c->g.canon_sites;  // the caller's field length
+        LQT_CHECK(!lqt::has_nonfinite(c, b, (size_t)(2 * ncanon * nrhs)), LQT_ENAN, "right-hand side holds NaN or Inf");
         DBuf bd, xd;
         bd.ensure(sizeof(double2) * (size_t)n * nrhs);
         xd.ensure(sizeof(double2) * (size_t)n * nrhs);

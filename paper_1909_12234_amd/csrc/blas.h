@@ -7,7 +7,13 @@ namespace lqt {
 void norm2_fields(lqt_ctx* c, const double2* x, int nf, double* out_dev);
 void dot_fields(lqt_ctx* c, const double2* x, const double2* y, int nf, double2* out_dev);
 void probes_gen(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double2* out);
-void probe_dots(lqt_ctx* c, uint64_t seed, long long j0, const double2* y, int nprobes, double2* out_dev);
+// z_j^T y_j for nprobes fields; per_lattice: out_dev[j * nlat + k] over the sites of lattice k
+void probe_dots(lqt_ctx* c, uint64_t seed, long long j0, const double2* y, int nprobes, double2* out_dev,
+                bool per_lattice = false);
+// out_dev[f * nlat + k] = |x_f|^2 over the sites of lattice k
+void norm2_lattices(lqt_ctx* c, const double2* x, int nf, double* out_dev);
+// out_dev[f * nlat + k] = sum of part[f * nparts + q] over the 256-site blocks q of lattice k
+void sum_partials_lattices(lqt_ctx* c, const double* part, int nparts, int nf, double* out_dev);
 void gamma5_fields(lqt_ctx* c, double2* x, int nf);
 bool has_nonfinite(lqt_ctx* c, const double* p, size_t n);
 

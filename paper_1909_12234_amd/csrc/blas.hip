@@ -1,9 +1,11 @@
 // Field-level BLAS on FP64 device-layout fields, and the Rademacher probes.
 //
-// Probes (Section 1: real +-1 entries, E[z_i z_j] = delta_ij): entry i (global index
-// 12*site + 3*spin + colour) of probe j is 1 - 2*bit63(h(seed ^ h(j ^ h(i)))) with h the
-// SplitMix64 output function of Steele, Lea and Flood (OOPSLA 2014).  They are generated
-// wherever they are consumed instead of being stored.
+// Probes (Section 1: real +-1 entries, E[z_i z_j] = delta_ij): entry i (index
+// 12*site + 3*spin + colour within its lattice) of probe j is 1 - 2*bit63(h(seed ^ h(j ^
+// h(i)))) with h the SplitMix64 output function of Steele, Lea and Flood (OOPSLA 2014).  They
+// are generated wherever they are consumed instead of being stored; every lattice of a
+// multi-lattice context gets the probes a context of that lattice alone would, and padding
+// sites get zeros.
 #include "lqt_internal.h"
 #include "blas.h"
 
@@ -63,34 +65,41 @@ void norm2_fields(lqt_ctx* c, const double2* x, int nf, double* out_dev) {
 }
 
 // out[j] = probe (seed, j0 + j) in device layout
-__global__ __launch_bounds__(256) void k_probe_gen(uint64_t seed, long long j0, int V, double2* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_probe_gen(uint64_t seed, long long j0, LatTab t, double2* __restrict__ out) {
+    const int V = t.off[t.nlat];
     const int j = blockIdx.y, s = blockIdx.x * 256 + threadIdx.x;
     if (s >= V) return;
     const long long n = 12LL * V;
+    int k;
+    uint32_t sl;
+    const bool ok = lat_site(t, (uint32_t)s, k, sl);
 #pragma unroll
     for (int c = 0; c < 12; c++)
         out[j * n + (long long)c * V + s] =
-            make_double2(probe_entry(seed, (uint64_t)(j0 + j), (uint64_t)(12LL * s + c)), 0.0);
+            make_double2(ok ? probe_entry(seed, (uint64_t)(j0 + j), (uint64_t)(12LL * sl + c)) : 0.0, 0.0);
 }
 
 void probes_gen(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double2* out) {
     if (nprobes <= 0) return;
-    hipLaunchKernelGGL(k_probe_gen, dim3((c->g.V + 255) / 256, nprobes), dim3(256), 0, c->stream, seed, j0, c->g.V,
+    hipLaunchKernelGGL(k_probe_gen, dim3((c->g.V + 255) / 256, nprobes), dim3(256), 0, c->stream, seed, j0, c->g.lat,
                        out);
     LQT_HIP(hipGetLastError());
 }
 
 // partial sums of z_j^T y_j (complex) per (block, probe): y device layout FP64
 __global__ __launch_bounds__(256) void k_probe_dot_part(uint64_t seed, long long j0, const double2* __restrict__ y,
-                                                        int V, double2* __restrict__ part) {
+                                                        LatTab t, double2* __restrict__ part) {
     __shared__ double red[4][2];
+    const int V = t.off[t.nlat];
     const int j = blockIdx.y, s = blockIdx.x * 256 + threadIdx.x;
     const long long n = 12LL * V;
     double a = 0, b = 0;
-    if (s < V)
+    int k;
+    uint32_t sl;
+    if (s < V && lat_site(t, (uint32_t)s, k, sl))
 #pragma unroll
         for (int c = 0; c < 12; c++) {
-            double z = probe_entry(seed, (uint64_t)(j0 + j), (uint64_t)(12LL * s + c));
+            double z = probe_entry(seed, (uint64_t)(j0 + j), (uint64_t)(12LL * sl + c));
             double2 v = y[j * n + (long long)c * V + s];
             a += z * v.x;
             b += z * v.y;
@@ -120,14 +129,64 @@ __global__ void k_sum_rows2(const double2* __restrict__ part, int nparts, double
     if (threadIdx.x == 0) out[f] = make_double2(a, b);
 }
 
-void probe_dots(lqt_ctx* c, uint64_t seed, long long j0, const double2* y, int nprobes, double2* out_dev) {
+// out[f * nlat + k] = sum of the block partials of row f over the blocks of lattice k
+// (256-site blocks; lattices start on block boundaries)
+template <typename T>
+__global__ void k_sum_rows_lat(const T* __restrict__ part, int nparts, LatTab t, T* __restrict__ out) {
+    const int f = blockIdx.x, k = blockIdx.y;
+    const int b0 = t.off[k] / 256, b1 = (t.off[k + 1] + 255) / 256;
+    double a = 0, b = 0;
+    for (int q = b0 + threadIdx.x; q < b1 && q < nparts; q += 64) {
+        if constexpr (sizeof(T) == 16) {
+            const double2 p = part[(long long)f * nparts + q];
+            a += p.x;
+            b += p.y;
+        } else {
+            a += part[(long long)f * nparts + q];
+        }
+    }
+    a = wsum(a);
+    b = wsum(b);
+    if (threadIdx.x == 0) {
+        if constexpr (sizeof(T) == 16)
+            out[f * t.nlat + k] = make_double2(a, b);
+        else
+            out[f * t.nlat + k] = a;
+    }
+}
+
+void probe_dots(lqt_ctx* c, uint64_t seed, long long j0, const double2* y, int nprobes, double2* out_dev,
+                bool per_lattice) {
     if (nprobes <= 0) return;
     const int nsb = (c->g.V + 255) / 256;
     c->scratch[6].ensure(sizeof(double2) * (size_t)nsb * nprobes);
-    hipLaunchKernelGGL(k_probe_dot_part, dim3(nsb, nprobes), dim3(256), 0, c->stream, seed, j0, y, c->g.V,
+    hipLaunchKernelGGL(k_probe_dot_part, dim3(nsb, nprobes), dim3(256), 0, c->stream, seed, j0, y, c->g.lat,
                        c->scratch[6].as<double2>());
     LQT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_rows2, dim3(nprobes), dim3(64), 0, c->stream, c->scratch[6].as<double2>(), nsb, out_dev);
+    if (per_lattice)
+        hipLaunchKernelGGL(k_sum_rows_lat<double2>, dim3(nprobes, c->g.lat.nlat), dim3(64), 0, c->stream,
+                           c->scratch[6].as<double2>(), nsb, c->g.lat, out_dev);
+    else
+        hipLaunchKernelGGL(k_sum_rows2, dim3(nprobes), dim3(64), 0, c->stream, c->scratch[6].as<double2>(), nsb,
+                           out_dev);
+    LQT_HIP(hipGetLastError());
+}
+
+void sum_partials_lattices(lqt_ctx* c, const double* part, int nparts, int nf, double* out_dev) {
+    if (nf <= 0) return;
+    hipLaunchKernelGGL(k_sum_rows_lat<double>, dim3(nf, c->g.lat.nlat), dim3(64), 0, c->stream, part, nparts,
+                       c->g.lat, out_dev);
+    LQT_HIP(hipGetLastError());
+}
+
+void norm2_lattices(lqt_ctx* c, const double2* x, int nf, double* out_dev) {
+    if (nf <= 0) return;
+    const int nsb = (c->g.V + 255) / 256;
+    c->scratch[6].ensure(sizeof(double) * (size_t)nsb * nf);
+    hipLaunchKernelGGL(k_norm2_part, dim3(nsb, nf), dim3(256), 0, c->stream, x, c->g.V, c->scratch[6].as<double>());
+    LQT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows_lat<double>, dim3(nf, c->g.lat.nlat), dim3(64), 0, c->stream,
+                       c->scratch[6].as<double>(), nsb, c->g.lat, out_dev);
     LQT_HIP(hipGetLastError());
 }
 

@@ -15,6 +15,7 @@
 //
 // One thread owns one site and R right-hand sides: each link is loaded once and applied
 // to R spinors.  Algorithmic traffic per site: 72 link reals + R*(24 in + 24 out) reals.
+#include "blas.h"
 #include "lqt_internal.h"
 
 namespace lqt {
@@ -41,6 +42,18 @@ __device__ __forceinline__ void st_c(double2* p, cpx<C> v) {
 template <typename C, typename S>
 __device__ __forceinline__ void st_c(S* p, cpx<C> v) {
     io<S>::st(p, make_float2((float)v.x, (float)v.y));
+}
+
+// element i of a field through a wave-uniform base and a 32-bit byte offset: the load
+// forms the address itself (scalar base + vector offset), no 64-bit vector arithmetic.
+// Valid while 12 V sizeof(S) < 4 GiB (checked when a context is created).
+template <typename S>
+__device__ __forceinline__ const S* at(const S* base, uint32_t i) {
+    return (const S*)((const char*)base + i * (uint32_t)sizeof(S));
+}
+template <typename S>
+__device__ __forceinline__ S* at(S* base, uint32_t i) {
+    return (S*)((char*)base + i * (uint32_t)sizeof(S));
 }
 
 // a + s*i*b  (s = +1 or -1)
@@ -98,26 +111,38 @@ __device__ __forceinline__ void rebuild_add(cpx<C> acc[12], const cpx<C> u0[3], 
     }
 }
 
+__device__ __forceinline__ float fm(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fm(double a, double b, double c) { return fma(a, b, c); }
+
+// o = l h with l = U (forward) or U^+ (backward), written as fused multiply-add chains
 template <bool DAGGER_LINK, typename C>
 __device__ __forceinline__ void su3_mul(const cpx<C> u[9], const cpx<C> h[3], cpx<C> o[3]) {
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        C re = 0, im = 0;
+        // l_b = U[a][b], or conj(U[b][a]) for the dagger
+        const cpx<C> l0 = DAGGER_LINK ? cpx<C>{u[a].x, -u[a].y} : u[3 * a];
+        C re = l0.x * h[0].x, im = l0.x * h[0].y;
+        re = fm(-l0.y, h[0].y, re);
+        im = fm(l0.y, h[0].x, im);
 #pragma unroll
-        for (int b = 0; b < 3; b++) {
-            cpx<C> l = DAGGER_LINK ? cpx<C>{u[3 * b + a].x, -u[3 * b + a].y} : u[3 * a + b];
-            re += l.x * h[b].x - l.y * h[b].y;
-            im += l.x * h[b].y + l.y * h[b].x;
+        for (int b = 1; b < 3; b++) {
+            const cpx<C> l = DAGGER_LINK ? cpx<C>{u[3 * b + a].x, -u[3 * b + a].y} : u[3 * a + b];
+            re = fm(l.x, h[b].x, re);
+            re = fm(-l.y, h[b].y, re);
+            im = fm(l.x, h[b].y, im);
+            im = fm(l.y, h[b].x, im);
         }
         o[a] = {re, im};
     }
 }
 
+// Fields are read through a wave-uniform base pointer (one right-hand side) and a 32-bit
+// element offset, so the address is formed by the load itself (no 64-bit vector adds).
 template <typename S, typename C>
-__device__ __forceinline__ void load_spinor(const S* __restrict__ f, int V, int s, bool g5, cpx<C> p[12]) {
+__device__ __forceinline__ void load_spinor(const S* __restrict__ f, uint32_t V, uint32_t s, bool g5, cpx<C> p[12]) {
 #pragma unroll
     for (int c = 0; c < 12; c++) {
-        p[c] = ld_c<C>(f + (long long)c * V + s);
+        p[c] = ld_c<C>(at(f, c * V + s));
         if (g5 && c >= 6) {
             p[c].x = -p[c].x;
             p[c].y = -p[c].y;
@@ -125,36 +150,38 @@ __device__ __forceinline__ void load_spinor(const S* __restrict__ f, int V, int 
     }
 }
 
+// Um = the links of direction mu ([ab][V] block, uniform base)
 template <typename S, typename C>
-__device__ __forceinline__ void load_link(const S* __restrict__ U, int V, int mu, int s, cpx<C> u[9]) {
+__device__ __forceinline__ void load_link(const S* __restrict__ Um, uint32_t V, uint32_t s, cpx<C> u[9]) {
 #pragma unroll
-    for (int i = 0; i < 9; i++) u[i] = ld_c<C>(U + (long long)(mu * 9 + i) * V + s);
+    for (int i = 0; i < 9; i++) u[i] = ld_c<C>(at(Um, i * V + s));
 }
 
 // hop for one direction: acc[r] += (1 - g) U(x) psi(x+mu) + (1 + g) U(x-mu)^+ psi(x-mu)
 // (projector signs swap for the adjoint)
 template <int MU, bool DAG, int R, typename S, typename C>
-__device__ __forceinline__ void hop_dir(const S* __restrict__ U, const S* __restrict__ in, long long in_stride, int V,
-                                        int s, int sf, int sb, int nr, bool g5in, cpx<C> acc[R][12]) {
+__device__ __forceinline__ void hop_dir(const S* __restrict__ U, const S* const inb[R], uint32_t V, uint32_t s,
+                                        uint32_t sf, uint32_t sb, int nr, bool g5in, cpx<C> acc[R][12]) {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     cpx<C> u[9], p[12], h0[3], h1[3], o0[3], o1[3];
-    load_link<S, C>(U, V, MU, s, u);
+    const S* Um = U + (long long)MU * 9 * V;
+    load_link<S, C>(Um, V, s, u);
 #pragma unroll
     for (int r = 0; r < R; r++) {
         if (r < nr) {
-            load_spinor<S, C>(in + r * in_stride, V, sf, g5in, p);
+            load_spinor<S, C>(inb[r], V, sf, g5in, p);
             project<MU, SF>(p, h0, h1);
             su3_mul<false>(u, h0, o0);
             su3_mul<false>(u, h1, o1);
             rebuild_add<MU, SF>(acc[r], o0, o1);
         }
     }
-    load_link<S, C>(U, V, MU, sb, u);
+    load_link<S, C>(Um, V, sb, u);
 #pragma unroll
     for (int r = 0; r < R; r++) {
         if (r < nr) {
-            load_spinor<S, C>(in + r * in_stride, V, sb, g5in, p);
+            load_spinor<S, C>(inb[r], V, sb, g5in, p);
             project<MU, SB>(p, h0, h1);
             su3_mul<true>(u, h0, o0);
             su3_mul<true>(u, h1, o1);
@@ -164,22 +191,25 @@ __device__ __forceinline__ void hop_dir(const S* __restrict__ U, const S* __rest
 }
 
 // EPI 0: out = op(in).  EPI 1 (FP64 only): out = b - A in, with per-block partial |out|^2.
-template <typename S, int R, bool DAG, int EPI>
+// Right-hand side r of a group is field act[r0 + r] (act may be null: r0 + r) of in and b,
+// and field r0 + r of out.  Sites of the lattice table tab; padding sites get zeros.
+template <typename S, int R, int OPK, int EPI>
 __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S* __restrict__ in, S* __restrict__ out,
-                                                const S* __restrict__ bvec, double* __restrict__ part, const int* act,
-                                                int L0, int L1, int L2, int L3, typename acc_of<S>::type diag, int nrhs,
-                                                long long in_stride, long long out_stride, int g5in, int g5out,
-                                                int chunk) {
+                                                const S* __restrict__ bvec, double* __restrict__ part,
+                                                const int* __restrict__ act, LatTab tab, int nrhs, long long in_stride,
+                                                long long out_stride, int chunk) {
+    constexpr bool DAG = OPK == LQT_A_DAG;
+    constexpr bool g5in = OPK == LQT_A_G5, g5out = OPK == LQT_G5_A;
     using C = typename acc_of<S>::type;
-    const int V = L0 * L1 * L2 * L3;
-    const int nsb = (V + blockDim.x - 1) / blockDim.x;
+    const uint32_t V = (uint32_t)tab.off[tab.nlat];
+    const int nsb = (int)((V + blockDim.x - 1) / blockDim.x);
     const int ngrp = (nrhs + R - 1) / R;
     const int lb = xcd_block(nsb * ngrp);
     if (lb < 0) return;
     // Block order.  chunk = 0: site block major (a thread's R links serve every group in
-    // turn).  chunk > 0: the lattice is cut into chunks of `chunk` site blocks (whole time
-    // slices for the usual sizes); each chunk is swept once per right-hand-side group, so
-    // the +-t and +-z neighbours of a block are read while they are still in the XCD's L2.
+    // turn).  chunk > 0: the sites are cut into chunks of `chunk` site blocks; each chunk is
+    // swept once per right-hand-side group, so the +-t and +-z neighbours of a block are
+    // read while they are still in the XCD's L2.
     int sblk, grp;
     if (chunk <= 0) {
         sblk = lb / ngrp;
@@ -191,63 +221,82 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
         grp = rem / cs;
         sblk = ch * chunk + (rem - grp * cs);
     }
-    const int s = sblk * blockDim.x + threadIdx.x;
+    // lattice of this block (uniform: blocks never straddle lattices)
+    const uint32_t s0 = (uint32_t)sblk * blockDim.x;
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < LQT_MAXLAT; i++)
+        if (i < tab.nlat && s0 >= (uint32_t)tab.off[i]) k = i;
+    const int L0 = tab.L[k][0], L1 = tab.L[k][1], L2 = tab.L[k][2], L3 = tab.L[k][3];
+    const uint32_t base = (uint32_t)tab.off[k];
+    const uint32_t Vk = (uint32_t)(L0 * L1 * L2 * L3);
+    const C diag = (C)tab.diag[k];
+    const uint32_t s = s0 + threadIdx.x;
     const int r0 = grp * R;
     const int nr = min(R, nrhs - r0);
+    const S* inb[R];
+    const S* bb[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int rr = min(r0 + r, nrhs - 1);
+        const long long f = act ? act[rr] : rr;
+        inb[r] = in + f * in_stride;
+        bb[r] = (EPI == 1) ? bvec + f * in_stride : nullptr;
+    }
     double nrm[R];
 #pragma unroll
     for (int r = 0; r < R; r++) nrm[r] = 0;
     if (s < V) {
-        const int x = s % L0;
-        const int y = (s / L0) % L1;
-        const int z = (s / (L0 * L1)) % L2;
-        const int t = s / (L0 * L1 * L2);
-        const int s1 = L0, s2 = L0 * L1, s3 = L0 * L1 * L2;
-        const int xf = (x == L0 - 1) ? s - (L0 - 1) : s + 1;
-        const int xb = (x == 0) ? s + (L0 - 1) : s - 1;
-        const int yf = (y == L1 - 1) ? s - (L1 - 1) * s1 : s + s1;
-        const int yb = (y == 0) ? s + (L1 - 1) * s1 : s - s1;
-        const int zf = (z == L2 - 1) ? s - (L2 - 1) * s2 : s + s2;
-        const int zb = (z == 0) ? s + (L2 - 1) * s2 : s - s2;
-        const int tf = (t == L3 - 1) ? s - (L3 - 1) * s3 : s + s3;
-        const int tb = (t == 0) ? s + (L3 - 1) * s3 : s - s3;
-
-        const long long istr = in_stride;
-        const S* inr = in + (long long)(act ? act[r0] : r0) * istr;
-
+        const uint32_t sl = s - base;  // site within lattice k
         cpx<C> acc[R][12];
 #pragma unroll
         for (int r = 0; r < R; r++)
 #pragma unroll
             for (int c = 0; c < 12; c++) acc[r][c] = {0, 0};
-
-        const bool g5 = g5in != 0;
-        hop_dir<0, DAG, R, S, C>(U, inr, istr, V, s, xf, xb, nr, g5, acc);
-        hop_dir<1, DAG, R, S, C>(U, inr, istr, V, s, yf, yb, nr, g5, acc);
-        hop_dir<2, DAG, R, S, C>(U, inr, istr, V, s, zf, zb, nr, g5, acc);
-        hop_dir<3, DAG, R, S, C>(U, inr, istr, V, s, tf, tb, nr, g5, acc);
-
+        const bool pad = sl >= Vk;
+        if (!pad) {
+            const int x = sl % L0;
+            const int y = (sl / L0) % L1;
+            const int z = (sl / (L0 * L1)) % L2;
+            const int t = sl / (L0 * L1 * L2);
+            const int s1 = L0, s2 = L0 * L1, s3 = L0 * L1 * L2;
+            const uint32_t xf = (x == L0 - 1) ? s - (L0 - 1) : s + 1;
+            const uint32_t xb = (x == 0) ? s + (L0 - 1) : s - 1;
+            const uint32_t yf = (y == L1 - 1) ? s - (L1 - 1) * s1 : s + s1;
+            const uint32_t yb = (y == 0) ? s + (L1 - 1) * s1 : s - s1;
+            const uint32_t zf = (z == L2 - 1) ? s - (L2 - 1) * s2 : s + s2;
+            const uint32_t zb = (z == 0) ? s + (L2 - 1) * s2 : s - s2;
+            const uint32_t tf = (t == L3 - 1) ? s - (L3 - 1) * s3 : s + s3;
+            const uint32_t tb = (t == 0) ? s + (L3 - 1) * s3 : s - s3;
+            hop_dir<0, DAG, R, S, C>(U, inb, V, s, xf, xb, nr, g5in, acc);
+            hop_dir<1, DAG, R, S, C>(U, inb, V, s, yf, yb, nr, g5in, acc);
+            hop_dir<2, DAG, R, S, C>(U, inb, V, s, zf, zb, nr, g5in, acc);
+            hop_dir<3, DAG, R, S, C>(U, inb, V, s, tf, tb, nr, g5in, acc);
+        }
 #pragma unroll
         for (int r = 0; r < R; r++) {
             if (r < nr) {
                 cpx<C> p[12];
-                load_spinor<S, C>(inr + r * istr, V, s, g5, p);
-                S* o = out + (long long)(r0 + r) * out_stride;
+                if (!pad)
+                    load_spinor<S, C>(inb[r], V, s, g5in, p);
+                else
+#pragma unroll
+                    for (int c = 0; c < 12; c++) p[c] = {0, 0};
+                S* o = out + (long long)(r0 + r) * out_stride;  // uniform
 #pragma unroll
                 for (int c = 0; c < 12; c++) {
-                    cpx<C> v = {diag * p[c].x - (C)0.5 * acc[r][c].x, diag * p[c].y - (C)0.5 * acc[r][c].y};
+                    cpx<C> v = {fm(diag, p[c].x, (C)-0.5 * acc[r][c].x), fm(diag, p[c].y, (C)-0.5 * acc[r][c].y)};
                     if (g5out && c >= 6) {
                         v.x = -v.x;
                         v.y = -v.y;
                     }
                     if (EPI == 1) {
-                        cpx<C> bb = ld_c<C>(bvec + (long long)(act ? act[r0 + r] : r0 + r) * in_stride +
-                                            (long long)c * V + s);
-                        v.x = bb.x - v.x;
-                        v.y = bb.y - v.y;
+                        const cpx<C> b = ld_c<C>(at(bb[r], c * V + s));
+                        v.x = b.x - v.x;
+                        v.y = b.y - v.y;
                         nrm[r] += (double)v.x * v.x + (double)v.y * v.y;
                     }
-                    st_c<C>(o + (long long)c * V + s, v);
+                    st_c<C>(at(o, c * V + s), v);
                 }
             }
         }
@@ -273,20 +322,19 @@ template <typename S, int R>
 static void launch_R(lqt_ctx* c, int op, const S* U, const S* in, S* out, int nrhs, long long is, long long os,
                      int bs, int chunk) {
     const Geom& g = c->g;
-    using C = typename acc_of<S>::type;
     int nsb = (g.V + bs - 1) / bs;
     int ngrp = (nrhs + R - 1) / R;
     int nl = nsb * ngrp;
-    C diag = (C)(4.0 + c->mass);
-    int g5in = (op == LQT_A_G5), g5out = (op == LQT_G5_A);
-    if (op == LQT_A_DAG)
-        hipLaunchKernelGGL((k_dslash<S, R, true, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,
-                           (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.L[0], g.L[1], g.L[2], g.L[3],
-                           diag, nrhs, is, os, 0, 0, chunk);
-    else
-        hipLaunchKernelGGL((k_dslash<S, R, false, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,
-                           (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.L[0], g.L[1], g.L[2], g.L[3],
-                           diag, nrhs, is, os, g5in, g5out, chunk);
+#define LQT_DSLASH_OP(OPK)                                                                                   \
+    hipLaunchKernelGGL((k_dslash<S, R, OPK, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,        \
+                       (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.lat, nrhs, is, os, chunk)
+    switch (op) {
+        case LQT_A_DAG: LQT_DSLASH_OP(LQT_A_DAG); break;
+        case LQT_A_G5: LQT_DSLASH_OP(LQT_A_G5); break;
+        case LQT_G5_A: LQT_DSLASH_OP(LQT_G5_A); break;
+        default: LQT_DSLASH_OP(LQT_A); break;
+    }
+#undef LQT_DSLASH_OP
     LQT_HIP(hipGetLastError());
 }
 
@@ -352,7 +400,7 @@ void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, l
     c->timer.begin(c->stream, KT_DSLASH);
     dslash_cfg(c, prec, op, in, out, nrhs, in_stride, out_stride, t);
     const double b = (double)storage_bytes(prec) / 2;  // bytes per real
-    c->timer.end(c->stream, (double)c->g.V * (72.0 * b + 48.0 * b * nrhs));
+    c->timer.end(c->stream, (double)c->g.canon_sites * (72.0 * b + 48.0 * b * nrhs));
 }
 
 // Autotuner: time every (rhs per thread, block size, chunk) candidate on scratch fields and keep
@@ -415,7 +463,7 @@ __global__ void k_sum_partials(const double* __restrict__ part, int nparts, int 
 }
 
 void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, double* rnorm2, int nrhs,
-                const int* act) {
+                const int* act, double* rnorm2_lat) {
     if (nrhs <= 0) return;
     const Geom& g = c->g;
     const int bs = 256;
@@ -424,14 +472,14 @@ void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, doub
     c->scratch[7].ensure(sizeof(double) * (size_t)nsb * nrhs);
     double* part = c->scratch[7].as<double>();
     c->timer.begin(c->stream, KT_RESID);
-    hipLaunchKernelGGL((k_dslash<double2, 1, false, 1>), dim3(xcd_grid(nsb * nrhs)), dim3(bs), 0, c->stream,
-                       c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.L[0], g.L[1], g.L[2], g.L[3],
-                       4.0 + c->mass, nrhs, n, n, 0, 0, 0);
+    hipLaunchKernelGGL((k_dslash<double2, 1, LQT_A, 1>), dim3(xcd_grid(nsb * nrhs)), dim3(bs), 0, c->stream,
+                       c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.lat, nrhs, n, n, 0);
     LQT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, c->stream, part, nsb, nrhs, rnorm2);
     LQT_HIP(hipGetLastError());
+    if (rnorm2_lat) sum_partials_lattices(c, part, nsb, nrhs, rnorm2_lat);
     // links once; x, b read and r written per right-hand side (FP64)
-    c->timer.end(c->stream, (double)g.V * (72.0 * 8 + 72.0 * 8 * nrhs));
+    c->timer.end(c->stream, (double)g.canon_sites * (72.0 * 8 + 72.0 * 8 * nrhs));
 }
 
 }  // namespace lqt

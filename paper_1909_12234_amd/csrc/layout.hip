@@ -4,17 +4,26 @@
 
 namespace lqt {
 
-// One thread per link: check U^+U = 1 and det U = 1, fold the antiperiodic sign into the
-// last time slice, scatter into [mu][ab][V] for every storage precision.
-__global__ void k_gauge_ingest(const double2* __restrict__ canon, int V, int slice, int Lt, int antiperiodic,
+// One thread per link of the canonical field (lattices one after the other, each
+// [site][mu][a][b]): check U^+U = 1 and det U = 1, fold the antiperiodic sign into the last
+// time slice of its lattice, scatter into [mu][ab][V] at the lattice's device sites for
+// every storage precision.
+__global__ void k_gauge_ingest(const double2* __restrict__ canon, LatTab t, long long nlinks, int antiperiodic,
                                double2* __restrict__ u64, float2* __restrict__ u32, h2* __restrict__ u16,
                                b2* __restrict__ ubf, double* __restrict__ err_unit, double* __restrict__ err_det) {
     __shared__ double s_u[256], s_d[256];
     int tid = threadIdx.x;
-    long long idx = (long long)blockIdx.x * blockDim.x + tid;  // link index = site*4 + mu
+    long long idx = (long long)blockIdx.x * blockDim.x + tid;  // link index = canonical site*4 + mu
     double eu = 0, ed = 0;
-    if (idx < 4LL * V) {
-        int site = (int)(idx >> 2), mu = (int)(idx & 3);
+    if (idx < nlinks) {
+        const int csite = (int)(idx >> 2), mu = (int)(idx & 3);
+        int k = 0;
+        for (int i = 1; i < t.nlat; i++)
+            if (csite >= t.coff[i]) k = i;
+        const int sl = csite - t.coff[k];
+        const int V = t.off[t.nlat];
+        const int site = t.off[k] + sl;
+        const int Lt = t.L[k][3], slice = t.L[k][0] * t.L[k][1] * t.L[k][2];
         double2 m[9];
         for (int i = 0; i < 9; i++) m[i] = canon[idx * 9 + i];
         // U^+ U - 1
@@ -41,7 +50,7 @@ __global__ void k_gauge_ingest(const double2* __restrict__ canon, int V, int sli
         d.y += t2.y;
         ed = sqrt((d.x - 1.0) * (d.x - 1.0) + d.y * d.y);
         if (!(eu == eu) || !(ed == ed)) eu = ed = 1e300;  // NaN -> reject
-        double sgn = (antiperiodic && (site / slice) == Lt - 1 && mu == 3) ? -1.0 : 1.0;
+        double sgn = (antiperiodic && (sl / slice) == Lt - 1 && mu == 3) ? -1.0 : 1.0;
         for (int i = 0; i < 9; i++) {
             double2 v = make_double2(sgn * m[i].x, sgn * m[i].y);
             long long o = (long long)(mu * 9 + i) * V + site;
@@ -70,24 +79,31 @@ __global__ void k_gauge_ingest(const double2* __restrict__ canon, int V, int sli
 
 void gauge_upload(lqt_ctx* c, const double* links, int on_device, double* max_unit_err, double* max_det_err) {
     const int V = c->g.V;
-    const size_t nlink = 4ull * V * 9;
+    const long long nlinks = 4LL * c->g.canon_sites;  // canonical links (no padding)
+    const size_t ncanon = (size_t)nlinks * 9;
+    const size_t ndev = 36ull * V;
     DBuf staging;
     const double2* src = (const double2*)links;
     if (!on_device) {
-        staging.ensure(nlink * sizeof(double2));
-        LQT_HIP(hipMemcpyAsync(staging.p, links, nlink * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+        staging.ensure(ncanon * sizeof(double2));
+        LQT_HIP(hipMemcpyAsync(staging.p, links, ncanon * sizeof(double2), hipMemcpyHostToDevice, c->stream));
         src = staging.as<double2>();
     }
-    c->U[LQT_F64].ensure(nlink * sizeof(double2));
-    c->U[LQT_F32].ensure(nlink * sizeof(float2));
-    c->U[LQT_F16].ensure(nlink * sizeof(h2));
-    c->U[LQT_BF16].ensure(nlink * sizeof(b2));
+    c->U[LQT_F64].ensure(ndev * sizeof(double2));
+    c->U[LQT_F32].ensure(ndev * sizeof(float2));
+    c->U[LQT_F16].ensure(ndev * sizeof(h2));
+    c->U[LQT_BF16].ensure(ndev * sizeof(b2));
+    if (c->g.lat.nlat > 1) {  // padding sites between lattices hold zero links
+        LQT_HIP(hipMemsetAsync(c->U[LQT_F64].p, 0, ndev * sizeof(double2), c->stream));
+        LQT_HIP(hipMemsetAsync(c->U[LQT_F32].p, 0, ndev * sizeof(float2), c->stream));
+        LQT_HIP(hipMemsetAsync(c->U[LQT_F16].p, 0, ndev * sizeof(h2), c->stream));
+        LQT_HIP(hipMemsetAsync(c->U[LQT_BF16].p, 0, ndev * sizeof(b2), c->stream));
+    }
     const int bs = 256;
-    const int nb = (int)((4LL * V + bs - 1) / bs);
+    const int nb = (int)((nlinks + bs - 1) / bs);
     DBuf errs;
     errs.ensure(2ull * nb * sizeof(double));
-    int slice = c->g.L[0] * c->g.L[1] * c->g.L[2];
-    hipLaunchKernelGGL(k_gauge_ingest, dim3(nb), dim3(bs), 0, c->stream, src, V, slice, c->g.L[3], c->antiperiodic,
+    hipLaunchKernelGGL(k_gauge_ingest, dim3(nb), dim3(bs), 0, c->stream, src, c->g.lat, nlinks, c->antiperiodic,
                        c->U[LQT_F64].as<double2>(), c->U[LQT_F32].as<float2>(), c->U[LQT_F16].as<h2>(),
                        c->U[LQT_BF16].as<b2>(), errs.as<double>(), errs.as<double>() + nb);
     LQT_HIP(hipGetLastError());
@@ -103,44 +119,44 @@ void gauge_upload(lqt_ctx* c, const double* links, int on_device, double* max_un
     *max_det_err = md;
 }
 
-// canonical [rhs][site][12] <-> device [rhs][12][site]; one thread per (site, comp) of one
-// rhs, reading the canonical side in order (consecutive threads = consecutive components).
-__global__ void k_aos_to_soa(const double2* __restrict__ in, double2* __restrict__ out, int V, int nrhs) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long n = 12LL * V;
+// canonical [rhs][lattice][site][12] <-> device [rhs][12][site] (lattice k at device sites
+// off[k]..); one thread per device element, consecutive threads = consecutive sites of one
+// component.  Padding sites are written as zeros on the way in and skipped on the way out.
+template <typename SI, typename SO>
+__global__ void k_to_dev(const SI* __restrict__ in, SO* __restrict__ out, LatTab t, long long ncanon, int nrhs) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long V = t.off[t.nlat], n = 12 * V;
     if (i >= n * nrhs) return;
-    long long r = i / n, e = i - r * n;
-    int site = (int)(e / 12), comp = (int)(e - 12LL * site);
-    out[r * n + (long long)comp * V + site] = in[i];
+    const long long r = i / n, e = i - r * n;
+    const int comp = (int)(e / V);
+    const uint32_t s = (uint32_t)(e - comp * V);
+    int k;
+    uint32_t sl;
+    const bool ok = lat_site(t, s, k, sl);
+    if constexpr (sizeof(SI) == 16 && sizeof(SO) == 16) {
+        out[i] = ok ? in[r * ncanon + 12LL * (t.coff[k] + sl) + comp] : make_double2(0, 0);
+    } else {
+        const float2 v = ok ? in[r * ncanon + 12LL * (t.coff[k] + sl) + comp] : make_float2(0, 0);
+        io<SO>::st(out + i, v);
+    }
 }
 
-__global__ void k_soa_to_aos(const double2* __restrict__ in, double2* __restrict__ out, int V, int nrhs) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long n = 12LL * V;
+template <typename SI, typename SO>
+__global__ void k_from_dev(const SI* __restrict__ in, SO* __restrict__ out, LatTab t, long long ncanon, int nrhs) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long V = t.off[t.nlat], n = 12 * V;
     if (i >= n * nrhs) return;
-    long long r = i / n, e = i - r * n;
-    int site = (int)(e / 12), comp = (int)(e - 12LL * site);
-    out[i] = in[r * n + (long long)comp * V + site];
-}
-
-// float2 <-> storage conversions (FP32 canonical input for the reduced-precision applies)
-template <typename SO>
-__global__ void k_c64_to_soa(const float2* __restrict__ in, SO* __restrict__ out, int V, int nrhs) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long n = 12LL * V;
-    if (i >= n * nrhs) return;
-    long long r = i / n, e = i - r * n;
-    int site = (int)(e / 12), comp = (int)(e - 12LL * site);
-    io<SO>::st(out + r * n + (long long)comp * V + site, in[i]);
-}
-template <typename SI>
-__global__ void k_soa_to_c64(const SI* __restrict__ in, float2* __restrict__ out, int V, int nrhs) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long n = 12LL * V;
-    if (i >= n * nrhs) return;
-    long long r = i / n, e = i - r * n;
-    int site = (int)(e / 12), comp = (int)(e - 12LL * site);
-    out[i] = io<SI>::ld(in + r * n + (long long)comp * V + site);
+    const long long r = i / n, e = i - r * n;
+    const int comp = (int)(e / V);
+    const uint32_t s = (uint32_t)(e - comp * V);
+    int k;
+    uint32_t sl;
+    if (!lat_site(t, s, k, sl)) return;
+    SO* o = out + r * ncanon + 12LL * (t.coff[k] + sl) + comp;
+    if constexpr (sizeof(SI) == 16 && sizeof(SO) == 16)
+        *o = in[i];
+    else
+        *o = io<SI>::ld(in + i);
 }
 
 static inline dim3 grid_for(long long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
@@ -148,15 +164,15 @@ static inline dim3 grid_for(long long n, int bs) { return dim3((unsigned)((n + b
 void to_device_layout(lqt_ctx* c, const double2* canon, double2* dev, int nrhs) {
     long long n = 12LL * c->g.V * nrhs;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_aos_to_soa, grid_for(n, 256), dim3(256), 0, c->stream, canon, dev, c->g.V,
-                       nrhs);
+    hipLaunchKernelGGL((k_to_dev<double2, double2>), grid_for(n, 256), dim3(256), 0, c->stream, canon, dev, c->g.lat,
+                       12LL * c->g.canon_sites, nrhs);
     LQT_HIP(hipGetLastError());
 }
 void from_device_layout(lqt_ctx* c, const double2* dev, double2* canon, int nrhs) {
     long long n = 12LL * c->g.V * nrhs;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_soa_to_aos, grid_for(n, 256), dim3(256), 0, c->stream, dev, canon, c->g.V,
-                       nrhs);
+    hipLaunchKernelGGL((k_from_dev<double2, double2>), grid_for(n, 256), dim3(256), 0, c->stream, dev, canon,
+                       c->g.lat, 12LL * c->g.canon_sites, nrhs);
     LQT_HIP(hipGetLastError());
 }
 
@@ -164,14 +180,16 @@ template <typename S>
 void convert_in_c64(lqt_ctx* c, const float2* canon, S* dev, int nrhs) {
     long long n = 12LL * c->g.V * nrhs;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_c64_to_soa<S>, grid_for(n, 256), dim3(256), 0, c->stream, canon, dev, c->g.V, nrhs);
+    hipLaunchKernelGGL((k_to_dev<float2, S>), grid_for(n, 256), dim3(256), 0, c->stream, canon, dev, c->g.lat,
+                       12LL * c->g.canon_sites, nrhs);
     LQT_HIP(hipGetLastError());
 }
 template <typename S>
 void convert_out_c64(lqt_ctx* c, const S* dev, float2* canon, int nrhs) {
     long long n = 12LL * c->g.V * nrhs;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_soa_to_c64<S>, grid_for(n, 256), dim3(256), 0, c->stream, dev, canon, c->g.V, nrhs);
+    hipLaunchKernelGGL((k_from_dev<S, float2>), grid_for(n, 256), dim3(256), 0, c->stream, dev, canon, c->g.lat,
+                       12LL * c->g.canon_sites, nrhs);
     LQT_HIP(hipGetLastError());
 }
 

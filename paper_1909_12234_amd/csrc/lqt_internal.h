@@ -107,10 +107,40 @@ inline size_t storage_bytes(int prec) {
 }
 
 // ------------------------------------------------------------------ geometry
-struct Geom {
-    int L[4];
-    int V;  // sites (fits 32 bits up to 64^3x128)
+constexpr int LQT_MAXLAT = 8;  // lattices of one context
+
+// Every lattice of a context, as the kernels see it (passed by value).  Lattice k owns the
+// device sites [off[k], off[k] + L0 L1 L2 L3); off[k] is a multiple of 256 so that no site
+// block straddles two lattices, and the sites between lattices are padding (zero fields).
+struct LatTab {
+    int nlat;
+    int L[LQT_MAXLAT][4];
+    int off[LQT_MAXLAT + 1];  // off[nlat] = V, the padded total
+    int coff[LQT_MAXLAT + 1]; // first site of lattice k in the canonical layout (no padding)
+    double diag[LQT_MAXLAT];  // 4 + m_k
 };
+
+struct Geom {
+    int L[4];  // lattice 0 (the only one of a single-lattice context)
+    int V;     // device sites of all lattices with padding
+    LatTab lat;
+    long long canon_sites;  // sites of all lattices without padding (canonical layout)
+};
+
+// lattice of device site s (every lattice of a context, at most LQT_MAXLAT)
+__device__ __forceinline__ int lat_of(const LatTab& t, uint32_t s) {
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < LQT_MAXLAT; i++)
+        if (i < t.nlat && s >= (uint32_t)t.off[i]) k = i;
+    return k;
+}
+// site of s within its lattice k; false for a padding site
+__device__ __forceinline__ bool lat_site(const LatTab& t, uint32_t s, int& k, uint32_t& sl) {
+    k = lat_of(t, s);
+    sl = s - (uint32_t)t.off[k];
+    return sl < (uint32_t)(t.L[k][0] * t.L[k][1] * t.L[k][2] * t.L[k][3]);
+}
 
 // XCD-aware block order: hardware hands consecutive workgroup ids to the 8 XCDs in turn;
 // remapping gives each XCD one contiguous range of logical blocks so neighbouring sites
@@ -206,7 +236,8 @@ enum {
     KT_PROJ = 5,    // deflation projections (FP64 MFMA)
     KT_PR = 6,      // prolongator restrict / prolong
     KT_NET = 7,     // transport-network preconditioner
-    KT_N = 8
+    KT_GRAPH = 8,   // graph-captured inner cycles (every kernel of a cycle in one launch)
+    KT_N = 9
 };
 
 // Non-blocking kernel timer: event pairs recorded around launches on the context stream,
@@ -309,6 +340,7 @@ struct lqt_ctx {
     lqt::HBuf pinned;
     std::map<long long, lqt::Tuned> tuned;
     lqt::KTimer timer;
+    hipStream_t capture_stream = nullptr;  // private stream for graph capture (created on demand)
     lqt::Net net;
     double sigma_max = 0;  // power-iteration estimate, filled on demand
 };
@@ -351,7 +383,9 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen = nullptr);
 // FP64 residual r = b - A x for nrhs fields and squared norms (device layout FP64).
 // act maps slot -> field index (nullptr = identity).
 // act (device, may be null) maps slot -> field index of b and x; r is slot-ordered.
+// r = b - A x (FP64) for the fields act[0..nrhs) of b and x (act null: 0..nrhs), written
+// to r[0..nrhs); rnorm2[q] = |r_q|^2 and, if given, rnorm2_lat[q * nlat + k] over lattice k
 void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, double* rnorm2, int nrhs,
-                const int* act = nullptr);
+                const int* act = nullptr, double* rnorm2_lat = nullptr);
 
 }  // namespace lqt

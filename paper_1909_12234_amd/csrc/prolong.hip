@@ -424,6 +424,7 @@ int lqt_basis_prolongator(lqt_ctx* c, const int block[4], int nv, int k, double 
     if (!c || !out) return LQT_EINVAL;
     *out = nullptr;
     return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
         lqt::check_block(c, block, nv);
         LQT_CHECK(null_xi > 0 && null_xi < 1 && null_maxit >= 1, LQT_EINVAL, "bad null-vector tolerance");
@@ -492,6 +493,7 @@ int lqt_basis_prolongator_from(lqt_ctx* c, const int block[4], int nv, const dou
     if (!c || !out) return LQT_EINVAL;
     *out = nullptr;
     return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(c->have_gauge || k == 0, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
         lqt::check_block(c, block, nv);
         LQT_CHECK(d_w, LQT_EINVAL, "null prolongator");

@@ -444,6 +444,7 @@ int lqt_precond_get(lqt_ctx* c, void* w, size_t nbytes) {
 int lqt_precond_apply(lqt_ctx* c, const double* in, double* out, int nrhs) {
     if (!c) return LQT_EINVAL;
     return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
         LQT_CHECK(c->net.set, LQT_ESTATE, "no preconditioner weights");
         LQT_CHECK(nrhs >= 0 && (nrhs == 0 || (in && out)), LQT_EINVAL, "bad fields");
@@ -462,6 +463,7 @@ int lqt_precond_apply(lqt_ctx* c, const double* in, double* out, int nrhs) {
 int lqt_precond_loss_grad(lqt_ctx* c, const double* e, int npairs, double* loss, double* grad) {
     if (!c) return LQT_EINVAL;
     return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
         LQT_CHECK(c->net.set, LQT_ESTATE, "no preconditioner weights");
         LQT_CHECK(npairs >= 1 && e && loss && grad, LQT_EINVAL, "bad arguments");
@@ -487,6 +489,7 @@ int lqt_precond_loss_grad(lqt_ctx* c, const double* e, int npairs, double* loss,
 int lqt_precond_train(lqt_ctx* c, int npairs, uint64_t seed, const lqt_train_opts* opts, double* final_loss) {
     if (!c) return LQT_EINVAL;
     return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
         LQT_CHECK(npairs >= 1, LQT_EINVAL, "npairs must be >= 1");
         LQT_CHECK(!opts || (opts->epochs >= 0 && opts->batch >= 0 && opts->lr >= 0 && opts->pair_xi >= 0 &&

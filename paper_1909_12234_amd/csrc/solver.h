@@ -14,6 +14,7 @@ struct SolveOpts {
     double inner_tol = 0.0;
     int verbose = 0;
     int outer_maxit = 60;
+    int graph = 0;
 };
 
 SolveOpts make_opts(const lqt_solver_opts* u);

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
 
 #include "blas.h"
 #include "krylov.h"
@@ -102,8 +103,10 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     StateBuf sb;
     sb.carve(stb, nb, m);
     partb.ensure(sizeof(double2) * (size_t)nb * nsb * (m + 2));
+    const int nlat = c->g.lat.nlat;
+    const bool multi = nlat > 1;  // several lattices: every lattice block must meet xi
     partnb.ensure(sizeof(double) * (size_t)nb * nsb + sizeof(double) * 2 * nb + sizeof(int) * 2 * nb +
-                  sizeof(double) * nb + 1024);
+                  sizeof(double) * nb + sizeof(double) * (size_t)nb * nlat + 1024);
 
     double2* r = rb.as<double2>();
     char* extra = (char*)partnb.p + sizeof(double) * (size_t)nb * nsb;
@@ -112,13 +115,15 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     int* act_d = (int*)(bn2 + nb);
     int* src_d = act_d + nb;
     double* tgt_d = (double*)(((uintptr_t)(src_d + nb) + 7) & ~uintptr_t(7));
+    double* rn2l = tgt_d + nb;  // [slot][lattice]
     double* partn = partnb.as<double>();
     double2* part = partb.as<double2>();
     void* basis = basisb.p;
 
-    c->pinned.ensure(sizeof(double) * 4 * (size_t)nb + 64);
+    c->pinned.ensure(sizeof(double) * (4 + (size_t)nlat) * nb + 64);
     double* h_rn2 = c->pinned.as<double>();
     int* h_flags = (int*)(h_rn2 + nb);
+    double* h_rn2l = h_rn2 + 2 * (size_t)nb;
 
     std::vector<double> bnorm(nb);
     c->timer.begin(c->stream, KT_KRYLOV);
@@ -128,7 +133,24 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     LQT_HIP(hipMemcpyAsync(h_rn2, bn2, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
     LQT_HIP(hipStreamSynchronize(c->stream));
     for (int i = 0; i < nb; i++) bnorm[i] = std::sqrt(h_rn2[i]);
+    std::vector<double> bnl;  // |b| per (system, lattice)
+    if (multi) {
+        norm2_lattices(c, b, nb, rn2l);
+        bnl.resize((size_t)nb * nlat);
+        LQT_HIP(hipMemcpyAsync(bnl.data(), rn2l, sizeof(double) * bnl.size(), hipMemcpyDeviceToHost, c->stream));
+        LQT_HIP(hipStreamSynchronize(c->stream));
+        for (double& v : bnl) v = std::sqrt(v);
+    }
 
+    // graph-captured cycles per active count, destroyed when the batch is done
+    struct Graphs {
+        std::map<int, hipGraphExec_t> m;
+        hipGraphExec_t& operator[](int k) { return m[k]; }
+        ~Graphs() {
+            for (auto& kv : m)
+                if (kv.second) (void)hipGraphExecDestroy(kv.second);
+        }
+    } graphs;
     std::vector<int> act(nb), its(nb, 0), cyc(nb, 0), done(nb, 0);
     std::vector<double> rel(nb, 1.0);
     for (int i = 0; i < nb; i++) act[i] = i;
@@ -139,8 +161,10 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     while (!act.empty()) {
         const int na = (int)act.size();
         LQT_HIP(hipMemcpyAsync(act_d, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
-        residual64(c, b, x, r, rn2, na, act_d);
+        residual64(c, b, x, r, rn2, na, act_d, multi ? rn2l : nullptr);
         LQT_HIP(hipMemcpyAsync(h_rn2, rn2, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream));
+        if (multi)
+            LQT_HIP(hipMemcpyAsync(h_rn2l, rn2l, sizeof(double) * na * nlat, hipMemcpyDeviceToHost, c->stream));
         LQT_HIP(hipStreamSynchronize(c->stream));
         std::vector<int> nact, src;
         std::vector<double> tgt;
@@ -149,6 +173,20 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
             cyc[i]++;
             double rr = std::sqrt(h_rn2[k]);
             rel[i] = bnorm[i] > 0 ? rr / bnorm[i] : 0.0;
+            double bmin = bnorm[i];  // the cycle target must serve the smallest lattice block
+            if (multi) {
+                double worst = 0;
+                for (int l = 0; l < nlat; l++) {
+                    const double bl = bnl[(size_t)i * nlat + l], rl = std::sqrt(h_rn2l[(size_t)k * nlat + l]);
+                    if (bl > 0) {
+                        worst = std::max(worst, rl / bl);
+                        bmin = std::min(bmin, bl);
+                    } else if (!(rl == rl)) {
+                        worst = rl;
+                    }
+                }
+                rel[i] = (rr == rr) ? worst : rr;
+            }
             if (!(rel[i] == rel[i])) {
                 done[i] = 1;
                 nfail++;
@@ -165,7 +203,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
             }
             nact.push_back(i);
             src.push_back(k);
-            tgt.push_back(std::max(xi * bnorm[i], o.inner_tol * rr));
+            tgt.push_back(std::max(xi * bmin, o.inner_tol * rr));
         }
         if (nact.empty()) break;
         const int nn = (int)nact.size();
@@ -185,7 +223,8 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         kry_start_state(c, sb.st, src_d, rn2, tgt_d, nn);
         kry_start<S>(c, basis, r, src_d, rn2, nn);
         c->timer.end(c->stream);
-        for (int j = 0; j < m; j++) {
+        // one Arnoldi step: (preconditioner,) operator, Gram-Schmidt and the Givens update
+        auto step = [&](int j) {
             const void* vj = (const char*)basis + (size_t)j * vstride * eb;
             void* vj1 = (char*)basis + (size_t)(j + 1) * vstride * eb;
             const void* aj = vj;
@@ -196,18 +235,63 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
             }
             dslash(c, prec, LQT_A, aj, vj1, nn, n, n);
             kry_step_orth<S>(c, basis, vstride, j, nn, sb.st, o.cgs2 != 0, part, partn);
-            if (j + 1 < m) {
-                LQT_HIP(hipMemcpyAsync(h_flags, sb.st.frozen, sizeof(int) * nn, hipMemcpyDeviceToHost, c->stream));
-                LQT_HIP(hipStreamSynchronize(c->stream));
-                bool all = true;
-                for (int k = 0; k < nn; k++) all = all && h_flags[k];
-                if (all) break;
+        };
+        auto finish = [&]() {
+            c->timer.begin(c->stream, KT_KRYLOV);
+            kry_backsolve(c, nn, sb.st);
+            kry_xupdate<S>(c, x, act_d, o.use_net ? zb.p : basis, vstride, nn, sb.st);
+            c->timer.end(c->stream);
+        };
+        if (o.graph) {
+            // the cycle of nn systems as one graph: captured on a private stream (the
+            // context stream may be the null stream), replayed on the context stream
+            hipGraphExec_t& ex = graphs[nn];
+            if (!ex) {
+                if (!c->capture_stream) LQT_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+                if (o.use_net) c->net.act.ensure(sizeof(float2) * (size_t)nn * 24 * c->g.V * 2);
+                const hipStream_t s0 = c->stream;
+                const bool timing = c->timer.on;
+                c->timer.on = false;
+                c->stream = c->capture_stream;
+                hipGraph_t gr = nullptr;
+                hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    try {
+                        for (int j = 0; j < m; j++) step(j);
+                        finish();
+                    } catch (...) {
+                        (void)hipStreamEndCapture(c->stream, &gr);
+                        if (gr) (void)hipGraphDestroy(gr);
+                        c->stream = s0;
+                        c->timer.on = timing;
+                        throw;
+                    }
+                    e = hipStreamEndCapture(c->stream, &gr);
+                }
+                c->stream = s0;
+                c->timer.on = timing;
+                LQT_HIP(e);
+                e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                LQT_HIP(e);
             }
+            c->timer.begin(c->stream, KT_GRAPH);
+            LQT_HIP(hipGraphLaunch(ex, c->stream));
+            c->timer.end(c->stream, 0);
+        } else {
+            for (int j = 0; j < m; j++) {
+                step(j);
+                if (j + 1 < m) {  // stop the cycle once every system's cycle has ended
+                    LQT_HIP(hipMemcpyAsync(h_flags, sb.st.frozen, sizeof(int) * nn, hipMemcpyDeviceToHost,
+                                           c->stream));
+                    LQT_HIP(hipStreamSynchronize(c->stream));
+                    bool all = true;
+                    for (int k = 0; k < nn; k++) all = all && h_flags[k];
+                    if (all) break;
+                }
+            }
+            finish();
         }
-        c->timer.begin(c->stream, KT_KRYLOV);
-        kry_backsolve(c, nn, sb.st);
-        kry_xupdate<S>(c, x, act_d, o.use_net ? zb.p : basis, vstride, nn, sb.st);
-        c->timer.end(c->stream);
         LQT_HIP(hipMemcpyAsync(h_flags, sb.st.kdim, sizeof(int) * nn, hipMemcpyDeviceToHost, c->stream));
         LQT_HIP(hipStreamSynchronize(c->stream));
         for (int k = 0; k < nn; k++) its[nact[k]] += h_flags[k];
@@ -237,6 +321,7 @@ SolveOpts make_opts(const lqt_solver_opts* u) {
         o.inner_tol = u->inner_tol > 0 ? u->inner_tol : 0.0;
         o.verbose = u->verbose;
         o.outer_maxit = u->outer_maxit > 0 ? u->outer_maxit : 60;
+        o.graph = u->graph;
     }
     return o;
 }
@@ -247,6 +332,7 @@ int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, 
     LQT_CHECK(o.prec >= LQT_F64 && o.prec <= LQT_BF16, LQT_EINVAL, "bad inner precision");
     LQT_CHECK(xi > 0, LQT_EINVAL, "tolerance must be positive");
     LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net requires preconditioner weights (lqt_precond_set/train)");
+    LQT_CHECK(!o.use_net || c->g.lat.nlat == 1, LQT_EINVAL, "the network preconditioner serves single-lattice contexts");
     const long long n = 12LL * c->g.V;
     // batch size: caller cap, else what fits in 70% of free device memory
     size_t fr = 0, tot = 0;

@@ -260,6 +260,7 @@ int lqt_basis_from_vectors(lqt_ctx* c, const double* vectors, int k, lqt_basis**
     if (!c || !out) return LQT_EINVAL;
     *out = nullptr;
     return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(vectors && k >= 1, LQT_EINVAL, "need k >= 1 vectors");
         need_gauge(c);
         const long long n = 12LL * c->g.V;
@@ -284,6 +285,7 @@ int lqt_basis_eig(lqt_ctx* c, int k, double xi, double tau, const lqt_solver_opt
     if (!c || !out) return LQT_EINVAL;
     *out = nullptr;
     return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(k >= 1, LQT_EINVAL, "k must be >= 1");
         LQT_CHECK(xi > 0 && xi < 1, LQT_EINVAL, "xi must be in (0, 1)");
         LQT_CHECK(tau == 0.0, LQT_EINVAL, "the shifted (tau != 0) eigensolver is not implemented");
@@ -368,11 +370,95 @@ void lqt_basis_free(lqt_basis* B) {
     delete B;
 }
 
+int lqt_trace_lattices(lqt_ctx* c, int nprobes, uint64_t seed, double xi, const lqt_solver_opts* opts,
+                       lqt_trace_result* res, double* samples) {
+    if (!c) return LQT_EINVAL;
+    int nfail_total = 0;
+    int rc = guard(c, [&] {
+        LQT_CHECK(res, LQT_EINVAL, "null result");
+        LQT_CHECK(nprobes >= 1, LQT_EINVAL, "nprobes must be >= 1");
+        LQT_CHECK(xi > 0 && xi < 1, LQT_EINVAL, "xi must be in (0, 1)");
+        need_gauge(c);
+        lqt::SolveOpts o = lqt::make_opts(opts);
+        LQT_CHECK(!o.use_net, LQT_EINVAL, "the network preconditioner serves single-lattice contexts");
+        const int nlat = c->g.lat.nlat;
+        const long long n = 12LL * c->g.V;
+        const int s = nprobes;
+        size_t fr = 0, tot = 0;
+        LQT_HIP(hipMemGetInfo(&fr, &tot));
+        size_t per = (size_t)n * 16 * 2 + (size_t)(o.restart + 1) * n * lqt::storage_bytes(o.prec) + (size_t)n * 32;
+        int fit = (int)std::max<size_t>(1, (size_t)(0.6 * (double)(fr + c->scratch[0].n + c->scratch[10].n +
+                                                                     c->scratch[11].n)) / per);
+        int chunk = std::min(s, o.max_batch > 0 ? o.max_batch : s);
+        chunk = std::max(1, std::min(chunk, fit));
+        c->scratch[10].ensure(sizeof(double2) * (size_t)chunk * n);
+        c->scratch[11].ensure(sizeof(double2) * (size_t)chunk * n);
+        double2* Z = c->scratch[10].as<double2>();
+        double2* Y = c->scratch[11].as<double2>();
+        std::vector<zd> t((size_t)s * nlat);  // [probe][lattice]
+        std::vector<lqt_solve_stats> st(s);
+        hipEvent_t e0, e1;
+        LQT_HIP(hipEventCreate(&e0));
+        LQT_HIP(hipEventCreate(&e1));
+        double t_solve = 0;
+        for (int j0 = 0; j0 < s; j0 += chunk) {
+            const int cs = std::min(chunk, s - j0);
+            lqt::probes_gen(c, seed, j0, cs, Z);
+            LQT_HIP(hipEventRecord(e0, c->stream));
+            nfail_total += lqt::solve_fields(c, Z, Y, cs, xi, o, st.data() + j0);
+            LQT_HIP(hipEventRecord(e1, c->stream));
+            c->scratch[9].ensure(sizeof(double2) * (size_t)cs * nlat);
+            lqt::probe_dots(c, seed, j0, Y, cs, c->scratch[9].as<double2>(), true);
+            lqt::d2h(c, t.data() + (size_t)j0 * nlat, c->scratch[9].p, sizeof(double2) * cs * nlat);
+            float a = 0;
+            LQT_HIP(hipEventElapsedTime(&a, e0, e1));
+            t_solve += a * 1e-3;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        long long iters = 0;
+        int nf = 0;
+        for (auto& x : st) {
+            iters += x.iters;
+            nf += x.converged ? 0 : 1;
+        }
+        for (int l = 0; l < nlat; l++) {
+            std::vector<zd> tl(s);
+            for (int j = 0; j < s; j++) tl[j] = t[(size_t)j * nlat + l];
+            Stats S = summarize(tl);
+            lqt_trace_result& R = res[l];
+            R.trace_re = S.mean.real();
+            R.trace_im = S.mean.imag();
+            R.t0_re = R.t0_im = 0;
+            R.var_sample = S.var;
+            R.var_mean = S.var / s;
+            R.jackknife_err = S.jk;
+            R.var_re_only = S.var_re;
+            R.nsolves = s;
+            R.nfailed = nf;
+            R.iters_total = iters;
+            R.seconds_solve = t_solve;
+            R.seconds_setup = 0;
+            if (samples)
+                for (int j = 0; j < s; j++) {
+                    samples[2 * ((size_t)l * s + j)] = tl[j].real();
+                    samples[2 * ((size_t)l * s + j) + 1] = tl[j].imag();
+                }
+        }
+    });
+    if (rc == LQT_OK && nfail_total > 0) {
+        c->err = std::to_string(nfail_total) + " probe solves missed the tolerance";
+        return LQT_ENOTCONV;
+    }
+    return rc;
+}
+
 int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64_t seed, double xi,
               const lqt_solver_opts* opts, lqt_trace_result* res, double* rank_curve, double* samples) {
     if (!c) return LQT_EINVAL;
     int nfail_total = 0;
     int rc = guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "several lattices: use lqt_trace_lattices");
         LQT_CHECK(res, LQT_EINVAL, "null result");
         LQT_CHECK(nprobes >= 1, LQT_EINVAL, "nprobes must be >= 1");
         LQT_CHECK(xi > 0 && xi < 1, LQT_EINVAL, "xi must be in (0, 1)");
@@ -545,6 +631,7 @@ int lqt_project_probes(lqt_ctx* c, const double* x, int ka, uint64_t seed, long 
                        double* h_cdn) {
     if (!c) return LQT_EINVAL;
     return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(ka >= 1 && s >= 1 && j0 >= 0 && x && h_cup && h_cdn, LQT_EINVAL, "bad projection arguments");
         const long long n = 12LL * c->g.V;
         DBuf X, out;

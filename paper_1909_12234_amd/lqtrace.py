@@ -27,7 +27,8 @@ ERROR_NAMES = {0: "LQT_OK", -1: "LQT_EINVAL", -2: "LQT_ENOMEM", -3: "LQT_EHIP", 
 class SolverOpts(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("use_net", ctypes.c_int), ("max_batch", ctypes.c_int), ("cgs2", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("verbose", ctypes.c_int), ("outer_maxit", ctypes.c_int)]
+                ("inner_tol", ctypes.c_double), ("verbose", ctypes.c_int), ("outer_maxit", ctypes.c_int),
+                ("graph", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -61,6 +62,8 @@ _I = ctypes.c_int
 _D = ctypes.c_double
 _SIGS = {
     "lqt_create": ([ctypes.POINTER(_P), _P, _D, _I, _P], _I),
+    "lqt_create_multi": ([ctypes.POINTER(_P), _I, _P, _P, _I, _P], _I),
+    "lqt_trace_lattices": ([_P, _I, ctypes.c_uint64, _D, _P, _P, _P], _I),
     "lqt_set_gauge": ([_P, _P, _I], _I),
     "lqt_set_mass": ([_P, _D], _I),
     "lqt_apply": ([_P, _I, _I, _P, _P, _I], _I),
@@ -116,24 +119,36 @@ def _ptr(t):
 
 
 def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0, verbose=0,
-          outer_maxit=0):
-    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit)
+          outer_maxit=0, graph=0):
+    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit, graph)
 
 
 class Context:
     """A lattice, its gauge field and the mass, bound to the current torch HIP stream."""
 
     def __init__(self, dims, mass, antiperiodic=True, stream=None):
-        self.dims = tuple(int(d) for d in dims)
-        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        """dims (Lx, Ly, Lz, Lt) and a mass; or a list of such dims and a list of masses for a
+        context of several lattices solved together (fields: the lattices one after another)."""
+        multi = isinstance(dims[0], (tuple, list))
+        self.lattices = [tuple(int(d) for d in x) for x in dims] if multi else [tuple(int(d) for d in dims)]
+        self.dims = self.lattices[0]
+        self.nlat = len(self.lattices)
+        self.V = sum(x[0] * x[1] * x[2] * x[3] for x in self.lattices)
         self.N = 12 * self.V
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._h = ctypes.c_void_p()
-        d = (ctypes.c_int * 4)(*self.dims)
-        rc = lib().lqt_create(ctypes.byref(self._h), d, float(mass), int(antiperiodic),
-                              ctypes.c_void_p(self.stream.cuda_stream))
+        if multi:
+            masses = [float(m) for m in mass] if isinstance(mass, (tuple, list)) else [float(mass)] * self.nlat
+            d = (ctypes.c_int * (4 * self.nlat))(*[v for x in self.lattices for v in x])
+            m = (ctypes.c_double * self.nlat)(*masses)
+            rc = lib().lqt_create_multi(ctypes.byref(self._h), self.nlat, d, m, int(antiperiodic),
+                                        ctypes.c_void_p(self.stream.cuda_stream))
+        else:
+            d = (ctypes.c_int * 4)(*self.dims)
+            rc = lib().lqt_create(ctypes.byref(self._h), d, float(mass), int(antiperiodic),
+                                  ctypes.c_void_p(self.stream.cuda_stream))
         if rc != 0:
-            raise LqtError(rc, "lqt_create failed")
+            raise LqtError(rc, "context creation failed")
 
     # -- plumbing
     def _check(self, rc, allow=()):
@@ -199,13 +214,14 @@ class Context:
         return (ms.value, tuple(tile)) if return_tile else ms.value
 
     KERNEL_FAMILIES = ["dslash", "cgs_dots", "cgs_update", "residual_fp64", "krylov_other", "projections",
-                       "prolongator", "net"]
+                       "prolongator", "net", "graph_cycles"]
 
     def kernel_times(self, mode=0):
         """{family: (ms, launches, algorithmic bytes)}; mode 2 starts timing, 3 stops it."""
-        ms = (ctypes.c_double * 8)()
-        calls = (ctypes.c_longlong * 8)()
-        byt = (ctypes.c_double * 8)()
+        nf = len(self.KERNEL_FAMILIES)
+        ms = (ctypes.c_double * nf)()
+        calls = (ctypes.c_longlong * nf)()
+        byt = (ctypes.c_double * nf)()
         self._check(lib().lqt_kernel_times(self._h, ms, calls, byt, int(mode)))
         return {f: (ms[i], calls[i], byt[i]) for i, f in enumerate(self.KERNEL_FAMILIES)}
 
@@ -308,6 +324,23 @@ class Context:
         return loss.value
 
     # -- trace
+    def trace_lattices(self, nprobes, seed, xi, raise_on_fail=True, samples=False, **opts):
+        """One undeflated estimate per lattice (list of dicts)."""
+        res = (TraceResult * self.nlat)()
+        o = _opts(**opts)
+        samp = torch.zeros((self.nlat, nprobes), dtype=torch.complex128) if samples else None
+        rc = lib().lqt_trace_lattices(self._h, int(nprobes), ctypes.c_uint64(seed), float(xi), ctypes.byref(o), res,
+                                      _ptr(samp))
+        self._check(rc, allow=() if raise_on_fail else (LQT_ENOTCONV,))
+        out = []
+        for k in range(self.nlat):
+            d = {f: getattr(res[k], f) for f, _ in TraceResult._fields_}
+            d["rc"] = rc
+            if samples:
+                d["samples"] = samp[k]
+            out.append(d)
+        return out
+
     def trace(self, nprobes, seed, xi, basis=None, projector=OBLIQUE_G5, rank_curve=False, samples=False,
               raise_on_fail=True, **opts):
         res = TraceResult()
