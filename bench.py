@@ -73,6 +73,122 @@ def cpu_baseline(U, dims, mass, iters_per_probe, budget_s=15.0):
     }
 
 
+def _roofline(kt):
+    """Dominant kernel family by device time among those with algorithmic bytes."""
+    fam = max((f for f in kt if kt[f][2] > 0), key=lambda f: kt[f][0])
+    ms, calls, byt = kt[fam]
+    achieved = byt / (ms * 1e-3) / 1e9
+    return {"kernel": fam, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "launches": calls,
+            "avg_launch_us": round(ms * 1e3 / max(calls, 1), 2)}
+
+
+def _line(a, value, elapsed, dtype, config, extra):
+    out = {"metric": "Rademacher probe solves/s at 1e-8 residual (16^3x32) + dslash HBM GB/s", "value": round(value, 3),
+           "unit": "probe solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": round(elapsed / a.steps * 1e3, 2), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def run_batched(a, w):
+    """Three lattices solved together: every kernel of a cycle is one launch over all of them
+    and the cycles are replayed from HIP graphs.  One step = the probes of every lattice."""
+    import numpy as np
+    import torch
+
+    import paper_1909_12234_amd as lq
+    import synth
+
+    torch.cuda.set_device(0)
+    lats = [d for d, _ in w["lattices"]]
+    links = [synth.su3_links(d, w["eps"], sd) for d, sd in w["lattices"]]
+    ctx = lq.Context(lats, [w["mass"]] * len(lats))
+    ctx.set_gauge(np.concatenate([u.ravel() for u in links]))
+    per = (a.nprobes or w["nprobes"]) // len(lats)
+    ctx.tune(lq.F32, per)
+    ctx.tune(lq.F64, 1)
+    opts = dict(prec=lq.F32, restart=16)
+
+    def step(graph):
+        return ctx.trace_lattices(per, w["probe_seed"], w["xi"], graph=graph, **opts)
+
+    for _ in range(a.warmup):
+        step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [step(1) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ok = sum(r[0]["nsolves"] - r[0]["nfailed"] for r in res) * len(lats)
+    # per-kernel timing needs eager launches: one more step with the timers on
+    ctx.kernel_times(mode=2)
+    t1 = time.perf_counter()
+    step(0)
+    torch.cuda.synchronize()
+    eager = time.perf_counter() - t1
+    kt = ctx.kernel_times(mode=3)
+    d_ms, _, d_b = kt["dslash"]
+    _line(a, ok / elapsed, elapsed, "f32",
+          {"workload": f"wilson_batched3: lattices {lats} solved together, eps={w['eps']}, m={w['mass']}, "
+                       f"{per} probes per lattice, FP32 inner GMRES(16), xi={w['xi']}, graph-captured cycles",
+           "lattices": lats, "probes": per * len(lats), "restart": 16},
+          {"roofline": _roofline(kt), "roofline_from": "one eager step with per-kernel HIP events",
+           "eager_step_ms": round(eager * 1e3, 2), "graph_speedup": round(eager / (elapsed / a.steps), 3),
+           "dslash_hbm_gbps": round(d_b / (d_ms * 1e-3) / 1e9, 1) if d_ms > 0 else None,
+           "traces": [r["trace_re"] for r in res[-1]], "jackknife_err": [r["jackknife_err"] for r in res[-1]],
+           "iters_per_probe": res[-1][0]["iters_total"] / max(1, res[-1][0]["nsolves"])})
+
+
+def run_net(a, w):
+    """16^3x32 with the transport net as FGMRES right preconditioner (trained before the
+    timed region), beside the plain path on the same probes."""
+    import torch
+
+    import paper_1909_12234_amd as lq
+    import synth
+
+    torch.cuda.set_device(0)
+    U = synth.su3_links(w["dims"], w["eps"], w["seed"])
+    ctx = lq.Context(w["dims"], w["mass"])
+    ctx.set_gauge(U)
+    nprobes = a.nprobes or w["nprobes"]
+    ctx.tune(lq.BF16, nprobes)
+    ctx.tune(lq.F64, 1)
+    t_train = time.perf_counter()
+    loss = ctx.precond_train(w.get("train_pairs", 256), seed=5, epochs=w.get("train_epochs", 4), lr=3e-3, batch=8,
+                             verbose=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    res = {}
+    for net in (1, 0):
+        def step():
+            return ctx.trace(nprobes, w["probe_seed"], w["xi"], prec=lq.BF16, use_net=net, restart=w.get("restart", 32))
+        for _ in range(a.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.kernel_times(mode=2)
+        t0 = time.perf_counter()
+        rr = [step() for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[net] = (rr, el, ctx.kernel_times(mode=3))
+    rr, el, kt = res[1]
+    ok = sum(r["nsolves"] - r["nfailed"] for r in rr)
+    rp, elp, _ = res[0]
+    okp = sum(r["nsolves"] - r["nfailed"] for r in rp)
+    _line(a, ok / el, el, "bf16",
+          {"workload": f"wilson16x32_net: 16^3x32, eps={w['eps']}, m={w['mass']}, {nprobes} probes, transport-net "
+                       f"FGMRES({w.get('restart', 32)}), BF16 inner, xi={w['xi']}",
+           "lattice": list(w["dims"]), "probes": nprobes, "restart": w.get("restart", 32)},
+          {"roofline": _roofline(kt), "net_ms": round(kt["net"][0], 2),
+           "iters_per_probe_net": rr[-1]["iters_total"] / rr[-1]["nsolves"],
+           "iters_per_probe_plain": rp[-1]["iters_total"] / rp[-1]["nsolves"],
+           "plain_same_probes_solves_per_s": round(okp / elp, 3), "train_s": round(t_train, 2),
+           "train_pairs": w.get("train_pairs", 256), "train_loss": loss})
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -97,6 +213,10 @@ def main():
     from paper_1909_12234_amd.workloads import PREC, WORKLOADS
 
     w = WORKLOADS[a.workload]
+    if "lattices" in w:
+        return run_batched(a, w)
+    if a.workload == "wilson16x32_net":
+        return run_net(a, w)
     dims, mass, eps = w["dims"], w["mass"], w["eps"]
     nprobes = a.nprobes or w["nprobes"]
     prec = PREC[w["inner_prec"]]

@@ -84,6 +84,11 @@ typedef struct {
                         per batch size and replay it; cycles always run all m steps (the
                         steps after a system has converged change nothing), so results
                         are bit-identical to graph = 0 [0]                               */
+    int sstep;       /* 1: s-step cycles (restart <= 8, no use_net): the cycle's basis is
+                        k_{i+1} = (A - theta) k_i / 2 with theta = 4 + m (powers of the
+                        hopping term, no Gram-Schmidt between the operator applications),
+                        made orthonormal afterwards through one Gram pass and an FP64
+                        Cholesky; the same Krylov space and minimisation as GMRES(m) [0]  */
 } lqt_solver_opts;
 
 /* Per right-hand side solve statistics. */

@@ -197,7 +197,7 @@ template <typename S, int R, int OPK, int EPI>
 __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S* __restrict__ in, S* __restrict__ out,
                                                 const S* __restrict__ bvec, double* __restrict__ part,
                                                 const int* __restrict__ act, LatTab tab, int nrhs, long long in_stride,
-                                                long long out_stride, int chunk) {
+                                                long long out_stride, int chunk, double shift, double scale) {
     constexpr bool DAG = OPK == LQT_A_DAG;
     constexpr bool g5in = OPK == LQT_A_G5, g5out = OPK == LQT_G5_A;
     using C = typename acc_of<S>::type;
@@ -230,7 +230,9 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
     const int L0 = tab.L[k][0], L1 = tab.L[k][1], L2 = tab.L[k][2], L3 = tab.L[k][3];
     const uint32_t base = (uint32_t)tab.off[k];
     const uint32_t Vk = (uint32_t)(L0 * L1 * L2 * L3);
-    const C diag = (C)tab.diag[k];
+    // out = scale * ((4 + m_k - shift) in - 1/2 hop(in)): shift 0, scale 1 is the operator itself
+    const C diag = (C)((tab.diag[k] - shift) * scale);
+    const C hs = (C)(-0.5 * scale);
     const uint32_t s = s0 + threadIdx.x;
     const int r0 = grp * R;
     const int nr = min(R, nrhs - r0);
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
                 S* o = out + (long long)(r0 + r) * out_stride;  // uniform
 #pragma unroll
                 for (int c = 0; c < 12; c++) {
-                    cpx<C> v = {fm(diag, p[c].x, (C)-0.5 * acc[r][c].x), fm(diag, p[c].y, (C)-0.5 * acc[r][c].y)};
+                    cpx<C> v = {fm(diag, p[c].x, hs * acc[r][c].x), fm(diag, p[c].y, hs * acc[r][c].y)};
                     if (g5out && c >= 6) {
                         v.x = -v.x;
                         v.y = -v.y;
@@ -320,14 +322,15 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
 
 template <typename S, int R>
 static void launch_R(lqt_ctx* c, int op, const S* U, const S* in, S* out, int nrhs, long long is, long long os,
-                     int bs, int chunk) {
+                     int bs, int chunk, double shift, double scale) {
     const Geom& g = c->g;
     int nsb = (g.V + bs - 1) / bs;
     int ngrp = (nrhs + R - 1) / R;
     int nl = nsb * ngrp;
 #define LQT_DSLASH_OP(OPK)                                                                                   \
     hipLaunchKernelGGL((k_dslash<S, R, OPK, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,        \
-                       (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.lat, nrhs, is, os, chunk)
+                       (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.lat, nrhs, is, os, chunk, shift,  \
+                       scale)
     switch (op) {
         case LQT_A_DAG: LQT_DSLASH_OP(LQT_A_DAG); break;
         case LQT_A_G5: LQT_DSLASH_OP(LQT_A_G5); break;
@@ -359,12 +362,12 @@ const b2* gauge_of<b2>(lqt_ctx* c) {
 
 template <typename S>
 static void launch_prec(lqt_ctx* c, int op, const void* in, void* out, int nrhs, long long is, long long os,
-                        const Tuned& t) {
+                        const Tuned& t, double shift, double scale) {
     const S* U = gauge_of<S>(c);
     switch (t.rhs_per_thread) {
-        case 1: launch_R<S, 1>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk); break;
-        case 2: launch_R<S, 2>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk); break;
-        default: launch_R<S, 4>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk); break;
+        case 1: launch_R<S, 1>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk, shift, scale); break;
+        case 2: launch_R<S, 2>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk, shift, scale); break;
+        default: launch_R<S, 4>(c, op, U, (const S*)in, (S*)out, nrhs, is, os, t.block, t.chunk, shift, scale); break;
     }
 }
 
@@ -382,23 +385,23 @@ static Tuned default_tile(int prec, int nrhs) {
 }
 
 static void dslash_cfg(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long is, long long os,
-                       Tuned t) {
+                       Tuned t, double shift = 0.0, double scale = 1.0) {
     switch (prec) {
-        case LQT_F64: launch_prec<double2>(c, op, in, out, nrhs, is, os, t); break;
-        case LQT_F32: launch_prec<float2>(c, op, in, out, nrhs, is, os, t); break;
-        case LQT_F16: launch_prec<h2>(c, op, in, out, nrhs, is, os, t); break;
-        default: launch_prec<b2>(c, op, in, out, nrhs, is, os, t); break;
+        case LQT_F64: launch_prec<double2>(c, op, in, out, nrhs, is, os, t, shift, scale); break;
+        case LQT_F32: launch_prec<float2>(c, op, in, out, nrhs, is, os, t, shift, scale); break;
+        case LQT_F16: launch_prec<h2>(c, op, in, out, nrhs, is, os, t, shift, scale); break;
+        default: launch_prec<b2>(c, op, in, out, nrhs, is, os, t, shift, scale); break;
     }
 }
 
 void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long in_stride,
-            long long out_stride) {
+            long long out_stride, double shift, double scale) {
     if (nrhs <= 0) return;
     Tuned t;
     auto it = c->tuned.find(tune_key(prec, nrhs));
     t = (it != c->tuned.end()) ? it->second : default_tile(prec, nrhs);
     c->timer.begin(c->stream, KT_DSLASH);
-    dslash_cfg(c, prec, op, in, out, nrhs, in_stride, out_stride, t);
+    dslash_cfg(c, prec, op, in, out, nrhs, in_stride, out_stride, t, shift, scale);
     const double b = (double)storage_bytes(prec) / 2;  // bytes per real
     c->timer.end(c->stream, (double)c->g.canon_sites * (72.0 * b + 48.0 * b * nrhs));
 }
@@ -473,7 +476,7 @@ void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, doub
     double* part = c->scratch[7].as<double>();
     c->timer.begin(c->stream, KT_RESID);
     hipLaunchKernelGGL((k_dslash<double2, 1, LQT_A, 1>), dim3(xcd_grid(nsb * nrhs)), dim3(bs), 0, c->stream,
-                       c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.lat, nrhs, n, n, 0);
+                       c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.lat, nrhs, n, n, 0, 0.0, 1.0);
     LQT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, c->stream, part, nsb, nrhs, rnorm2);
     LQT_HIP(hipGetLastError());

@@ -41,5 +41,10 @@ void kry_norm_givens(lqt_ctx* c, const double* part, int nsb, int j, int ns, con
 void kry_backsolve(lqt_ctx* c, int ns, const KryState& st);
 void kry_start_state(lqt_ctx* c, const KryState& st, const int* src, const double* rn2, const double* target_abs,
                      int ns);
+// s-step cycle end (vectors k_0..k_s of ns slots, A k_i = k_{i+1}/sigma + theta k_i): Gram,
+// Cholesky, least squares; leaves the update coefficients in st.beta and kdim = steps used
+template <typename S>
+void sstep_finish(lqt_ctx* c, const void* Vb, long long vstride, int s, int ns, const KryState& st, double theta,
+                  double sigma, DBuf& work);
 
 }  // namespace lqt

@@ -519,6 +519,210 @@ __global__ void k_start_state(KryState st, const int* __restrict__ src, const do
     st.target[q] = target_abs[q];
 }
 
+// ---------------------------------------------------------------------------- s-step cycles
+// The cycle's basis is k_0 = r sqrt(N)/|r|, k_{i+1} = sigma (A - theta) k_i (no Gram-Schmidt
+// between the operator applications), so A k_i = k_{i+1}/sigma + theta k_i.  One pass forms
+// the Gram matrix G = K^+ K; with G = R^+ R (Cholesky, FP64) K = Q R, A Q_s = Q H with
+// H = R T R_s^{-1}, T[i][i] = theta, T[i+1][i] = 1/sigma, and GMRES minimises
+// |rho R_00 e_1 - H y| (rho = |r|/sqrt(N)); the update is x += K_s R_s^{-1} y.
+
+// Gram partial sums of the NV = s+1 stored vectors of slot q over the elements of block
+// blk: part[(q*nblk + blk)*2*NP + 2p (+1)] for the upper-triangle pair p = (i <= j).
+template <typename S, int NV>
+__global__ __launch_bounds__(256) void k_sgram(const S* __restrict__ Vb, long long vstride, long long n,
+                                               double* __restrict__ part) {
+    using C = typename acc_of<S>::type;
+    constexpr int NP = NV * (NV + 1) / 2;
+    __shared__ double red[4][2 * NP];
+    const int q = blockIdx.y, nblk = gridDim.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long per = ((n + nblk - 1) / nblk + 255) / 256 * 256;
+    const long long e0 = (long long)blockIdx.x * per, e1 = min(n, e0 + per);
+    C ar[NP], ai[NP];
+#pragma unroll
+    for (int p = 0; p < NP; p++) ar[p] = ai[p] = 0;
+    const S* base = Vb + q * n;
+    for (long long e = e0 + threadIdx.x; e < e1; e += 256) {
+        cx<C> v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++) v[i] = ldk<S, C>(base + i * vstride + e);
+        int p = 0;
+#pragma unroll
+        for (int i = 0; i < NV; i++)
+#pragma unroll
+            for (int j = i; j < NV; j++, p++) {
+                ar[p] += v[i].x * v[j].x + v[i].y * v[j].y;
+                ai[p] += v[i].x * v[j].y - v[i].y * v[j].x;
+            }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+        const double a = wsum(ar[p]), b = wsum(ai[p]);
+        if (lane == 0) {
+            red[wave][2 * p] = a;
+            red[wave][2 * p + 1] = b;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 2 * NP; t += 256)
+        part[((long long)q * nblk + blockIdx.x) * 2 * NP + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+// One thread per slot: sum the Gram partials, Cholesky (truncated at the first pivot below
+// 1e-12 G_00: the basis then stops at that column), H, Givens least squares, coefficients.
+// The small FP64 part of an s-step cycle for one system: G (NV x NV Hermitian Gram matrix
+// of k_0..k_s), nr = |r|; writes beta[0..m] and returns the steps used (kdim) and *est.
+template <int NV>
+__host__ __device__ int sstep_small_solve(const double2 (&G)[NV][NV], double nr, double theta, double sigma,
+                                          double sqrtN, int m, double2* beta, double* est) {
+    constexpr int S = NV - 1;
+    // Cholesky G = R^+ R, R upper triangular
+    double2 R[NV][NV];
+    for (int i = 0; i < NV; i++)
+        for (int j = 0; j < NV; j++) R[i][j] = make_double2(0, 0);
+    int kk = NV;
+    const double floor = 1e-12 * G[0][0].x;
+    for (int j = 0; j < NV; j++) {
+        double d = G[j][j].x;
+        for (int k = 0; k < j; k++) d -= R[k][j].x * R[k][j].x + R[k][j].y * R[k][j].y;
+        if (!(d > floor)) {
+            kk = j;
+            break;
+        }
+        const double rd = sqrt(d);
+        R[j][j] = make_double2(rd, 0);
+        for (int l = j + 1; l < NV; l++) {
+            double2 t = G[j][l];
+            for (int k = 0; k < j; k++) {  // t -= conj(R[k][j]) R[k][l]
+                const double2 a = R[k][j], b = R[k][l];
+                t.x -= a.x * b.x + a.y * b.y;
+                t.y -= a.x * b.y - a.y * b.x;
+            }
+            R[j][l] = make_double2(t.x / rd, t.y / rd);
+        }
+    }
+    const int ss = kk - 1;  // usable steps
+    for (int i = 0; i <= m; i++) beta[i] = make_double2(0, 0);
+    if (ss < 1 || !(nr > 0)) {
+        *est = nr;
+        return 0;
+    }
+    // Rinv = R_ss^{-1} (upper triangular)
+    double2 Ri[S][S];
+    for (int i = 0; i < ss; i++)
+        for (int j = 0; j < ss; j++) Ri[i][j] = make_double2(0, 0);
+    for (int j = 0; j < ss; j++) {
+        Ri[j][j] = make_double2(1.0 / R[j][j].x, 0);
+        for (int i = j - 1; i >= 0; i--) {
+            double2 t = make_double2(0, 0);
+            for (int k = i + 1; k <= j; k++) {  // t += R[i][k] Ri[k][j]
+                const double2 a = R[i][k], b = Ri[k][j];
+                t.x += a.x * b.x - a.y * b.y;
+                t.y += a.x * b.y + a.y * b.x;
+            }
+            Ri[i][j] = make_double2(-t.x / R[i][i].x, -t.y / R[i][i].x);
+        }
+    }
+    // H = R[0..ss][0..ss] T Rinv, with (T Rinv)[k][j] = theta Rinv[k][j] + Rinv[k-1][j] / sigma
+    double2 H[NV][S];
+    for (int i = 0; i <= ss; i++)
+        for (int j = 0; j < ss; j++) {
+            double2 h = make_double2(0, 0);
+            for (int k = i; k <= ss; k++) {
+                double2 tr = make_double2(0, 0);
+                if (k < ss) tr = make_double2(theta * Ri[k][j].x, theta * Ri[k][j].y);
+                if (k >= 1) {
+                    tr.x += Ri[k - 1][j].x / sigma;
+                    tr.y += Ri[k - 1][j].y / sigma;
+                }
+                const double2 a = R[i][k];
+                h.x += a.x * tr.x - a.y * tr.y;
+                h.y += a.x * tr.y + a.y * tr.x;
+            }
+            H[i][j] = h;
+        }
+    // Givens QR of H against g = rho R_00 e_1
+    double2 g[NV];
+    for (int i = 0; i <= ss; i++) g[i] = make_double2(0, 0);
+    g[0] = make_double2(nr / sqrtN * R[0][0].x, 0);
+    for (int j = 0; j < ss; j++) {
+        const double2 a = H[j][j], b = H[j + 1][j];
+        const double absa = sqrt(a.x * a.x + a.y * a.y), absb = sqrt(b.x * b.x + b.y * b.y);
+        const double r = sqrt(absa * absa + absb * absb);
+        double c;
+        double2 sn;
+        if (r == 0) {
+            c = 1;
+            sn = make_double2(0, 0);
+        } else if (absa == 0) {
+            c = 0;
+            sn = make_double2(b.x / absb, -b.y / absb);  // conj(b)/|b|
+        } else {
+            c = absa / r;
+            // s = (a/|a|) conj(b) / r
+            const double ux = a.x / absa, uy = a.y / absa;
+            sn = make_double2((ux * b.x + uy * b.y) / r, (uy * b.x - ux * b.y) / r);
+        }
+        for (int l = j; l < ss; l++) {  // rows j, j+1: [c s; -conj(s) c]
+            const double2 h0 = H[j][l], h1 = H[j + 1][l];
+            H[j][l] = make_double2(c * h0.x + sn.x * h1.x - sn.y * h1.y, c * h0.y + sn.x * h1.y + sn.y * h1.x);
+            H[j + 1][l] = make_double2(-(sn.x * h0.x + sn.y * h0.y) + c * h1.x, -(sn.x * h0.y - sn.y * h0.x) + c * h1.y);
+        }
+        const double2 g0 = g[j], g1 = g[j + 1];
+        g[j] = make_double2(c * g0.x + sn.x * g1.x - sn.y * g1.y, c * g0.y + sn.x * g1.y + sn.y * g1.x);
+        g[j + 1] = make_double2(-(sn.x * g0.x + sn.y * g0.y) + c * g1.x, -(sn.x * g0.y - sn.y * g0.x) + c * g1.y);
+    }
+    double2 y[S];
+    for (int i = ss - 1; i >= 0; i--) {
+        double2 t = g[i];
+        for (int l = i + 1; l < ss; l++) {
+            const double2 h = H[i][l];
+            t.x -= h.x * y[l].x - h.y * y[l].y;
+            t.y -= h.x * y[l].y + h.y * y[l].x;
+        }
+        const double2 d = H[i][i];
+        const double den = d.x * d.x + d.y * d.y;
+        y[i] = den > 0 ? make_double2((t.x * d.x + t.y * d.y) / den, (t.y * d.x - t.x * d.y) / den)
+                       : make_double2(0, 0);
+    }
+    for (int i = 0; i < ss; i++) {  // beta = Rinv y
+        double2 t = make_double2(0, 0);
+        for (int k = i; k < ss; k++) {
+            const double2 a = Ri[i][k], b = y[k];
+            t.x += a.x * b.x - a.y * b.y;
+            t.y += a.x * b.y + a.y * b.x;
+        }
+        beta[i] = t;
+    }
+    *est = sqrt(g[ss].x * g[ss].x + g[ss].y * g[ss].y) * sqrtN / R[0][0].x;
+    return ss;
+}
+
+template <int NV>
+__global__ void k_sstep_solve(const double* __restrict__ part, int nblk, KryState st, int ns, double theta,
+                              double sigma, double sqrtN) {
+    constexpr int NP = NV * (NV + 1) / 2;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ns) return;
+    const int m = st.m;
+    double2 G[NV][NV];
+    int p = 0;
+    for (int i = 0; i < NV; i++)
+        for (int j = i; j < NV; j++, p++) {
+            double a = 0, b = 0;
+            for (int k = 0; k < nblk; k++) {
+                a += part[((long long)q * nblk + k) * 2 * NP + 2 * p];
+                b += part[((long long)q * nblk + k) * 2 * NP + 2 * p + 1];
+            }
+            G[i][j] = make_double2(a, b);
+            G[j][i] = make_double2(a, -b);
+        }
+    double est = 0;
+    st.kdim[q] = sstep_small_solve<NV>(G, st.g[(long long)q * (m + 1)].x, theta, sigma, sqrtN, m,
+                                       st.beta + (long long)q * (m + 1), &est);
+    st.est[q] = est;
+}
+
 // ---------------------------------------------------------------------------- host side
 // chunks of 16 bytes in one slot vector (12 V complex values of S)
 template <typename S>
@@ -579,13 +783,68 @@ void kry_start_state(lqt_ctx* c, const KryState& st, const int* src, const doubl
     LQT_HIP(hipGetLastError());
 }
 
+// s-step cycle end: Gram of the ns slots' s+1 stored vectors, then the small solves
+constexpr int SGRAM_BLOCKS = 48;
+template <typename S>
+void sstep_finish(lqt_ctx* c, const void* Vb, long long vstride, int s, int ns, const KryState& st, double theta,
+                  double sigma, DBuf& work) {
+    const long long n = 12LL * c->g.V;
+    const int nv = s + 1;
+    const int np = nv * (nv + 1) / 2;
+    work.ensure(sizeof(double) * (size_t)ns * SGRAM_BLOCKS * 2 * np);
+    double* part = work.as<double>();
+    dim3 grid(SGRAM_BLOCKS, ns);
+    const double sqrtN = sqrt((double)n);
+    c->timer.begin(c->stream, KT_DOTS);
+#define LQT_SSTEP(NV)                                                                                      \
+    case NV:                                                                                               \
+        hipLaunchKernelGGL((k_sgram<S, NV>), grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, n, part); \
+        break;
+    switch (nv) {
+        LQT_SSTEP(2)
+        LQT_SSTEP(3)
+        LQT_SSTEP(4)
+        LQT_SSTEP(5)
+        LQT_SSTEP(6)
+        LQT_SSTEP(7)
+        LQT_SSTEP(8)
+        LQT_SSTEP(9)
+        default: throw Error{LQT_EINVAL, "s-step cycles need 1 <= restart <= 8"};
+    }
+#undef LQT_SSTEP
+    LQT_HIP(hipGetLastError());
+    c->timer.end(c->stream, (double)nv * n * sizeof(S) * ns);
+    c->timer.begin(c->stream, KT_KRYLOV);
+#define LQT_SSOLVE(NV)                                                                                          \
+    case NV:                                                                                                    \
+        hipLaunchKernelGGL(k_sstep_solve<NV>, dim3((ns + 63) / 64), dim3(64), 0, c->stream, part, SGRAM_BLOCKS, st, \
+                           ns, theta, sigma, sqrtN);                                                            \
+        break;
+    switch (nv) {
+        LQT_SSOLVE(2)
+        LQT_SSOLVE(3)
+        LQT_SSOLVE(4)
+        LQT_SSOLVE(5)
+        LQT_SSOLVE(6)
+        LQT_SSOLVE(7)
+        LQT_SSOLVE(8)
+        LQT_SSOLVE(9)
+        default: break;
+    }
+#undef LQT_SSOLVE
+    LQT_HIP(hipGetLastError());
+    c->timer.end(c->stream);
+}
+
 #define INST(S)                                                                                          \
     template int kry_blocks<S>(const lqt_ctx*);                                                          \
     template void kry_dots<S>(lqt_ctx*, const void*, long long, int, int, double2*);                     \
     template void kry_update<S>(lqt_ctx*, void*, long long, int, int, const KryState&, int, double*);    \
     template void kry_xupdate<S>(lqt_ctx*, double2*, const int*, const void*, long long, int,            \
                                  const KryState&);                                                      \
-    template void kry_start<S>(lqt_ctx*, void*, const double2*, const int*, const double*, int);
+    template void kry_start<S>(lqt_ctx*, void*, const double2*, const int*, const double*, int);        \
+    template void sstep_finish<S>(lqt_ctx*, const void*, long long, int, int, const KryState&, double, double, \
+                                  DBuf&);
 INST(double2)
 INST(float2)
 INST(h2)

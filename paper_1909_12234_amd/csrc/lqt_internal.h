@@ -335,8 +335,9 @@ struct lqt_ctx {
     lqt::DBuf U[4];  // gauge per precision (LQT_F64 .. LQT_BF16)
     // work buffers, grown on demand: 0 Krylov basis, 1 residuals, 2 Krylov state,
     // 3-4 Krylov partial sums, 5-6 apply / BLAS partials, 7 residual partials,
-    // 8 GEMM partials, 9 small matrices, 10-11 estimator fields, 12 FGMRES preconditioned basis
-    lqt::DBuf scratch[13];
+    // 8 GEMM partials, 9 small matrices, 10-11 estimator fields, 12 FGMRES preconditioned basis,
+    // 13 s-step Gram partials
+    lqt::DBuf scratch[14];
     lqt::HBuf pinned;
     std::map<long long, lqt::Tuned> tuned;
     lqt::KTimer timer;
@@ -377,8 +378,9 @@ template <typename S>
 void convert_out_c64(lqt_ctx* c, const S* dev, float2* canon, int nrhs);
 
 // ---- dslash (dslash.hip): out = op(in), device layout, nrhs fields
+// out = scale * (op(in) - shift * in) for op = A (shift, scale apply to A only)
 void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long in_stride,
-            long long out_stride);
+            long long out_stride, double shift = 0.0, double scale = 1.0);
 double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen = nullptr);
 // FP64 residual r = b - A x for nrhs fields and squared norms (device layout FP64).
 // act maps slot -> field index (nullptr = identity).

@@ -15,6 +15,7 @@ struct SolveOpts {
     int verbose = 0;
     int outer_maxit = 60;
     int graph = 0;
+    int sstep = 0;
 };
 
 SolveOpts make_opts(const lqt_solver_opts* u);

@@ -105,6 +105,12 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     partb.ensure(sizeof(double2) * (size_t)nb * nsb * (m + 2));
     const int nlat = c->g.lat.nlat;
     const bool multi = nlat > 1;  // several lattices: every lattice block must meet xi
+    // s-step basis k_{i+1} = sigma (A - theta) k_i: theta = 4 + m centres the spectrum of A
+    // (A - theta is the hopping term), sigma = 1/2 keeps the vectors' scale near one
+    double theta = 0;
+    for (int l = 0; l < nlat; l++) theta += c->g.lat.diag[l] / nlat;
+    const double sigma = 0.5;
+    if (o.sstep) c->scratch[13].ensure(sizeof(double) * (size_t)nb * 48 * (m + 1) * (m + 2));  // before any capture
     partnb.ensure(sizeof(double) * (size_t)nb * nsb + sizeof(double) * 2 * nb + sizeof(int) * 2 * nb +
                   sizeof(double) * nb + sizeof(double) * (size_t)nb * nlat + 1024);
 
@@ -223,10 +229,15 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         kry_start_state(c, sb.st, src_d, rn2, tgt_d, nn);
         kry_start<S>(c, basis, r, src_d, rn2, nn);
         c->timer.end(c->stream);
-        // one Arnoldi step: (preconditioner,) operator, Gram-Schmidt and the Givens update
+        // one Arnoldi step: (preconditioner,) operator, Gram-Schmidt and the Givens update;
+        // s-step cycles: the operator step k_{j+1} = sigma (A - theta) k_j only
         auto step = [&](int j) {
             const void* vj = (const char*)basis + (size_t)j * vstride * eb;
             void* vj1 = (char*)basis + (size_t)(j + 1) * vstride * eb;
+            if (o.sstep) {
+                dslash(c, prec, LQT_A, vj, vj1, nn, n, n, theta, sigma);
+                return;
+            }
             const void* aj = vj;
             if (o.use_net) {
                 void* zj = (char*)zb.p + (size_t)j * vstride * eb;
@@ -237,8 +248,10 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
             kry_step_orth<S>(c, basis, vstride, j, nn, sb.st, o.cgs2 != 0, part, partn);
         };
         auto finish = [&]() {
+            if (o.sstep)
+                sstep_finish<S>(c, basis, vstride, m, nn, sb.st, theta, sigma, c->scratch[13]);
             c->timer.begin(c->stream, KT_KRYLOV);
-            kry_backsolve(c, nn, sb.st);
+            if (!o.sstep) kry_backsolve(c, nn, sb.st);
             kry_xupdate<S>(c, x, act_d, o.use_net ? zb.p : basis, vstride, nn, sb.st);
             c->timer.end(c->stream);
         };
@@ -281,7 +294,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         } else {
             for (int j = 0; j < m; j++) {
                 step(j);
-                if (j + 1 < m) {  // stop the cycle once every system's cycle has ended
+                if (j + 1 < m && !o.sstep) {  // stop the cycle once every system's cycle has ended
                     LQT_HIP(hipMemcpyAsync(h_flags, sb.st.frozen, sizeof(int) * nn, hipMemcpyDeviceToHost,
                                            c->stream));
                     LQT_HIP(hipStreamSynchronize(c->stream));
@@ -322,6 +335,7 @@ SolveOpts make_opts(const lqt_solver_opts* u) {
         o.verbose = u->verbose;
         o.outer_maxit = u->outer_maxit > 0 ? u->outer_maxit : 60;
         o.graph = u->graph;
+        o.sstep = u->sstep;
     }
     return o;
 }
@@ -333,6 +347,8 @@ int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, 
     LQT_CHECK(xi > 0, LQT_EINVAL, "tolerance must be positive");
     LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net requires preconditioner weights (lqt_precond_set/train)");
     LQT_CHECK(!o.use_net || c->g.lat.nlat == 1, LQT_EINVAL, "the network preconditioner serves single-lattice contexts");
+    LQT_CHECK(!o.sstep || (!o.use_net && o.restart <= 8), LQT_EINVAL,
+              "s-step cycles need restart <= 8 and no network preconditioner");
     const long long n = 12LL * c->g.V;
     // batch size: caller cap, else what fits in 70% of free device memory
     size_t fr = 0, tot = 0;

@@ -28,7 +28,7 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("use_net", ctypes.c_int), ("max_batch", ctypes.c_int), ("cgs2", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("verbose", ctypes.c_int), ("outer_maxit", ctypes.c_int),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("sstep", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -119,8 +119,8 @@ def _ptr(t):
 
 
 def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0, verbose=0,
-          outer_maxit=0, graph=0):
-    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit, graph)
+          outer_maxit=0, graph=0, sstep=0):
+    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit, graph, sstep)
 
 
 class Context:

@@ -1,0 +1,87 @@
+"""s-step cycles (basis of hopping-term powers, Gram pass and FP64 Cholesky) against the oracle
+and against ordinary GMRES cycles."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import core
+
+pytestmark = pytest.mark.gpu
+
+
+def _relres(U, dims, m, b, x):
+    r = b - core.apply(U, dims, m, core.OP_A, x)
+    return np.linalg.norm(r, axis=1) / np.linalg.norm(b, axis=1)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+@pytest.mark.parametrize("s", [4, 8])
+def test_sstep_solves_match_oracle(gpu, prec, s):
+    lq = gpu
+    dims, m, xi = (4, 4, 6, 8), -0.6, 1e-9
+    print(f"s-step s={s} prec={prec}", flush=True)
+    U = synth.su3_links(dims, 0.5, 3)
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    b = synth.random_spinors(dims, 5, 4).reshape(5, -1)
+    bt = torch.as_tensor(b).cuda()
+    x, st, _ = c.solve(bt, xi, prec=prec, restart=s, sstep=1)
+    assert all(q[0] for q in st)
+    assert np.all(_relres(U, dims, m, b, x.cpu().numpy()) <= xi * 1.05)
+    _, st0, _ = c.solve(bt, xi, prec=prec, restart=s)
+    # the same Krylov spaces: whole cycles of s steps against GMRES(s) stopping mid-cycle
+    for a, q in zip(st, st0):
+        assert a[1] <= 1.15 * q[1] + 2 * s, (a, q)
+    c.close()
+
+
+def test_sstep_near_critical_16x8(gpu):
+    """A harder operator (m = -1.4 on 8^3x16): BF16 storage, restart 8, to 1e-8."""
+    lq = gpu
+    dims, m, xi = (8, 8, 8, 16), -1.4, 1e-8
+    U = synth.su3_links(dims, 0.5, 1)
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    z = c.probes(77, 8)
+    y, st, _ = c.solve(z, xi, prec=3, restart=8, sstep=1)
+    _, st0, _ = c.solve(z, xi, prec=3, restart=8)
+    assert all(q[0] for q in st)
+    zs, ys = z[:3].cpu().numpy(), y[:3].cpu().numpy()
+    assert np.all(_relres(U, dims, m, zs, ys) <= xi * 1.05)
+    print("steps s-step", [q[1] for q in st], "GMRES(8)", [q[1] for q in st0], flush=True)
+    assert sum(q[1] for q in st) <= 1.15 * sum(q[1] for q in st0) + 8 * len(st)
+    c.close()
+
+
+def test_sstep_graph_bit_identical_and_several_lattices(gpu):
+    lq = gpu
+    lats, masses = [(4, 4, 4, 4), (2, 4, 6, 4)], [-0.3, 0.05]
+    links = [synth.su3_links(d, 0.5, 7 + k) for k, d in enumerate(lats)]
+    c = lq.Context(lats, masses)
+    c.set_gauge(np.concatenate([u.ravel() for u in links]))
+    b = np.concatenate([synth.random_spinors(d, 3, 9 + k).reshape(3, -1) for k, d in enumerate(lats)], axis=1)
+    bt = torch.as_tensor(b).cuda()
+    x0, st0, _ = c.solve(bt, 1e-9, prec=3, restart=8, sstep=1)
+    x1, st1, _ = c.solve(bt, 1e-9, prec=3, restart=8, sstep=1, graph=1)
+    assert torch.equal(x0, x1)
+    assert [q[:3] for q in st0] == [q[:3] for q in st1]
+    x0 = x0.cpu().numpy()
+    o = 0
+    for k, d in enumerate(lats):
+        n = 12 * d[0] * d[1] * d[2] * d[3]
+        assert np.all(_relres(links[k], d, masses[k], b[:, o:o + n], x0[:, o:o + n]) <= 1.05e-9)
+        o += n
+    c.close()
+
+
+def test_sstep_option_limits(gpu):
+    lq = gpu
+    dims = (4, 4, 4, 4)
+    c = lq.Context(dims, -0.3)
+    c.set_gauge(synth.su3_links(dims, 0.5, 1))
+    b = torch.as_tensor(synth.random_spinors(dims, 1, 1).reshape(1, -1)).cuda()
+    with pytest.raises(lq.LqtError) as ei:
+        c.solve(b, 1e-6, restart=9, sstep=1)
+    assert ei.value.code == lq.LQT_EINVAL
+    c.close()
