@@ -84,7 +84,8 @@ typedef struct {
                         per batch size and replay it; cycles always run all m steps (the
                         steps after a system has converged change nothing), so results
                         are bit-identical to graph = 0 [0]                               */
-    int sstep;       /* 1: s-step cycles (restart <= 8, no use_net): the cycle's basis is
+    int sstep;       /* 1: s-step cycles (restart <= 15 with FP16/BF16 storage, <= 8 with
+                        FP32/FP64; no use_net): the cycle's basis is
                         k_{i+1} = (A - theta) k_i / 2 with theta = 4 + m (powers of the
                         hopping term, no Gram-Schmidt between the operator applications),
                         made orthonormal afterwards through one Gram pass and an FP64
@@ -327,7 +328,9 @@ int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const d
  * 64/128/256 sites, block order: site-block major or chunks of 16/64 site blocks swept per
  * right-hand-side group) for (prec, nrhs) now and cache the choice in the context; *ms
  * receives the best time and tile[0..2] the chosen (rhs per thread, block, chunk); either
- * may be NULL. */
+ * may be NULL.  Also tunes the FP64 residual of the solvers' restarts (r = b - A x with its
+ * norms; 1 or 2 right-hand sides per thread, block order) for nrhs right-hand sides, used
+ * for every batch size until tuned again. */
 int lqt_tune(lqt_ctx *ctx, int prec, int nrhs, double *ms, int *tile);
 
 /* Kernel timers: HIP event pairs recorded around the library's launches on the context

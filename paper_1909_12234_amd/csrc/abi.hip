@@ -223,6 +223,7 @@ int lqt_tune(lqt_ctx* c, int prec, int nrhs, double* ms, int* tile) {
         need_gauge(c);
         lqt::Tuned t;
         double best = lqt::dslash_tune(c, prec, nrhs, &t);
+        lqt::residual_tune(c, nrhs);  // the FP64 defect-correction residual for this batch size
         if (ms) *ms = best;
         if (tile) {
             tile[0] = t.rhs_per_thread;

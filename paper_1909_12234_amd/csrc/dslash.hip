@@ -465,24 +465,85 @@ __global__ void k_sum_partials(const double* __restrict__ part, int nparts, int 
     if (threadIdx.x == 0 && r < nrhs) out[r] = red[0];
 }
 
+// FP64 residual launch with R right-hand sides per thread and block order `chunk`
+// (256-site blocks: the per-lattice norm sums need blocks aligned to the lattices).
+static void residual_launch(lqt_ctx* c, const double2* b, const double2* x, double2* r, double* part, const int* act,
+                            int nrhs, int R, int chunk) {
+    const Geom& g = c->g;
+    const int nsb = (g.V + 255) / 256;
+    const long long n = 12LL * g.V;
+    const int ngrp = (nrhs + R - 1) / R;
+    if (R == 2)
+        hipLaunchKernelGGL((k_dslash<double2, 2, LQT_A, 1>), dim3(xcd_grid(nsb * ngrp)), dim3(256), 0, c->stream,
+                           c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.lat, nrhs, n, n, chunk, 0.0, 1.0);
+    else
+        hipLaunchKernelGGL((k_dslash<double2, 1, LQT_A, 1>), dim3(xcd_grid(nsb * ngrp)), dim3(256), 0, c->stream,
+                           c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.lat, nrhs, n, n, chunk, 0.0, 1.0);
+    LQT_HIP(hipGetLastError());
+}
+
+static long long resid_key(int nrhs) { return (100LL << 32) | (unsigned)nrhs; }
+
 void residual64(lqt_ctx* c, const double2* b, const double2* x, double2* r, double* rnorm2, int nrhs,
                 const int* act, double* rnorm2_lat) {
     if (nrhs <= 0) return;
     const Geom& g = c->g;
-    const int bs = 256;
-    const int nsb = (g.V + bs - 1) / bs;
-    const long long n = 12LL * g.V;
+    const int nsb = (g.V + 255) / 256;
     c->scratch[7].ensure(sizeof(double) * (size_t)nsb * nrhs);
     double* part = c->scratch[7].as<double>();
+    auto it = c->tuned.find(resid_key(nrhs));
+    if (it == c->tuned.end()) it = c->tuned.find(resid_key(0));  // the last tuned batch size
+    const Tuned t = it != c->tuned.end() ? it->second : Tuned{1, 256, 0};
     c->timer.begin(c->stream, KT_RESID);
-    hipLaunchKernelGGL((k_dslash<double2, 1, LQT_A, 1>), dim3(xcd_grid(nsb * nrhs)), dim3(bs), 0, c->stream,
-                       c->U[LQT_F64].as<double2>(), x, r, b, part, act, g.lat, nrhs, n, n, 0, 0.0, 1.0);
-    LQT_HIP(hipGetLastError());
+    residual_launch(c, b, x, r, part, act, nrhs, t.rhs_per_thread, t.chunk);
     hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, c->stream, part, nsb, nrhs, rnorm2);
     LQT_HIP(hipGetLastError());
     if (rnorm2_lat) sum_partials_lattices(c, part, nsb, nrhs, rnorm2_lat);
     // links once; x, b read and r written per right-hand side (FP64)
     c->timer.end(c->stream, (double)g.canon_sites * (72.0 * 8 + 72.0 * 8 * nrhs));
+}
+
+// Autotuner of the FP64 residual for nrhs right-hand sides: (R, chunk) on scratch fields.
+double residual_tune(lqt_ctx* c, int nrhs) {
+    const long long n = 12LL * c->g.V;
+    const int nsb = (c->g.V + 255) / 256;
+    DBuf xb, bb, rb, pb;
+    xb.ensure(sizeof(double2) * (size_t)n * nrhs);
+    bb.ensure(sizeof(double2) * (size_t)n * nrhs);
+    rb.ensure(sizeof(double2) * (size_t)n * nrhs);
+    pb.ensure(sizeof(double) * (size_t)nsb * nrhs);
+    LQT_HIP(hipMemsetAsync(xb.p, 0, sizeof(double2) * (size_t)n * nrhs, c->stream));
+    LQT_HIP(hipMemsetAsync(bb.p, 0, sizeof(double2) * (size_t)n * nrhs, c->stream));
+    hipEvent_t e0, e1;
+    LQT_HIP(hipEventCreate(&e0));
+    LQT_HIP(hipEventCreate(&e1));
+    double best = 1e30;
+    Tuned bt{1, 256, 0};
+    const int Rs[2] = {1, 2}, Cs[3] = {0, 16, 64};
+    for (int R : Rs) {
+        if (R > nrhs) continue;
+        for (int ch : Cs) {
+            residual_launch(c, bb.as<double2>(), xb.as<double2>(), rb.as<double2>(), pb.as<double>(), nullptr, nrhs, R,
+                            ch);  // warm
+            LQT_HIP(hipEventRecord(e0, c->stream));
+            for (int k = 0; k < 3; k++)
+                residual_launch(c, bb.as<double2>(), xb.as<double2>(), rb.as<double2>(), pb.as<double>(), nullptr,
+                                nrhs, R, ch);
+            LQT_HIP(hipEventRecord(e1, c->stream));
+            LQT_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            LQT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / 3 < best) {
+                best = ms / 3;
+                bt = Tuned{R, 256, ch};
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tuned[resid_key(nrhs)] = bt;
+    c->tuned[resid_key(0)] = bt;
+    return best;
 }
 
 }  // namespace lqt

@@ -568,6 +568,98 @@ __global__ __launch_bounds__(256) void k_sgram(const S* __restrict__ Vb, long lo
         part[((long long)q * nblk + blockIdx.x) * 2 * NP + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
 }
 
+// Gram partials with the matrix cores, for 16-bit storage and up to 16 vectors: the rows of
+// X are the real parts (rows 0..15) and the imaginary parts (rows 16..31) of k_0..k_15 (zero
+// rows past s+1), X X^T accumulates in one 32x32 FP32 tile per wave over 16 elements per
+// MFMA (products of 16-bit values are exact in FP32), flushed to FP64 every 1024 elements;
+// G = K^+ K = (RR + II) + i (RI - IR) is written as the same upper-triangle partials as
+// k_sgram.  MFMA 32x32x16 operands: lane l holds row l % 32, elements 8 (l / 32) + 0..7;
+// result: lane l, register v holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+typedef __bf16 lqt_bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 lqt_h8 __attribute__((ext_vector_type(8)));
+typedef float lqt_f16v __attribute__((ext_vector_type(16)));
+
+template <typename S>
+__device__ __forceinline__ lqt_f16v mfma_xxt(const uint32_t (&w)[8], int im, lqt_f16v acc) {
+    // w: 8 packed complex values (re low, im high 16 bits); pick one half of each
+    if constexpr (std::is_same<S, b2>::value) {
+        lqt_bf8 a;
+#pragma unroll
+        for (int t = 0; t < 8; t++) a[t] = __builtin_bit_cast(__bf16, (uint16_t)(im ? (w[t] >> 16) : (w[t] & 0xffffu)));
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, a, acc, 0, 0, 0);
+    } else {
+        lqt_h8 a;
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            a[t] = __builtin_bit_cast(_Float16, (uint16_t)(im ? (w[t] >> 16) : (w[t] & 0xffffu)));
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, a, acc, 0, 0, 0);
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_sgram_mf(const S* __restrict__ Vb, long long vstride, long long n, int nv,
+                                                  double* __restrict__ part) {
+    static_assert(sizeof(S) == 4, "16-bit complex storage only");
+    __shared__ double red[32][33];
+    const int q = blockIdx.y, nblk = gridDim.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = lane & 31, half = lane >> 5;
+    const int vec = row & 15, im = row >> 4;
+    const bool live = vec < nv;
+    const uint32_t* base = (const uint32_t*)(Vb + (live ? vec : 0) * vstride + q * n);
+    const long long ngroups = (n + 15) / 16;
+    const long long wid = (long long)blockIdx.x * 4 + wave, nw = (long long)nblk * 4;
+    lqt_f16v acc = {};
+    double accd[16];
+#pragma unroll
+    for (int v = 0; v < 16; v++) accd[v] = 0;
+    int cnt = 0;
+    for (long long g = wid; g < ngroups; g += nw) {
+        const long long e = g * 16 + half * 8;
+        uint32_t w[8];
+        if (live && e + 8 <= n) {
+            const uint4 a = *(const uint4*)(base + e), b = *(const uint4*)(base + e + 4);
+            w[0] = a.x, w[1] = a.y, w[2] = a.z, w[3] = a.w, w[4] = b.x, w[5] = b.y, w[6] = b.z, w[7] = b.w;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; t++) w[t] = (live && e + t < n) ? base[e + t] : 0u;
+        }
+        acc = mfma_xxt<S>(w, im, acc);
+        if (++cnt == 64) {
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                accd[v] += acc[v];
+                acc[v] = 0;
+            }
+            cnt = 0;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; v++) accd[v] += acc[v];
+    // sum the four waves' tiles in LDS
+    for (int t = threadIdx.x; t < 32 * 33; t += 256) (&red[0][0])[t] = 0;
+    __syncthreads();
+    for (int wv = 0; wv < 4; wv++) {
+        if (wave == wv)
+#pragma unroll
+            for (int v = 0; v < 16; v++) red[8 * (v / 4) + 4 * half + (v % 4)][row] += accd[v];
+        __syncthreads();
+    }
+    const int NP = nv * (nv + 1) / 2;
+    for (int p = threadIdx.x; p < NP; p += 256) {
+        int i = 0, rem = p;
+        while (rem >= nv - i) {
+            rem -= nv - i;
+            i++;
+        }
+        const int j = i + rem;
+        const double re = red[i][j] + red[16 + i][16 + j], imv = red[i][16 + j] - red[16 + i][j];
+        double* o = part + ((long long)q * nblk + blockIdx.x) * 2 * NP;
+        o[2 * p] = re;
+        o[2 * p + 1] = imv;
+    }
+}
+
 // One thread per slot: sum the Gram partials, Cholesky (truncated at the first pivot below
 // 1e-12 G_00: the basis then stops at that column), H, Givens least squares, coefficients.
 // The small FP64 part of an s-step cycle for one system: G (NV x NV Hermitian Gram matrix
@@ -723,6 +815,180 @@ __global__ void k_sstep_solve(const double* __restrict__ part, int nblk, KryStat
     st.est[q] = est;
 }
 
+// The same small solve with one 64-thread block per system and the matrices in LDS (the
+// one-thread form keeps them in private memory, which is slow for 16 x 16).
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cjmul(double2 a, double2 b) {  // conj(a) b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+template <int NV>
+__global__ __launch_bounds__(64) void k_sstep_solve_w(const double* __restrict__ part, int nblk, KryState st,
+                                                      double theta, double sigma, double sqrtN) {
+    constexpr int NP = NV * (NV + 1) / 2;
+    __shared__ double2 G[NV][NV + 1], R[NV][NV + 1], Ri[NV][NV + 1], H[NV][NV + 1];
+    __shared__ double2 g[NV + 1], y[NV];
+    __shared__ int kk_s;
+    __shared__ double cs_c;
+    __shared__ double2 cs_s;
+    const int q = blockIdx.x, t = threadIdx.x;
+    const int m = st.m;
+    // 1. Gram matrix from the block partials
+    for (int p = t; p < NP; p += 64) {
+        double a = 0, b = 0;
+        for (int k = 0; k < nblk; k++) {
+            a += part[((long long)q * nblk + k) * 2 * NP + 2 * p];
+            b += part[((long long)q * nblk + k) * 2 * NP + 2 * p + 1];
+        }
+        int i = 0, rem = p;
+        while (rem >= NV - i) {
+            rem -= NV - i;
+            i++;
+        }
+        const int j = i + rem;
+        G[i][j] = make_double2(a, b);
+        G[j][i] = make_double2(a, -b);
+    }
+    for (int e = t; e < NV * NV; e += 64) R[e / NV][e % NV] = make_double2(0, 0);
+    if (t == 0) kk_s = NV;
+    __syncthreads();
+    // 2. Cholesky G = R^+ R, stopping at the first pivot below 1e-12 G_00
+    const double floor = 1e-12 * G[0][0].x;
+    for (int j = 0; j < NV; j++) {
+        if (t == 0) {
+            double d = G[j][j].x;
+            for (int k = 0; k < j; k++) d -= R[k][j].x * R[k][j].x + R[k][j].y * R[k][j].y;
+            if (!(d > floor))
+                kk_s = j;
+            else
+                R[j][j] = make_double2(sqrt(d), 0);
+        }
+        __syncthreads();
+        if (kk_s <= j) break;
+        for (int l = j + 1 + t; l < NV; l += 64) {
+            double2 v = G[j][l];
+            for (int k = 0; k < j; k++) {
+                const double2 c = cjmul(R[k][j], R[k][l]);
+                v.x -= c.x;
+                v.y -= c.y;
+            }
+            R[j][l] = make_double2(v.x / R[j][j].x, v.y / R[j][j].x);
+        }
+        __syncthreads();
+    }
+    const int ss = kk_s - 1;
+    const double nr = st.g[(long long)q * (m + 1)].x;
+    double2* beta = st.beta + (long long)q * (m + 1);
+    for (int i = t; i <= m; i += 64) beta[i] = make_double2(0, 0);
+    if (ss < 1 || !(nr > 0)) {
+        if (t == 0) {
+            st.kdim[q] = 0;
+            st.est[q] = nr;
+        }
+        return;
+    }
+    // 3. Ri = R_ss^{-1}, one column per thread
+    for (int j = t; j < ss; j += 64) {
+        for (int i = 0; i < ss; i++) Ri[i][j] = make_double2(0, 0);
+        Ri[j][j] = make_double2(1.0 / R[j][j].x, 0);
+        for (int i = j - 1; i >= 0; i--) {
+            double2 v = make_double2(0, 0);
+            for (int k = i + 1; k <= j; k++) {
+                const double2 c = cmul(R[i][k], Ri[k][j]);
+                v.x += c.x;
+                v.y += c.y;
+            }
+            Ri[i][j] = make_double2(-v.x / R[i][i].x, -v.y / R[i][i].x);
+        }
+    }
+    __syncthreads();
+    // 4. H = R T Ri, (T Ri)[k][j] = theta Ri[k][j] + Ri[k-1][j] / sigma
+    for (int e = t; e < (ss + 1) * ss; e += 64) {
+        const int i = e / ss, j = e % ss;
+        double2 h = make_double2(0, 0);
+        for (int k = i; k <= ss; k++) {
+            double2 tr = make_double2(0, 0);
+            if (k < ss) tr = make_double2(theta * Ri[k][j].x, theta * Ri[k][j].y);
+            if (k >= 1) {
+                tr.x += Ri[k - 1][j].x / sigma;
+                tr.y += Ri[k - 1][j].y / sigma;
+            }
+            const double2 c = cmul(R[i][k], tr);
+            h.x += c.x;
+            h.y += c.y;
+        }
+        H[i][j] = h;
+    }
+    for (int i = t; i <= ss; i += 64) g[i] = make_double2(i == 0 ? nr / sqrtN * R[0][0].x : 0.0, 0);
+    __syncthreads();
+    // 5. Givens QR of H against g
+    for (int j = 0; j < ss; j++) {
+        if (t == 0) {
+            const double2 a = H[j][j], b = H[j + 1][j];
+            const double absa = sqrt(a.x * a.x + a.y * a.y), absb = sqrt(b.x * b.x + b.y * b.y);
+            const double r = sqrt(absa * absa + absb * absb);
+            if (r == 0) {
+                cs_c = 1;
+                cs_s = make_double2(0, 0);
+            } else if (absa == 0) {
+                cs_c = 0;
+                cs_s = make_double2(b.x / absb, -b.y / absb);
+            } else {
+                cs_c = absa / r;
+                const double ux = a.x / absa, uy = a.y / absa;
+                cs_s = make_double2((ux * b.x + uy * b.y) / r, (uy * b.x - ux * b.y) / r);
+            }
+        }
+        __syncthreads();
+        const double c = cs_c;
+        const double2 sn = cs_s;
+        for (int l = j + t; l <= ss; l += 64) {  // column l < ss of H, l == ss stands for g
+            const double2 h0 = l < ss ? H[j][l] : g[j], h1 = l < ss ? H[j + 1][l] : g[j + 1];
+            const double2 a0 = make_double2(c * h0.x + sn.x * h1.x - sn.y * h1.y, c * h0.y + sn.x * h1.y + sn.y * h1.x);
+            const double2 a1 =
+                make_double2(-(sn.x * h0.x + sn.y * h0.y) + c * h1.x, -(sn.x * h0.y - sn.y * h0.x) + c * h1.y);
+            if (l < ss) {
+                H[j][l] = a0;
+                H[j + 1][l] = a1;
+            } else {
+                g[j] = a0;
+                g[j + 1] = a1;
+            }
+        }
+        __syncthreads();
+    }
+    // 6. back substitution, then beta = Ri y
+    if (t == 0)
+        for (int i = ss - 1; i >= 0; i--) {
+            double2 v = g[i];
+            for (int l = i + 1; l < ss; l++) {
+                const double2 c = cmul(H[i][l], y[l]);
+                v.x -= c.x;
+                v.y -= c.y;
+            }
+            const double2 d = H[i][i];
+            const double den = d.x * d.x + d.y * d.y;
+            y[i] = den > 0 ? make_double2((v.x * d.x + v.y * d.y) / den, (v.y * d.x - v.x * d.y) / den)
+                           : make_double2(0, 0);
+        }
+    __syncthreads();
+    for (int i = t; i < ss; i += 64) {
+        double2 v = make_double2(0, 0);
+        for (int k = i; k < ss; k++) {
+            const double2 c = cmul(Ri[i][k], y[k]);
+            v.x += c.x;
+            v.y += c.y;
+        }
+        beta[i] = v;
+    }
+    if (t == 0) {
+        st.kdim[q] = ss;
+        st.est[q] = sqrt(g[ss].x * g[ss].x + g[ss].y * g[ss].y) * sqrtN / R[0][0].x;
+    }
+}
+
 // ---------------------------------------------------------------------------- host side
 // chunks of 16 bytes in one slot vector (12 V complex values of S)
 template <typename S>
@@ -784,7 +1050,7 @@ void kry_start_state(lqt_ctx* c, const KryState& st, const int* src, const doubl
 }
 
 // s-step cycle end: Gram of the ns slots' s+1 stored vectors, then the small solves
-constexpr int SGRAM_BLOCKS = 48;
+constexpr int SGRAM_BLOCKS = 64;
 template <typename S>
 void sstep_finish(lqt_ctx* c, const void* Vb, long long vstride, int s, int ns, const KryState& st, double theta,
                   double sigma, DBuf& work) {
@@ -796,6 +1062,13 @@ void sstep_finish(lqt_ctx* c, const void* Vb, long long vstride, int s, int ns, 
     dim3 grid(SGRAM_BLOCKS, ns);
     const double sqrtN = sqrt((double)n);
     c->timer.begin(c->stream, KT_DOTS);
+    // up to 9 vectors the vector-ALU pass is faster (measured 1.25 vs 2.4 ms for 9 BF16
+    // vectors of 128 probes on 16^3x32); longer 16-bit cycles use the matrix cores
+    if (sizeof(S) == 4 && nv > 9) {
+        if (nv > 16) throw Error{LQT_EINVAL, "s-step cycles need restart <= 15"};
+        if constexpr (sizeof(S) == 4)
+            hipLaunchKernelGGL(k_sgram_mf<S>, grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, n, nv, part);
+    } else {
 #define LQT_SSTEP(NV)                                                                                      \
     case NV:                                                                                               \
         hipLaunchKernelGGL((k_sgram<S, NV>), grid, dim3(256), 0, c->stream, (const S*)Vb, vstride, n, part); \
@@ -809,16 +1082,17 @@ void sstep_finish(lqt_ctx* c, const void* Vb, long long vstride, int s, int ns, 
         LQT_SSTEP(7)
         LQT_SSTEP(8)
         LQT_SSTEP(9)
-        default: throw Error{LQT_EINVAL, "s-step cycles need 1 <= restart <= 8"};
+        default: throw Error{LQT_EINVAL, "s-step cycles in FP32/FP64 storage need 1 <= restart <= 8"};
     }
 #undef LQT_SSTEP
+    }
     LQT_HIP(hipGetLastError());
     c->timer.end(c->stream, (double)nv * n * sizeof(S) * ns);
     c->timer.begin(c->stream, KT_KRYLOV);
-#define LQT_SSOLVE(NV)                                                                                          \
-    case NV:                                                                                                    \
-        hipLaunchKernelGGL(k_sstep_solve<NV>, dim3((ns + 63) / 64), dim3(64), 0, c->stream, part, SGRAM_BLOCKS, st, \
-                           ns, theta, sigma, sqrtN);                                                            \
+#define LQT_SSOLVE(NV)                                                                                           \
+    case NV:                                                                                                     \
+        hipLaunchKernelGGL(k_sstep_solve_w<NV>, dim3(ns), dim3(64), 0, c->stream, part, SGRAM_BLOCKS, st, theta, sigma, \
+                           sqrtN);                                                                               \
         break;
     switch (nv) {
         LQT_SSOLVE(2)
@@ -829,6 +1103,13 @@ void sstep_finish(lqt_ctx* c, const void* Vb, long long vstride, int s, int ns, 
         LQT_SSOLVE(7)
         LQT_SSOLVE(8)
         LQT_SSOLVE(9)
+        LQT_SSOLVE(10)
+        LQT_SSOLVE(11)
+        LQT_SSOLVE(12)
+        LQT_SSOLVE(13)
+        LQT_SSOLVE(14)
+        LQT_SSOLVE(15)
+        LQT_SSOLVE(16)
         default: break;
     }
 #undef LQT_SSOLVE

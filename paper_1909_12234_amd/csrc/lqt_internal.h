@@ -382,6 +382,8 @@ void convert_out_c64(lqt_ctx* c, const S* dev, float2* canon, int nrhs);
 void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long in_stride,
             long long out_stride, double shift = 0.0, double scale = 1.0);
 double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen = nullptr);
+// tune the FP64 residual (r = b - A x with norms) for nrhs right-hand sides
+double residual_tune(lqt_ctx* c, int nrhs);
 // FP64 residual r = b - A x for nrhs fields and squared norms (device layout FP64).
 // act maps slot -> field index (nullptr = identity).
 // act (device, may be null) maps slot -> field index of b and x; r is slot-ordered.

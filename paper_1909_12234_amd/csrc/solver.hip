@@ -110,7 +110,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     double theta = 0;
     for (int l = 0; l < nlat; l++) theta += c->g.lat.diag[l] / nlat;
     const double sigma = 0.5;
-    if (o.sstep) c->scratch[13].ensure(sizeof(double) * (size_t)nb * 48 * (m + 1) * (m + 2));  // before any capture
+    if (o.sstep) c->scratch[13].ensure(sizeof(double) * (size_t)nb * 64 * (m + 1) * (m + 2));  // before any capture
     partnb.ensure(sizeof(double) * (size_t)nb * nsb + sizeof(double) * 2 * nb + sizeof(int) * 2 * nb +
                   sizeof(double) * nb + sizeof(double) * (size_t)nb * nlat + 1024);
 
@@ -347,8 +347,8 @@ int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, 
     LQT_CHECK(xi > 0, LQT_EINVAL, "tolerance must be positive");
     LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net requires preconditioner weights (lqt_precond_set/train)");
     LQT_CHECK(!o.use_net || c->g.lat.nlat == 1, LQT_EINVAL, "the network preconditioner serves single-lattice contexts");
-    LQT_CHECK(!o.sstep || (!o.use_net && o.restart <= 8), LQT_EINVAL,
-              "s-step cycles need restart <= 8 and no network preconditioner");
+    LQT_CHECK(!o.sstep || (!o.use_net && o.restart <= (storage_bytes(o.prec) == 4 ? 15 : 8)), LQT_EINVAL,
+              "s-step cycles need restart <= 15 (16-bit storage) or <= 8, and no network preconditioner");
     const long long n = 12LL * c->g.V;
     // batch size: caller cap, else what fits in 70% of free device memory
     size_t fr = 0, tot = 0;

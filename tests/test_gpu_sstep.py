@@ -26,11 +26,32 @@ def test_sstep_solves_match_oracle(gpu, prec, s):
     c.set_gauge(U)
     b = synth.random_spinors(dims, 5, 4).reshape(5, -1)
     bt = torch.as_tensor(b).cuda()
-    x, st, _ = c.solve(bt, xi, prec=prec, restart=s, sstep=1)
+    x, st, _ = c.solve(bt, xi, prec=prec, restart=s, sstep=1, maxit=20000)
     assert all(q[0] for q in st)
     assert np.all(_relres(U, dims, m, b, x.cpu().numpy()) <= xi * 1.05)
     _, st0, _ = c.solve(bt, xi, prec=prec, restart=s)
     # the same Krylov spaces: whole cycles of s steps against GMRES(s) stopping mid-cycle
+    for a, q in zip(st, st0):
+        assert a[1] <= 1.15 * q[1] + 2 * s, (a, q)
+    c.close()
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("s", [12, 15])
+def test_sstep_long_cycles_16bit(gpu, prec, s):
+    """Cycles longer than 8 (16-bit storage: the Gram matrix from the matrix cores)."""
+    lq = gpu
+    dims, m, xi = (4, 4, 6, 8), -0.6, 1e-9
+    print(f"s-step s={s} prec={prec}", flush=True)
+    U = synth.su3_links(dims, 0.5, 3)
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    b = synth.random_spinors(dims, 5, 4).reshape(5, -1)
+    bt = torch.as_tensor(b).cuda()
+    x, st, _ = c.solve(bt, xi, prec=prec, restart=s, sstep=1, maxit=20000)
+    assert all(q[0] for q in st)
+    assert np.all(_relres(U, dims, m, b, x.cpu().numpy()) <= xi * 1.05)
+    _, st0, _ = c.solve(bt, xi, prec=prec, restart=s)
     for a, q in zip(st, st0):
         assert a[1] <= 1.15 * q[1] + 2 * s, (a, q)
     c.close()
@@ -44,7 +65,7 @@ def test_sstep_near_critical_16x8(gpu):
     c = lq.Context(dims, m)
     c.set_gauge(U)
     z = c.probes(77, 8)
-    y, st, _ = c.solve(z, xi, prec=3, restart=8, sstep=1)
+    y, st, _ = c.solve(z, xi, prec=3, restart=8, sstep=1, maxit=20000)
     _, st0, _ = c.solve(z, xi, prec=3, restart=8)
     assert all(q[0] for q in st)
     zs, ys = z[:3].cpu().numpy(), y[:3].cpu().numpy()
@@ -82,6 +103,6 @@ def test_sstep_option_limits(gpu):
     c.set_gauge(synth.su3_links(dims, 0.5, 1))
     b = torch.as_tensor(synth.random_spinors(dims, 1, 1).reshape(1, -1)).cuda()
     with pytest.raises(lq.LqtError) as ei:
-        c.solve(b, 1e-6, restart=9, sstep=1)
+        c.solve(b, 1e-6, restart=9, sstep=1)  # FP64 storage: at most 8
     assert ei.value.code == lq.LQT_EINVAL
     c.close()

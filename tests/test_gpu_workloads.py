@@ -17,7 +17,7 @@ def _relres(U, dims, m, b, x):
 
 
 def test_mixed_16x32_probe_solves(gpu):
-    """16^3x32, m = -1.90, BF16 inner GMRES(8) with FP64 defect correction to 1e-8, in the
+    """16^3x32, m = -1.90, BF16 inner s-step GMRES(8) with FP64 defect correction to 1e-8, in the
     batched launch configuration of the benchmark (128 probes); 4 sampled solutions are
     checked with the oracle operator and their samples z^T y against the oracle's dot."""
     lq = gpu
@@ -28,13 +28,13 @@ def test_mixed_16x32_probe_solves(gpu):
     c = lq.Context(dims, m)
     c.set_gauge(U)
     z = c.probes(w["probe_seed"], 128)
-    y, st, _ = c.solve(z, w["xi"], prec=lq.BF16, restart=w["restart"])
+    y, st, _ = c.solve(z, w["xi"], prec=lq.BF16, restart=w["restart"], sstep=w.get("sstep", 0))
     assert all(s[0] for s in st) and max(s[3] for s in st) <= w["xi"]
     pick = [0, 37, 90, 127]
     zs, ys = z[pick].cpu().numpy(), y[pick].cpu().numpy()
     assert np.array_equal(zs.real, core.probes(w["probe_seed"], 128, zs.shape[1])[pick])
     assert np.all(_relres(U, dims, m, zs, ys) <= w["xi"] * 1.05)
-    r = c.trace(128, w["probe_seed"], w["xi"], samples=True, prec=lq.BF16, restart=w["restart"])
+    r = c.trace(128, w["probe_seed"], w["xi"], samples=True, prec=lq.BF16, restart=w["restart"], sstep=w.get("sstep", 0))
     t = r["samples"].numpy()[pick]
     assert np.max(np.abs(t - np.sum(zs * ys, axis=1))) <= 1e-6 * np.max(np.abs(t))
     c.close()
