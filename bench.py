@@ -2,10 +2,10 @@
 
 One step = one deflated Hutchinson estimate through the C-ABI (lqt_trace): 128 real
 Rademacher probes generated on the device, the deflation projections U^+ z and U^+ g5 z
-against a k = 64 basis of A g5 eigenvectors (FP64 MFMA), batched restarted s-step GMRES(8)
-(basis of hopping-term powers, one Gram pass and an FP64 Cholesky per cycle) with BF16 links
-and Krylov vectors, FP32 arithmetic and FP64 defect correction at every restart until the
-FP64 true residual is <= 1e-8, the probe samples and the estimate.
+against a k = 64 basis of A g5 eigenvectors (FP64 MFMA), batched restarted s-step GMRES(15)
+(basis of hopping-term powers, one Gram pass and an FP64 Cholesky per cycle) with FP16 links
+and Krylov vectors, FP32 accumulation, residuals carried between cycles and FP64 defect
+correction until the FP64 true residual is <= 1e-8, the probe samples and the estimate.
 Gauge field, mass, basis and dslash tiling are set up before the timed region (the
 basis build is reported separately).  Inputs are synthetic (seeded random SU(3) links).
 
@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GMRES comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration) and exit")
+    ap.add_argument("--inner-prec", choices=["f32", "f16", "bf16"], default=None,
+                    help="override the workload's inner storage precision")
     ap.add_argument("--basis-iters", type=int, default=6,
                     help="subspace iterations of the A g5 eigensolver before the timed region (setup budget; "
                          "about 60 reach the Table 1 criterion for all 64 pairs on 16^3x32)")
@@ -85,15 +87,18 @@ def dslash_flops(byt, calls, sites, b):
     return 1392.0 * site_rhs
 
 
-def _measured_traffic(family):
+def _measured_traffic(family, tile=None):
     """HBM bytes per launch of a kernel family from the recorded counter runs, or None when
-    the kernel's source has changed since they were taken (hash mismatch) or none exist."""
+    the kernel's source has changed since they were taken (hash mismatch), the tuned tile is
+    not the one measured, or none exist."""
     import hashlib
 
     try:
         with open(os.path.join(ROOT, "paper_1909_12234_amd", "traffic.json")) as f:
             rec = json.load(f)["kernels"].get(family)
         if rec is None:
+            return None
+        if tile is not None and "tile" in rec and list(rec["tile"]) != list(tile):
             return None
         with open(os.path.join(ROOT, "paper_1909_12234_amd", rec["source"]), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_16"]:
@@ -103,15 +108,17 @@ def _measured_traffic(family):
         return None
 
 
-def _roofline(kt, sites=None, b=None):
+def _roofline(kt, sites=None, b=None, tile=None):
     """Dominant kernel family by device time among those with algorithmic bytes.  The
-    reduced-precision Wilson operator is bound by the vector ALUs, so it is
-    reported against their FMA peak; the other families against HBM."""
+    reduced-precision Wilson operator with FP32 arithmetic on the vector ALUs (tile kind 0) is
+    reported against their FMA peak; the packed-FP16 and matrix-core operators (kinds 2, 1)
+    and the other families against HBM."""
+    kind = tile[3] if tile else 0
     fam = max((f for f in kt if kt[f][2] > 0), key=lambda f: kt[f][0])
     ms, calls, byt = kt[fam]
-    base = {"kernel": fam, "traffic": _measured_traffic(fam), "launches": calls,
+    base = {"kernel": fam, "traffic": _measured_traffic(fam, tile if fam == "dslash" else None), "launches": calls,
             "avg_launch_us": round(ms * 1e3 / max(calls, 1), 2)}
-    if fam == "dslash" and sites and b and b < 8:
+    if fam == "dslash" and sites and b and b < 8 and kind == 0:
         tf = dslash_flops(byt, calls, sites, b) / (ms * 1e-3) / 1e12
         base.update({"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tf / VALU_PEAK_TFLOPS, 4),
@@ -259,6 +266,8 @@ def main():
         return run_net(a, w)
     dims, mass, eps = w["dims"], w["mass"], w["eps"]
     nprobes = a.nprobes or w["nprobes"]
+    if a.inner_prec:
+        w = dict(w, inner_prec=a.inner_prec)
     prec = PREC[w["inner_prec"]]
     V = int(np.prod(dims))
     torch.cuda.set_device(0)
@@ -267,7 +276,7 @@ def main():
     U = synth.su3_links(dims, eps, w["seed"])
     ctx = lq.Context(dims, mass)
     ctx.set_gauge(U)
-    ctx.tune(prec, nprobes)
+    _, tile = ctx.tune(prec, nprobes, return_tile=True)
     ctx.tune(0, 1)
     t_basis = time.perf_counter()
     basis = (ctx.basis_eig(w["k"], xi=1e-2, prec=lq.F32, verbose=1, outer_maxit=a.basis_iters)
@@ -298,7 +307,7 @@ def main():
 
     # roofline of the dominant kernel family (by device time), from live HIP events
     bpr = {0: 8, 1: 4, 2: 2, 3: 2}[prec]  # bytes per real of the inner storage
-    roof = _roofline(kt, V, bpr)
+    roof = _roofline(kt, V, bpr, tile=tile)
     d_ms, d_calls, d_b = kt["dslash"]
     dslash_gbs = d_b / (d_ms * 1e-3) / 1e9 if d_ms > 0 else None
 
@@ -314,7 +323,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": w["inner_prec"],
-        "dtype_detail": f"{w['inner_prec']} links and Krylov vectors, fp32 accumulate, fp64 defect correction",
+        "dtype_detail": f"{w['inner_prec']} links and Krylov vectors, fp32 accumulate, fp64 defect correction"
+                        + (" (operator half spinors in packed fp16)" if tile[3] == 2 else ""),
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: Wilson-Dirac {dims[0]}^3x{dims[3]}, eps={eps}, m={mass}, "
                                f"{nprobes} Rademacher probes, xi={w['xi']}, oblique g5 deflation k={w.get('k', 0)}, "
@@ -324,6 +334,8 @@ def main():
         "dslash_hbm_gbps": round(dslash_gbs, 1) if dslash_gbs else None,
         "dslash_frac_of_peak": round(dslash_gbs / HBM_PEAK_GBS, 4) if dslash_gbs else None,
         "roofline": roof,
+        "dslash_tile": {"per_thread_or_lane": tile[0], "block": tile[1], "chunk": tile[2],
+                        "kernel": {0: "vector ALUs, fp32", 1: "matrix cores", 2: "vector ALUs, packed fp16"}[tile[3]]},
         "kernel_ms": {f: round(kt[f][0], 2) for f in kt},
         "iters_per_probe_mixed": round(iters_mixed, 1),
         "estimate": {"trace": results[-1]["trace_re"], "var_sample": results[-1]["var_sample"],
@@ -337,9 +349,10 @@ def main():
 
     if not a.no_fp64:
         # plain FP64 GMRES, one right-hand side at a time, same probes (a sample of 4), with the
-        # restart length of the timed path and with 32
+        # restart length of the timed path, 8 and 32; the fastest is the reference
         zs = ctx.probes(w["probe_seed"], 4)
-        for m in sorted({w.get("restart", 32), 32}):
+        restarts = sorted({w.get("restart", 32), 8, 32})
+        for m in restarts:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             its = []
@@ -350,7 +363,7 @@ def main():
             rate = zs.shape[0] / (time.perf_counter() - t1)
             out[f"fp64_plain_gmres{m}_solves_per_s"] = round(rate, 3)
             out[f"fp64_plain_gmres{m}_iters_per_probe"] = float(np.mean(its))
-        fp64_rate = max(out[f"fp64_plain_gmres{m}_solves_per_s"] for m in {w.get("restart", 32), 32})
+        fp64_rate = max(out[f"fp64_plain_gmres{m}_solves_per_s"] for m in restarts)
         out["fp64_plain_iters_per_probe"] = out["fp64_plain_gmres32_iters_per_probe"]
         out["speedup_vs_fp64_plain"] = round(value / fp64_rate, 2)
     if not a.no_cpu:

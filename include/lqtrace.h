@@ -90,6 +90,13 @@ typedef struct {
                         hopping term, no Gram-Schmidt between the operator applications),
                         made orthonormal afterwards through one Gram pass and an FP64
                         Cholesky; the same Krylov space and minimisation as GMRES(m) [0]  */
+    double reliable; /* s-step cycles on one lattice: the FP64 residual b - A x is formed
+                        only when the residual carried in the basis (r - A K beta, with
+                        A K = K T from the basis recurrence, written as the next start
+                        vector by the solution update's pass) has fallen below `reliable`
+                        times the last formed one, meets the tolerance, or is not finite;
+                        other cycles start from the carried residual (reliable updates).
+                        Values in (0, 1); negative: form it at every restart [0.1]      */
 } lqt_solver_opts;
 
 /* Per right-hand side solve statistics. */
@@ -324,14 +331,24 @@ int lqt_prolongator_get(const lqt_basis *basis, double *d_w, long long *nc);
 int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const double *d_w,
                                const double *d_coarse, int k, lqt_basis **out);
 
-/* Autotuner: time the candidate dslash tilings (right-hand sides per thread 1/2/4, block
- * 64/128/256 sites, block order: site-block major or chunks of 16/64 site blocks swept per
- * right-hand-side group) for (prec, nrhs) now and cache the choice in the context; *ms
- * receives the best time and tile[0..2] the chosen (rhs per thread, block, chunk); either
- * may be NULL.  Also tunes the FP64 residual of the solvers' restarts (r = b - A x with its
- * norms; 1 or 2 right-hand sides per thread, block order) for nrhs right-hand sides, used
- * for every batch size until tuned again. */
+/* Autotuner: time the candidate dslash tilings for (prec, nrhs) now and cache the choice in
+ * the context.  Candidates: the vector-ALU kernel (kind 0: right-hand sides per thread 1/2/4,
+ * block 64/128/256 threads, block order site-block major or chunks of 16/64 site blocks swept
+ * per right-hand-side group); for FP16/BF16 storage the matrix-core kernel (kind 1: 1 or 2
+ * groups of 4 right-hand sides per lane, 16 sites per wave, same blocks and orders); for FP16
+ * storage the vector kernel with packed half-precision arithmetic (kind 2: the half spinors
+ * rounded to FP16, link products as FP16 dot products accumulated in FP32; tiles as kind 0).  *ms
+ * receives the best time and tile[0..3] the chosen (rhs per thread or groups per lane, block,
+ * chunk, kind); either may be NULL.  Also tunes the FP64 residual of the solvers' restarts
+ * (r = b - A x with its norms; 1 or 2 right-hand sides per thread, block order) for nrhs
+ * right-hand sides, used for every batch size until tuned again. */
 int lqt_tune(lqt_ctx *ctx, int prec, int nrhs, double *ms, int *tile);
+
+/* Set the dslash tiling used for (prec, nrhs) without timing: tile[0..3] as lqt_tune reports
+ * it (kind 1 only for LQT_F16 and LQT_BF16, with 1 or 2 groups per lane; kind 2 only for
+ * LQT_F16).  LQT_EINVAL for a
+ * tiling the kernels do not have. */
+int lqt_set_tile(lqt_ctx *ctx, int prec, int nrhs, const int *tile);
 
 /* Kernel timers: HIP event pairs recorded around the library's launches on the context
  * stream, summed per kernel family: 0 Wilson operator of the inner cycles, 1 CGS dot

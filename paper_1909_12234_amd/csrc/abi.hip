@@ -229,7 +229,29 @@ int lqt_tune(lqt_ctx* c, int prec, int nrhs, double* ms, int* tile) {
             tile[0] = t.rhs_per_thread;
             tile[1] = t.block;
             tile[2] = t.chunk;
+            tile[3] = t.kind;
         }
+    });
+}
+
+int lqt_set_tile(lqt_ctx* c, int prec, int nrhs, const int* tile) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(prec >= LQT_F64 && prec <= LQT_BF16 && nrhs >= 1 && tile, LQT_EINVAL, "bad tiling request");
+        lqt::Tuned t{tile[0], tile[1], tile[2]};
+        t.kind = tile[3];
+        LQT_CHECK(t.block == 64 || t.block == 128 || t.block == 256, LQT_EINVAL, "block must be 64, 128 or 256");
+        LQT_CHECK(t.chunk >= 0, LQT_EINVAL, "chunk must be >= 0");
+        if (t.kind == 0 || t.kind == 2) {
+            LQT_CHECK(t.rhs_per_thread == 1 || t.rhs_per_thread == 2 || (t.rhs_per_thread == 4 && prec != LQT_F64),
+                      LQT_EINVAL, "rhs per thread must be 1, 2 or 4 (1 or 2 for FP64)");
+            LQT_CHECK(t.kind == 0 || prec == LQT_F16, LQT_EINVAL, "packed half-precision arithmetic takes FP16 storage");
+        } else {
+            LQT_CHECK(t.kind == 1 && (prec == LQT_F16 || prec == LQT_BF16), LQT_EINVAL,
+                      "the matrix-core kernel takes FP16 or BF16 storage");
+            LQT_CHECK(t.rhs_per_thread == 1 || t.rhs_per_thread == 2, LQT_EINVAL, "groups per lane must be 1 or 2");
+        }
+        c->tuned[lqt::tune_key(prec, nrhs)] = t;
     });
 }
 

@@ -16,6 +16,7 @@
 // One thread owns one site and R right-hand sides: each link is loaded once and applied
 // to R spinors.  Algorithmic traffic per site: 72 link reals + R*(24 in + 24 out) reals.
 #include "blas.h"
+#include "dslash_mfma.h"
 #include "lqt_internal.h"
 
 namespace lqt {
@@ -190,10 +191,120 @@ __device__ __forceinline__ void hop_dir(const S* __restrict__ U, const S* const 
     }
 }
 
+// ---- FP16 storage with packed half-precision arithmetic (kind 2 of the tuner)
+// The spin projection h = p_a + c p_b (c = +-1, +-i) is one packed FP16 add per complex
+// number (its result rounded to FP16), and each complex product with a link element is a
+// pair of FP16 dot products accumulated in FP32: Re(U h) = U . (Re h, -Im h),
+// Im(U h) = U . (Im h, Re h) with U = (Re U, Im U) as stored; for U^+ the pairs are
+// (Re h, Im h) and (Im h, -Re h).  Links and neighbour spinors are used as loaded.
+typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ hv2 ldh(const h2* base, uint32_t i) {
+    return __builtin_bit_cast(hv2, *(const uint32_t*)((const char*)base + i * 4u));
+}
+// c q for c = CRE + i CIM in {+-1, +-i}
+template <int CRE, int CIM>
+__device__ __forceinline__ hv2 cmul_unit(hv2 q) {
+    if constexpr (CRE == 1) return q;
+    else if constexpr (CRE == -1) return -q;
+    else if constexpr (CIM == 1) return hv2{-q.y, q.x};
+    else return hv2{q.y, -q.x};
+}
+// the two operand forms of h = a + c b for the dot products: forward link (Re h, -Im h),
+// (Im h, Re h); backward link (Re h, Im h), (Im h, -Re h)
+template <bool BWD, int CRE, int CIM>
+__device__ __forceinline__ void hforms(hv2 a, hv2 b, hv2& f0, hv2& f1) {
+    const hv2 cb = cmul_unit<CRE, CIM>(b);
+    if constexpr (!BWD) {
+        f0 = hv2{a.x, -a.y} + hv2{cb.x, -cb.y};
+        f1 = hv2{a.y, a.x} + hv2{cb.y, cb.x};
+    } else {
+        f0 = a + cb;
+        f1 = hv2{a.y, -a.x} + hv2{cb.y, -cb.x};
+    }
+}
+// coefficient c of the projection (1 + SG g_MU) rows h0 (k = 0) and h1 (k = 1), and the spin
+// of p_b: the same rules as project<MU, SG>
+template <int MU, int SG, int K>
+struct pk_rule {
+    static constexpr int pb = MU == 0 ? (K == 0 ? 3 : 2) : MU == 1 ? (K == 0 ? 3 : 2) : MU == 2 ? (K == 0 ? 2 : 3) : (K == 0 ? 2 : 3);
+    static constexpr int cre = MU == 1 ? (K == 0 ? -SG : SG) : MU == 3 ? SG : 0;
+    static constexpr int cim = MU == 0 ? SG : MU == 2 ? (K == 0 ? SG : -SG) : 0;
+};
+
+template <int MU, int SG, bool BWD, int K>
+__device__ __forceinline__ void pk_half(const hv2 u[9], const hv2 p[12], cpx<float> o[3]) {
+    using Rl = pk_rule<MU, SG, K>;
+    hv2 f0[3], f1[3];
+#pragma unroll
+    for (int b = 0; b < 3; b++) hforms<BWD, Rl::cre, Rl::cim>(p[3 * K + b], p[3 * Rl::pb + b], f0[b], f1[b]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            const hv2 l = BWD ? u[3 * b + a] : u[3 * a + b];
+            re = __builtin_amdgcn_fdot2(l, f0[b], re, false);
+            im = __builtin_amdgcn_fdot2(l, f1[b], im, false);
+        }
+        o[a] = {re, im};
+    }
+}
+
+template <int MU, bool DAG, int R>
+__device__ __forceinline__ void hop_dir_pk(const h2* __restrict__ U, const h2* const inb[R], uint32_t V, uint32_t s,
+                                           uint32_t sf, uint32_t sb, int nr, bool g5in, cpx<float> acc[R][12]) {
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const h2* Um = U + (long long)MU * 9 * V;
+    hv2 u[9], p[12];
+    cpx<float> o0[3], o1[3];
+#pragma unroll
+    for (int i = 0; i < 9; i++) u[i] = ldh(Um, i * V + s);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (r < nr) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                p[c] = ldh(inb[r], c * V + sf);
+                if (g5in && c >= 6) p[c] = -p[c];
+            }
+            pk_half<MU, SF, false, 0>(u, p, o0);
+            pk_half<MU, SF, false, 1>(u, p, o1);
+            rebuild_add<MU, SF>(acc[r], o0, o1);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; i++) u[i] = ldh(Um, i * V + sb);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (r < nr) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                p[c] = ldh(inb[r], c * V + sb);
+                if (g5in && c >= 6) p[c] = -p[c];
+            }
+            pk_half<MU, SB, true, 0>(u, p, o0);
+            pk_half<MU, SB, true, 1>(u, p, o1);
+            rebuild_add<MU, SB>(acc[r], o0, o1);
+        }
+    }
+}
+
+// one direction on the vector ALUs: FP32 arithmetic, or packed FP16 arithmetic (PKH, FP16 storage)
+template <int MU, bool DAG, int R, typename S, typename C, bool PKH>
+__device__ __forceinline__ void hop_any(const S* __restrict__ U, const S* const inb[R], uint32_t V, uint32_t s,
+                                        uint32_t sf, uint32_t sb, int nr, bool g5in, cpx<C> acc[R][12]) {
+    if constexpr (PKH)
+        hop_dir_pk<MU, DAG, R>(U, inb, V, s, sf, sb, nr, g5in, acc);
+    else
+        hop_dir<MU, DAG, R, S, C>(U, inb, V, s, sf, sb, nr, g5in, acc);
+}
+
 // EPI 0: out = op(in).  EPI 1 (FP64 only): out = b - A in, with per-block partial |out|^2.
 // Right-hand side r of a group is field act[r0 + r] (act may be null: r0 + r) of in and b,
 // and field r0 + r of out.  Sites of the lattice table tab; padding sites get zeros.
-template <typename S, int R, int OPK, int EPI>
+template <typename S, int R, int OPK, int EPI, bool PKH = false>
 __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S* __restrict__ in, S* __restrict__ out,
                                                 const S* __restrict__ bvec, double* __restrict__ part,
                                                 const int* __restrict__ act, LatTab tab, int nrhs, long long in_stride,
@@ -270,10 +381,10 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
             const uint32_t zb = (z == 0) ? s + (L2 - 1) * s2 : s - s2;
             const uint32_t tf = (t == L3 - 1) ? s - (L3 - 1) * s3 : s + s3;
             const uint32_t tb = (t == 0) ? s + (L3 - 1) * s3 : s - s3;
-            hop_dir<0, DAG, R, S, C>(U, inb, V, s, xf, xb, nr, g5in, acc);
-            hop_dir<1, DAG, R, S, C>(U, inb, V, s, yf, yb, nr, g5in, acc);
-            hop_dir<2, DAG, R, S, C>(U, inb, V, s, zf, zb, nr, g5in, acc);
-            hop_dir<3, DAG, R, S, C>(U, inb, V, s, tf, tb, nr, g5in, acc);
+            hop_any<0, DAG, R, S, C, PKH>(U, inb, V, s, xf, xb, nr, g5in, acc);
+            hop_any<1, DAG, R, S, C, PKH>(U, inb, V, s, yf, yb, nr, g5in, acc);
+            hop_any<2, DAG, R, S, C, PKH>(U, inb, V, s, zf, zb, nr, g5in, acc);
+            hop_any<3, DAG, R, S, C, PKH>(U, inb, V, s, tf, tb, nr, g5in, acc);
         }
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -320,7 +431,7 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
     }
 }
 
-template <typename S, int R>
+template <typename S, int R, bool PKH = false>
 static void launch_R(lqt_ctx* c, int op, const S* U, const S* in, S* out, int nrhs, long long is, long long os,
                      int bs, int chunk, double shift, double scale) {
     const Geom& g = c->g;
@@ -328,7 +439,7 @@ static void launch_R(lqt_ctx* c, int op, const S* U, const S* in, S* out, int nr
     int ngrp = (nrhs + R - 1) / R;
     int nl = nsb * ngrp;
 #define LQT_DSLASH_OP(OPK)                                                                                   \
-    hipLaunchKernelGGL((k_dslash<S, R, OPK, 0>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,        \
+    hipLaunchKernelGGL((k_dslash<S, R, OPK, 0, PKH>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,   \
                        (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.lat, nrhs, is, os, chunk, shift,  \
                        scale)
     switch (op) {
@@ -371,7 +482,7 @@ static void launch_prec(lqt_ctx* c, int op, const void* in, void* out, int nrhs,
     }
 }
 
-static long long tune_key(int prec, int nrhs) { return ((long long)prec << 32) | (unsigned)nrhs; }
+long long tune_key(int prec, int nrhs) { return ((long long)prec << 32) | (unsigned)nrhs; }
 
 static Tuned default_tile(int prec, int nrhs) {
     Tuned t;
@@ -384,8 +495,33 @@ static Tuned default_tile(int prec, int nrhs) {
     return t;
 }
 
+static void launch_pkh(lqt_ctx* c, int op, const void* in, void* out, int nrhs, long long is, long long os,
+                       const Tuned& t, double shift, double scale) {
+    const h2* U = gauge_of<h2>(c);
+    switch (t.rhs_per_thread) {
+        case 1:
+            launch_R<h2, 1, true>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
+            break;
+        case 2:
+            launch_R<h2, 2, true>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
+            break;
+        default:
+            launch_R<h2, 4, true>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
+            break;
+    }
+}
+
 static void dslash_cfg(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long is, long long os,
                        Tuned t, double shift = 0.0, double scale = 1.0) {
+    if (t.kind == 1) {
+        dslash_mf(c, prec, op, in, out, nrhs, is, os, t, shift, scale);
+        return;
+    }
+    if (t.kind == 2) {
+        LQT_CHECK(prec == LQT_F16, LQT_EINVAL, "packed half-precision dslash: FP16 storage only");
+        launch_pkh(c, op, in, out, nrhs, is, os, t, shift, scale);
+        return;
+    }
     switch (prec) {
         case LQT_F64: launch_prec<double2>(c, op, in, out, nrhs, is, os, t, shift, scale); break;
         case LQT_F32: launch_prec<float2>(c, op, in, out, nrhs, is, os, t, shift, scale); break;
@@ -423,24 +559,36 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen) {
     LQT_HIP(hipEventCreate(&e1));
     double best = 1e30;
     Tuned bt = default_tile(prec, nrhs);
-    for (int ri = 0; ri < 3; ri++) {
-        if (Rs[ri] > nrhs) continue;
-        if (prec == LQT_F64 && Rs[ri] > 2) continue;
-        for (int bi = 0; bi < 3; bi++)
-        for (int ci = 0; ci < 3; ci++) {
-            Tuned t{Rs[ri], Bs[bi], Cs[ci]};
-            dslash_cfg(c, prec, LQT_A, a.p, b.p, nrhs, n, n, t);  // warm
-            LQT_HIP(hipEventRecord(e0, c->stream));
-            const int reps = 5;
-            for (int k = 0; k < reps; k++) dslash_cfg(c, prec, LQT_A, a.p, b.p, nrhs, n, n, t);
-            LQT_HIP(hipEventRecord(e1, c->stream));
-            LQT_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            LQT_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms / reps < best) {
-                best = ms / reps;
-                bt = t;
-            }
+    // candidates: vector kernel (R right-hand sides per thread), for 16-bit storage the
+    // matrix-core kernel (R groups of 4 right-hand sides per lane), for FP16 storage the
+    // vector kernel with packed half-precision arithmetic
+    std::vector<Tuned> cand;
+    for (int kind = 0; kind < 3; kind++)
+        for (int ri = 0; ri < 3; ri++) {
+            if (kind == 0 && (Rs[ri] > nrhs || (prec == LQT_F64 && Rs[ri] > 2))) continue;
+            if (kind == 2 && (prec != LQT_F16 || Rs[ri] > nrhs)) continue;
+            if (kind == 1 && (prec == LQT_F64 || prec == LQT_F32 || Rs[ri] > 2 || (Rs[ri] == 2 && nrhs <= 4) ||
+                              !dslash_mf_fits(c->g, Rs[ri], n, n)))
+                continue;
+            for (int bi = 0; bi < 3; bi++)
+                for (int ci = 0; ci < 3; ci++) {
+                    Tuned t{Rs[ri], Bs[bi], Cs[ci]};
+                    t.kind = kind;
+                    cand.push_back(t);
+                }
+        }
+    for (const Tuned& t : cand) {
+        dslash_cfg(c, prec, LQT_A, a.p, b.p, nrhs, n, n, t);  // warm
+        LQT_HIP(hipEventRecord(e0, c->stream));
+        const int reps = 5;
+        for (int k = 0; k < reps; k++) dslash_cfg(c, prec, LQT_A, a.p, b.p, nrhs, n, n, t);
+        LQT_HIP(hipEventRecord(e1, c->stream));
+        LQT_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        LQT_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / reps < best) {
+            best = ms / reps;
+            bt = t;
         }
     }
     (void)hipEventDestroy(e0);

@@ -39,6 +39,14 @@ int kry_blocks(const lqt_ctx* c);
 void kry_finish(lqt_ctx* c, const double2* part, int nsb, int j, int ns, const KryState& st, int pass);
 void kry_norm_givens(lqt_ctx* c, const double* part, int nsb, int j, int ns, const KryState& st);
 void kry_backsolve(lqt_ctx* c, int ns, const KryState& st);
+// s-step cycle end with the residual carried in the basis: x[act[q]] += K_s beta and
+// k_0 <- (r - A K_s beta) sqrt(N)/est; rn2[q] = |r - A K_s beta|^2 (part: ns * ceil(V/256)
+// doubles of workspace)
+template <typename S>
+void kry_sstep_carry(lqt_ctx* c, double2* x, const int* act, void* Kb, long long kstride, int ns, const KryState& st,
+                     double theta, double sigma, double* part, double* rn2);
+// cycle state of slots starting from the carried residual
+void kry_start_state_carry(lqt_ctx* c, const KryState& st, const double* target_abs, int ns);
 void kry_start_state(lqt_ctx* c, const KryState& st, const int* src, const double* rn2, const double* target_abs,
                      int ns);
 // s-step cycle end (vectors k_0..k_s of ns slots, A k_i = k_{i+1}/sigma + theta k_i): Gram,

@@ -483,6 +483,108 @@ __global__ __launch_bounds__(256) void k_xupdate(double2* __restrict__ x, const 
     for (int c = 0; c < 12; c++) xq[(long long)c * V + s] = acc[c];
 }
 
+// End of an s-step cycle that carries the residual in the basis (reliable updates): with
+// beta the cycle's coefficients (x += K_s beta) and A k_i = k_{i+1}/sigma + theta k_i for the
+// stored vectors, the new residual is r - A K_s beta = rho k_0 - K_{s+1} gamma, gamma = T beta
+// (gamma_i = theta beta_i + beta_{i-1}/sigma), rho = |r|/sqrt(N) of the cycle's start.  It is
+// written over k_0 scaled by sqrt(N)/est (est: the cycle's least-squares residual norm, which
+// the next cycle takes as its |r|), so x and the next start vector come from one pass over
+// the basis.  part[q * gridDim.x + blk] = partial |r_new|^2 of the block's 256 sites.
+template <typename S>
+__global__ __launch_bounds__(256) void k_sstep_carry(double2* __restrict__ x, const int* __restrict__ act,
+                                                     S* __restrict__ Kb, long long kstride, int V, KryState st,
+                                                     double theta, double sigma, double sqrtN,
+                                                     double* __restrict__ part) {
+    __shared__ double2 bx[KRY_MAXM + 1], wk[KRY_MAXM + 1];
+    __shared__ double red[256];
+    const int q = blockIdx.y;
+    const int m = st.m;
+    const int kd = st.kdim[q];
+    if (threadIdx.x <= kd) {
+        const int i = threadIdx.x;
+        const double2* beta = st.beta + (long long)q * (m + 1);
+        const double2 bi = i < kd ? beta[i] : make_double2(0, 0);
+        const double2 bm = i >= 1 ? beta[i - 1] : make_double2(0, 0);
+        const double est = st.est[q];
+        const double f = est > 0 ? sqrtN / est : 0.0;
+        const double rho = i == 0 ? st.g[(long long)q * (m + 1)].x / sqrtN : 0.0;
+        bx[i] = bi;
+        wk[i] = make_double2((rho - theta * bi.x - bm.x / sigma) * f, (-theta * bi.y - bm.y / sigma) * f);
+    }
+    __syncthreads();
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    double nrm = 0;
+    if (s < V) {
+        const long long n = 12LL * V;
+        double2* xq = x + (long long)act[q] * n;
+        S* k0 = Kb + q * n;
+        double2 ax[12], ak[12];
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            ax[c] = xq[(long long)c * V + s];
+            ak[c] = make_double2(0, 0);
+        }
+        for (int i = 0; i <= kd; i++) {
+            const double2 b = bx[i], w = wk[i];
+            const S* ki = Kb + (long long)i * kstride + q * n;
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                const cx<double> v = ldk<S, double>(ki + (long long)c * V + s);
+                ax[c].x += b.x * v.x - b.y * v.y;
+                ax[c].y += b.x * v.y + b.y * v.x;
+                ak[c].x += w.x * v.x - w.y * v.y;
+                ak[c].y += w.x * v.y + w.y * v.x;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            xq[(long long)c * V + s] = ax[c];
+            stk<S, double>(k0 + (long long)c * V + s, cx<double>{ak[c].x, ak[c].y});
+            nrm += ak[c].x * ak[c].x + ak[c].y * ak[c].y;
+        }
+    }
+    red[threadIdx.x] = nrm;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double sc = st.est[q] / sqrtN;
+        part[(long long)q * gridDim.x + blockIdx.x] = red[0] * sc * sc;
+    }
+}
+
+// rn2[q] = sum of the nblk partials of slot q (fixed order)
+__global__ void k_carry_norms(const double* __restrict__ part, int nblk, double* __restrict__ rn2) {
+    __shared__ double red[256];
+    const int q = blockIdx.x;
+    double v = 0;
+    for (int i = threadIdx.x; i < nblk; i += 256) v += part[(long long)q * nblk + i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rn2[q] = red[0];
+}
+
+// Cycle state of a slot that starts from the carried residual: k_0 already holds r sqrt(N)/est
+// (est of the previous cycle), so |r| is taken as est.
+__global__ void k_start_state_carry(KryState st, const double* __restrict__ target_abs, int ns, double sqrtN) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ns) return;
+    const int m = st.m;
+    const double nr = st.est[q];
+    st.sc[(long long)q * (m + 1)] = 1.0 / sqrtN;
+    st.g[(long long)q * (m + 1)] = make_double2(nr, 0);
+    for (int i = 1; i <= m; i++) st.g[(long long)q * (m + 1) + i] = make_double2(0, 0);
+    st.kdim[q] = 0;
+    st.frozen[q] = nr > 0 ? 0 : 1;
+    st.target[q] = target_abs[q];
+}
+
 // vhat_0[q] = r[src[q]] * sqrt(N)/|r|, in storage S.  Also resets the slot's cycle state.
 template <typename S>
 __global__ __launch_bounds__(256) void k_start(S* __restrict__ V0, const double2* __restrict__ r,
@@ -607,6 +709,9 @@ __global__ __launch_bounds__(256) void k_sgram_mf(const S* __restrict__ Vb, long
     const int vec = row & 15, im = row >> 4;
     const bool live = vec < nv;
     const uint32_t* base = (const uint32_t*)(Vb + (live ? vec : 0) * vstride + q * n);
+    // a wave takes GU consecutive groups of 16 elements per pass (256 contiguous bytes of each
+    // vector, all loads issued before the products)
+    constexpr int GU = 4;
     const long long ngroups = (n + 15) / 16;
     const long long wid = (long long)blockIdx.x * 4 + wave, nw = (long long)nblk * 4;
     lqt_f16v acc = {};
@@ -614,18 +719,24 @@ __global__ __launch_bounds__(256) void k_sgram_mf(const S* __restrict__ Vb, long
 #pragma unroll
     for (int v = 0; v < 16; v++) accd[v] = 0;
     int cnt = 0;
-    for (long long g = wid; g < ngroups; g += nw) {
-        const long long e = g * 16 + half * 8;
-        uint32_t w[8];
-        if (live && e + 8 <= n) {
-            const uint4 a = *(const uint4*)(base + e), b = *(const uint4*)(base + e + 4);
-            w[0] = a.x, w[1] = a.y, w[2] = a.z, w[3] = a.w, w[4] = b.x, w[5] = b.y, w[6] = b.z, w[7] = b.w;
-        } else {
+    for (long long g0 = wid * GU; g0 < ngroups; g0 += nw * GU) {
+        uint32_t w[GU][8];
 #pragma unroll
-            for (int t = 0; t < 8; t++) w[t] = (live && e + t < n) ? base[e + t] : 0u;
+        for (int u = 0; u < GU; u++) {
+            const long long e = (g0 + u) * 16 + half * 8;
+            if (live && e + 8 <= n) {
+                const uint4 a = *(const uint4*)(base + e), b = *(const uint4*)(base + e + 4);
+                w[u][0] = a.x, w[u][1] = a.y, w[u][2] = a.z, w[u][3] = a.w;
+                w[u][4] = b.x, w[u][5] = b.y, w[u][6] = b.z, w[u][7] = b.w;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; t++) w[u][t] = (live && e + t < n) ? base[e + t] : 0u;
+            }
         }
-        acc = mfma_xxt<S>(w, im, acc);
-        if (++cnt == 64) {
+#pragma unroll
+        for (int u = 0; u < GU; u++) acc = mfma_xxt<S>(w[u], im, acc);
+        cnt += GU;
+        if (cnt >= 64) {
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 accd[v] += acc[v];
@@ -1030,6 +1141,23 @@ void kry_start(lqt_ctx* c, void* V0, const double2* r, const int* src, const dou
     LQT_HIP(hipGetLastError());
 }
 
+template <typename S>
+void kry_sstep_carry(lqt_ctx* c, double2* x, const int* act, void* Kb, long long kstride, int ns, const KryState& st,
+                     double theta, double sigma, double* part, double* rn2) {
+    const int nblk = (c->g.V + 255) / 256;
+    dim3 grid(nblk, ns);
+    hipLaunchKernelGGL(k_sstep_carry<S>, grid, dim3(256), 0, c->stream, x, act, (S*)Kb, kstride, c->g.V, st, theta,
+                       sigma, sqrt(12.0 * c->g.V), part);
+    LQT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_carry_norms, dim3(ns), dim3(256), 0, c->stream, part, nblk, rn2);
+    LQT_HIP(hipGetLastError());
+}
+void kry_start_state_carry(lqt_ctx* c, const KryState& st, const double* target_abs, int ns) {
+    hipLaunchKernelGGL(k_start_state_carry, dim3((ns + 63) / 64), dim3(64), 0, c->stream, st, target_abs, ns,
+                       sqrt(12.0 * c->g.V));
+    LQT_HIP(hipGetLastError());
+}
+
 void kry_finish(lqt_ctx* c, const double2* part, int nsb, int j, int ns, const KryState& st, int pass) {
     hipLaunchKernelGGL(k_cgs_finish, dim3(ns), dim3(256), 0, c->stream, part, nsb, j, st, pass, sqrt(12.0 * c->g.V));
     LQT_HIP(hipGetLastError());
@@ -1124,6 +1252,8 @@ void sstep_finish(lqt_ctx* c, const void* Vb, long long vstride, int s, int ns, 
     template void kry_xupdate<S>(lqt_ctx*, double2*, const int*, const void*, long long, int,            \
                                  const KryState&);                                                      \
     template void kry_start<S>(lqt_ctx*, void*, const double2*, const int*, const double*, int);        \
+    template void kry_sstep_carry<S>(lqt_ctx*, double2*, const int*, void*, long long, int, const KryState&, double, \
+                                     double, double*, double*);                                                     \
     template void sstep_finish<S>(lqt_ctx*, const void*, long long, int, int, const KryState&, double, double, \
                                   DBuf&);
 INST(double2)

@@ -7,7 +7,7 @@ namespace lqt {
 // One thread per link of the canonical field (lattices one after the other, each
 // [site][mu][a][b]): check U^+U = 1 and det U = 1, fold the antiperiodic sign into the last
 // time slice of its lattice, scatter into [mu][ab][V] at the lattice's device sites for
-// every storage precision.
+// every storage precision (FP32 and FP16 rounded from FP64, BF16 from the FP32 value).
 __global__ void k_gauge_ingest(const double2* __restrict__ canon, LatTab t, long long nlinks, int antiperiodic,
                                double2* __restrict__ u64, float2* __restrict__ u32, h2* __restrict__ u16,
                                b2* __restrict__ ubf, double* __restrict__ err_unit, double* __restrict__ err_det) {
@@ -57,7 +57,11 @@ __global__ void k_gauge_ingest(const double2* __restrict__ canon, LatTab t, long
             u64[o] = v;
             float2 f = make_float2((float)v.x, (float)v.y);
             u32[o] = f;
-            io<h2>::st(u16 + o, f);
+            // FP16: rounded once from FP64 (to nearest even); BF16: from the FP32 value
+            h2 hv;
+            hv.x = __half_raw{static_cast<_Float16>(v.x)};
+            hv.y = __half_raw{static_cast<_Float16>(v.y)};
+            u16[o] = hv;
             io<b2>::st(ubf + o, f);
         }
     }

@@ -310,7 +310,8 @@ struct KTimer {
 struct Tuned {
     int rhs_per_thread;
     int block;
-    int chunk;  // site blocks per sweep (0: site-block-major order)
+    int chunk;     // site blocks per sweep (0: site-block-major order)
+    int kind = 0;  // 0 vector-ALU kernel, 1 matrix-core kernel (16-bit storage)
 };
 
 struct Net {
@@ -382,6 +383,8 @@ void convert_out_c64(lqt_ctx* c, const S* dev, float2* canon, int nrhs);
 void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long in_stride,
             long long out_stride, double shift = 0.0, double scale = 1.0);
 double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen = nullptr);
+// key of the tuned-tile map for (precision, right-hand sides)
+long long tune_key(int prec, int nrhs);
 // tune the FP64 residual (r = b - A x with norms) for nrhs right-hand sides
 double residual_tune(lqt_ctx* c, int nrhs);
 // FP64 residual r = b - A x for nrhs fields and squared norms (device layout FP64).

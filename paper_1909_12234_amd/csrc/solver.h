@@ -16,6 +16,7 @@ struct SolveOpts {
     int outer_maxit = 60;
     int graph = 0;
     int sstep = 0;
+    double reliable = 0.1;  // 0: the FP64 residual at every restart
 };
 
 SolveOpts make_opts(const lqt_solver_opts* u);

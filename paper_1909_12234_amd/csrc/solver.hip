@@ -112,7 +112,9 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     const double sigma = 0.5;
     if (o.sstep) c->scratch[13].ensure(sizeof(double) * (size_t)nb * 64 * (m + 1) * (m + 2));  // before any capture
     partnb.ensure(sizeof(double) * (size_t)nb * nsb + sizeof(double) * 2 * nb + sizeof(int) * 2 * nb +
-                  sizeof(double) * nb + sizeof(double) * (size_t)nb * nlat + 1024);
+                  sizeof(double) * nb + sizeof(double) * (size_t)nb * nlat + sizeof(double) * nb + 1024);
+    // s-step cycles on one lattice carry the residual in the basis between FP64 residuals
+    const bool carry = o.sstep && o.reliable > 0 && !multi;
 
     double2* r = rb.as<double2>();
     char* extra = (char*)partnb.p + sizeof(double) * (size_t)nb * nsb;
@@ -122,14 +124,16 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     int* src_d = act_d + nb;
     double* tgt_d = (double*)(((uintptr_t)(src_d + nb) + 7) & ~uintptr_t(7));
     double* rn2l = tgt_d + nb;  // [slot][lattice]
+    double* rn2c = rn2l + (size_t)nb * nlat;  // |carried residual|^2 per slot
     double* partn = partnb.as<double>();
     double2* part = partb.as<double2>();
     void* basis = basisb.p;
 
-    c->pinned.ensure(sizeof(double) * (4 + (size_t)nlat) * nb + 64);
+    c->pinned.ensure(sizeof(double) * (5 + (size_t)nlat) * nb + 64);
     double* h_rn2 = c->pinned.as<double>();
     int* h_flags = (int*)(h_rn2 + nb);
     double* h_rn2l = h_rn2 + 2 * (size_t)nb;
+    double* h_rn2c = h_rn2l + (size_t)nlat * nb;
 
     std::vector<double> bnorm(nb);
     c->timer.begin(c->stream, KT_KRYLOV);
@@ -158,77 +162,107 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         }
     } graphs;
     std::vector<int> act(nb), its(nb, 0), cyc(nb, 0), done(nb, 0);
-    std::vector<double> rel(nb, 1.0);
+    std::vector<double> rel(nb, 1.0), rlast(nb, 0.0);
     for (int i = 0; i < nb; i++) act[i] = i;
     int nfail = 0;
-    const double sqrtN = std::sqrt((double)n);
-    (void)sqrtN;
+    bool carried = false;  // the basis start vectors hold the residuals carried from the last cycle
 
     while (!act.empty()) {
         const int na = (int)act.size();
-        LQT_HIP(hipMemcpyAsync(act_d, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
-        residual64(c, b, x, r, rn2, na, act_d, multi ? rn2l : nullptr);
-        LQT_HIP(hipMemcpyAsync(h_rn2, rn2, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream));
-        if (multi)
-            LQT_HIP(hipMemcpyAsync(h_rn2l, rn2l, sizeof(double) * na * nlat, hipMemcpyDeviceToHost, c->stream));
-        LQT_HIP(hipStreamSynchronize(c->stream));
-        std::vector<int> nact, src;
-        std::vector<double> tgt;
-        for (int k = 0; k < na; k++) {
+        // A cycle may start from the carried residual unless some system's carried residual
+        // meets the tolerance, fell below `reliable` times its last FP64 residual, is not
+        // finite or the step cap is reached: then every active system gets its FP64 residual.
+        bool from_carry = carried;
+        for (int k = 0; k < na && from_carry; k++) {
             const int i = act[k];
-            cyc[i]++;
-            double rr = std::sqrt(h_rn2[k]);
-            rel[i] = bnorm[i] > 0 ? rr / bnorm[i] : 0.0;
-            double bmin = bnorm[i];  // the cycle target must serve the smallest lattice block
-            if (multi) {
-                double worst = 0;
-                for (int l = 0; l < nlat; l++) {
-                    const double bl = bnl[(size_t)i * nlat + l], rl = std::sqrt(h_rn2l[(size_t)k * nlat + l]);
-                    if (bl > 0) {
-                        worst = std::max(worst, rl / bl);
-                        bmin = std::min(bmin, bl);
-                    } else if (!(rl == rl)) {
-                        worst = rl;
-                    }
-                }
-                rel[i] = (rr == rr) ? worst : rr;
-            }
-            if (!(rel[i] == rel[i])) {
-                done[i] = 1;
-                nfail++;
-                continue;
-            }
-            if (rel[i] <= xi) {
-                done[i] = 1;
-                continue;
-            }
-            if (its[i] >= o.maxit) {
-                done[i] = 1;
-                nfail++;
-                continue;
-            }
-            nact.push_back(i);
-            src.push_back(k);
-            tgt.push_back(std::max(xi * bmin, o.inner_tol * rr));
+            const double rr = std::sqrt(h_rn2c[k]);
+            if (!(rr == rr) || rr <= xi * bnorm[i] || rr <= o.reliable * rlast[i] || its[i] >= o.maxit)
+                from_carry = false;
         }
-        if (nact.empty()) break;
+        if (from_carry) {
+            std::vector<double> tgt(na);
+            for (int k = 0; k < na; k++) {
+                const int i = act[k];
+                const double rr = std::sqrt(h_rn2c[k]);
+                cyc[i]++;
+                rel[i] = bnorm[i] > 0 ? rr / bnorm[i] : 0.0;
+                tgt[k] = std::max(xi * bnorm[i], o.inner_tol * rr);
+            }
+            LQT_HIP(hipMemcpyAsync(tgt_d, tgt.data(), sizeof(double) * na, hipMemcpyHostToDevice, c->stream));
+            c->timer.begin(c->stream, KT_KRYLOV);
+            kry_start_state_carry(c, sb.st, tgt_d, na);
+            c->timer.end(c->stream);
+        }
+        std::vector<int> nact;
+        if (from_carry) {
+            nact = act;
+        } else {
+            LQT_HIP(hipMemcpyAsync(act_d, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, c->stream));
+            residual64(c, b, x, r, rn2, na, act_d, multi ? rn2l : nullptr);
+            LQT_HIP(hipMemcpyAsync(h_rn2, rn2, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream));
+            if (multi)
+                LQT_HIP(hipMemcpyAsync(h_rn2l, rn2l, sizeof(double) * na * nlat, hipMemcpyDeviceToHost, c->stream));
+            LQT_HIP(hipStreamSynchronize(c->stream));
+            std::vector<int> src;
+            std::vector<double> tgt;
+            for (int k = 0; k < na; k++) {
+                const int i = act[k];
+                cyc[i]++;
+                double rr = std::sqrt(h_rn2[k]);
+                rlast[i] = rr;
+                rel[i] = bnorm[i] > 0 ? rr / bnorm[i] : 0.0;
+                double bmin = bnorm[i];  // the cycle target must serve the smallest lattice block
+                if (multi) {
+                    double worst = 0;
+                    for (int l = 0; l < nlat; l++) {
+                        const double bl = bnl[(size_t)i * nlat + l], rl = std::sqrt(h_rn2l[(size_t)k * nlat + l]);
+                        if (bl > 0) {
+                            worst = std::max(worst, rl / bl);
+                            bmin = std::min(bmin, bl);
+                        } else if (!(rl == rl)) {
+                            worst = rl;
+                        }
+                    }
+                    rel[i] = (rr == rr) ? worst : rr;
+                }
+                if (!(rel[i] == rel[i])) {
+                    done[i] = 1;
+                    nfail++;
+                    continue;
+                }
+                if (rel[i] <= xi) {
+                    done[i] = 1;
+                    continue;
+                }
+                if (its[i] >= o.maxit) {
+                    done[i] = 1;
+                    nfail++;
+                    continue;
+                }
+                nact.push_back(i);
+                src.push_back(k);
+                tgt.push_back(std::max(xi * bmin, o.inner_tol * rr));
+            }
+            if (nact.empty()) break;
+            const int nn0 = (int)nact.size();
+            // new active list; src maps new slot -> slot of r
+            LQT_HIP(hipMemcpyAsync(act_d, nact.data(), sizeof(int) * nn0, hipMemcpyHostToDevice, c->stream));
+            LQT_HIP(hipMemcpyAsync(src_d, src.data(), sizeof(int) * nn0, hipMemcpyHostToDevice, c->stream));
+            LQT_HIP(hipMemcpyAsync(tgt_d, tgt.data(), sizeof(double) * nn0, hipMemcpyHostToDevice, c->stream));
+            c->timer.begin(c->stream, KT_KRYLOV);
+            kry_start_state(c, sb.st, src_d, rn2, tgt_d, nn0);
+            kry_start<S>(c, basis, r, src_d, rn2, nn0);
+            c->timer.end(c->stream);
+        }
         const int nn = (int)nact.size();
         if (o.verbose && (cyc[nact[0]] % 16) == 0) {
             double mx = 0;
             for (int i : nact) mx = std::max(mx, rel[i]);
-            fprintf(stderr, "[lqtrace] solve: %d of %d systems active, cycle %d, max relres %.3e\n", nn, nb,
-                    cyc[nact[0]], mx);
+            fprintf(stderr, "[lqtrace] solve: %d of %d systems active, cycle %d, max relres %.3e%s\n", nn, nb,
+                    cyc[nact[0]], mx, from_carry ? " (carried)" : "");
             fflush(stderr);
         }
-        // new active list; src maps new slot -> slot of r
-        LQT_HIP(hipMemcpyAsync(act_d, nact.data(), sizeof(int) * nn, hipMemcpyHostToDevice, c->stream));
-        LQT_HIP(hipMemcpyAsync(src_d, src.data(), sizeof(int) * nn, hipMemcpyHostToDevice, c->stream));
-        LQT_HIP(hipMemcpyAsync(tgt_d, tgt.data(), sizeof(double) * nn, hipMemcpyHostToDevice, c->stream));
         const long long vstride = (long long)nn * n;
-        c->timer.begin(c->stream, KT_KRYLOV);
-        kry_start_state(c, sb.st, src_d, rn2, tgt_d, nn);
-        kry_start<S>(c, basis, r, src_d, rn2, nn);
-        c->timer.end(c->stream);
         // one Arnoldi step: (preconditioner,) operator, Gram-Schmidt and the Givens update;
         // s-step cycles: the operator step k_{j+1} = sigma (A - theta) k_j only
         auto step = [&](int j) {
@@ -252,7 +286,10 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
                 sstep_finish<S>(c, basis, vstride, m, nn, sb.st, theta, sigma, c->scratch[13]);
             c->timer.begin(c->stream, KT_KRYLOV);
             if (!o.sstep) kry_backsolve(c, nn, sb.st);
-            kry_xupdate<S>(c, x, act_d, o.use_net ? zb.p : basis, vstride, nn, sb.st);
+            if (carry)
+                kry_sstep_carry<S>(c, x, act_d, basis, vstride, nn, sb.st, theta, sigma, (double*)part, rn2c);
+            else
+                kry_xupdate<S>(c, x, act_d, o.use_net ? zb.p : basis, vstride, nn, sb.st);
             c->timer.end(c->stream);
         };
         if (o.graph) {
@@ -306,9 +343,11 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
             finish();
         }
         LQT_HIP(hipMemcpyAsync(h_flags, sb.st.kdim, sizeof(int) * nn, hipMemcpyDeviceToHost, c->stream));
+        if (carry) LQT_HIP(hipMemcpyAsync(h_rn2c, rn2c, sizeof(double) * nn, hipMemcpyDeviceToHost, c->stream));
         LQT_HIP(hipStreamSynchronize(c->stream));
         for (int k = 0; k < nn; k++) its[nact[k]] += h_flags[k];
         act = nact;
+        carried = carry;
     }
     if (stats)
         for (int i = 0; i < nb; i++) {
@@ -336,6 +375,7 @@ SolveOpts make_opts(const lqt_solver_opts* u) {
         o.outer_maxit = u->outer_maxit > 0 ? u->outer_maxit : 60;
         o.graph = u->graph;
         o.sstep = u->sstep;
+        o.reliable = u->reliable < 0 ? 0.0 : (u->reliable > 0 ? u->reliable : 0.1);
     }
     return o;
 }
@@ -349,6 +389,7 @@ int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, 
     LQT_CHECK(!o.use_net || c->g.lat.nlat == 1, LQT_EINVAL, "the network preconditioner serves single-lattice contexts");
     LQT_CHECK(!o.sstep || (!o.use_net && o.restart <= (storage_bytes(o.prec) == 4 ? 15 : 8)), LQT_EINVAL,
               "s-step cycles need restart <= 15 (16-bit storage) or <= 8, and no network preconditioner");
+    LQT_CHECK(o.reliable >= 0 && o.reliable < 1, LQT_EINVAL, "reliable must be below 1");
     const long long n = 12LL * c->g.V;
     // batch size: caller cap, else what fits in 70% of free device memory
     size_t fr = 0, tot = 0;

@@ -28,7 +28,7 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("use_net", ctypes.c_int), ("max_batch", ctypes.c_int), ("cgs2", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("verbose", ctypes.c_int), ("outer_maxit", ctypes.c_int),
-                ("graph", ctypes.c_int), ("sstep", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("sstep", ctypes.c_int), ("reliable", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -89,6 +89,7 @@ _SIGS = {
     "lqt_prolongator_get": ([_P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
     "lqt_basis_prolongator_from": ([_P, _P, _I, _P, _P, _I, ctypes.POINTER(_P)], _I),
     "lqt_tune": ([_P, _I, _I, ctypes.POINTER(_D), _P], _I),
+    "lqt_set_tile": ([_P, _I, _I, _P], _I),
     "lqt_kernel_times": ([_P, _P, _P, _P, _I], _I),
     "lqt_last_error": ([_P], ctypes.c_char_p),
     "lqt_destroy": ([_P], None),
@@ -119,8 +120,9 @@ def _ptr(t):
 
 
 def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0, verbose=0,
-          outer_maxit=0, graph=0, sstep=0):
-    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit, graph, sstep)
+          outer_maxit=0, graph=0, sstep=0, reliable=0.0):
+    return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit, graph, sstep,
+                      reliable)
 
 
 class Context:
@@ -207,11 +209,16 @@ class Context:
 
     def tune(self, prec, nrhs, return_tile=False):
         """Autotune the dslash tiling for (prec, nrhs); the best time in ms (and the tile
-        (rhs per thread, block, chunk) with return_tile)."""
+        (rhs per thread or groups per lane, block, chunk, kind) with return_tile)."""
         ms = ctypes.c_double(0)
-        tile = (ctypes.c_int * 3)()
+        tile = (ctypes.c_int * 4)()
         self._check(lib().lqt_tune(self._h, int(prec), int(nrhs), ctypes.byref(ms), tile))
         return (ms.value, tuple(tile)) if return_tile else ms.value
+
+    def set_tile(self, prec, nrhs, tile):
+        """Use tile = (rhs per thread or groups per lane, block, chunk, kind) for (prec, nrhs)."""
+        t = (ctypes.c_int * 4)(*[int(v) for v in tile])
+        self._check(lib().lqt_set_tile(self._h, int(prec), int(nrhs), t))
 
     KERNEL_FAMILIES = ["dslash", "cgs_dots", "cgs_update", "residual_fp64", "krylov_other", "projections",
                        "prolongator", "net", "graph_cycles"]

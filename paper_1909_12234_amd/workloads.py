@@ -9,7 +9,8 @@ WORKLOADS = {
     # 4^4, the small workload: exact trace by dense LU
     "wilson4x4_plain": dict(dims=(4, 4, 4, 4), eps=0.3, seed=1, mass=0.1, nprobes=64, probe_seed=1000,
                             xi=1e-10, k=16, inner_prec="f64"),
-    # 16^3x32 mixed precision: BF16 inner cycles, FP64 defect correction to 1e-8, k = 64 basis.
+    # 16^3x32 mixed precision: FP16 inner s-step cycles (packed half arithmetic in the operator,
+    # FP32 accumulation), FP64 defect correction to 1e-8, k = 64 basis.
     # The mass sits just inside the left edge of the spectrum of A(0) (complex pairs near
     # Re lambda = 1.96 for these fields): moving past it makes restarted GMRES stagnate.
     # s-step cycles of 15: GMRES steps per probe barely depend on the restart length (604 at
@@ -18,7 +19,7 @@ WORKLOADS = {
     # restart over more steps (measured 52 / 85 / 99 probe solves/s for GMRES(8), s-step 8
     # and s-step 15).
     "wilson16x32_mixed": dict(dims=(16, 16, 16, 32), eps=0.5, seed=1, mass=-1.90, nprobes=128, probe_seed=1001,
-                              xi=1e-8, k=64, inner_prec="bf16", restart=15, sstep=1),
+                              xi=1e-8, k=64, inner_prec="f16", restart=15, sstep=1),
     # three lattices solved one after the other in a batch of 192 probes, FP32 storage
     "wilson_batched3": dict(lattices=[((8, 8, 8, 8), 1), ((12, 12, 12, 24), 2), ((16, 16, 16, 32), 3)], eps=0.4,
                             mass=0.1, nprobes=192, probe_seed=1002, xi=1e-8, inner_prec="f32"),

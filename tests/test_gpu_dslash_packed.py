@@ -1,0 +1,72 @@
+"""The FP16 Wilson operator with packed half-precision arithmetic (tuner kind 2) against the
+oracle.
+
+Inputs and links as the library stores them (tests/storage16.py).  The kernel rounds each
+half spinor h = p_a + c p_b (c = +-1, +-i) to FP16 (|dh| <= u |h|, u = 2^-11 per real), then
+forms link products exactly and sums them in FP32, and rounds the output once to FP16.  A link
+row has unit norm, so a rounded half spinor moves U h by at most u |h|_2 <= 2 sqrt(3) u m_psi
+per colour (m_psi = the largest |component| of the input); each output real receives 1/2 U h
+from each of the 8 hops, so it is within u |ref| + 8 sqrt(3) u m_psi + 1e-5 max |ref| of the
+oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import core
+from storage16 import stored
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [((4, 4, 4, 4), 0.3), ((3, 5, 4, 6), 0.5), ((8, 6, 4, 10), 0.5)]
+TILES = [(1, 64, 0, 2), (2, 256, 16, 2), (4, 128, 64, 2)]
+U = 2.0 ** -11
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("dims,eps", SHAPES)
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
+def test_packed_half_dslash_matches_oracle(gpu, dims, eps, op, tile):
+    lq = gpu
+    nrhs = 5
+    print(f"packed FP16 dslash dims={dims} op={op} tile={tile}", flush=True)
+    links = synth.su3_links(dims, eps, 1)
+    c = lq.Context(dims, -0.4)
+    c.set_gauge(links)
+    c.set_tile(2, nrhs, tile)
+    psi = synth.random_spinors(dims, nrhs, 2).reshape(nrhs, -1)
+    out = c.apply(torch.as_tensor(psi).to(torch.complex64).cuda(), op=op, prec=2).cpu().numpy().astype(np.complex128)
+    ps = stored(psi, 2)
+    ref = core.apply(stored(links, 2, links=True), dims, -0.4, op, ps)
+    m, mpsi = np.max(np.abs(ref)), np.max(np.abs(ps))
+    for part in (np.real, np.imag):
+        d = np.abs(part(out) - part(ref))
+        assert np.all(d <= U * np.abs(part(ref)) + 8 * np.sqrt(3) * U * mpsi + 1e-5 * m), float(np.max(d / m))
+    c.close()
+
+
+def test_packed_half_solves(gpu):
+    """s-step cycles with the packed FP16 operator: solutions to 1e-8 against the oracle"""
+    lq = gpu
+    dims, m = (6, 6, 6, 8), -0.6
+    links = synth.su3_links(dims, 0.5, 2)
+    c = lq.Context(dims, m)
+    c.set_gauge(links)
+    z = c.probes(91, 8)
+    c.set_tile(2, 8, (2, 256, 0, 2))
+    y, st, _ = c.solve(z, 1e-8, prec=2, restart=15, sstep=1)
+    assert all(s[0] for s in st)
+    zs, ys = z.cpu().numpy(), y.cpu().numpy()
+    r = zs - core.apply(links, dims, m, core.OP_A, ys)
+    assert np.all(np.linalg.norm(r, axis=1) <= 1.05e-8 * np.linalg.norm(zs, axis=1))
+    c.close()
+
+
+def test_packed_half_rejects_other_storage(gpu):
+    lq = gpu
+    c = lq.Context((4, 4, 4, 4), 0.1)
+    for prec in (0, 1, 3):
+        with pytest.raises(lq.LqtError) as e:
+            c.set_tile(prec, 8, (1, 256, 0, 2))
+        assert e.value.code == -1
+    c.close()

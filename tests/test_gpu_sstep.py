@@ -106,3 +106,43 @@ def test_sstep_option_limits(gpu):
         c.solve(b, 1e-6, restart=9, sstep=1)  # FP64 storage: at most 8
     assert ei.value.code == lq.LQT_EINVAL
     c.close()
+
+
+@pytest.mark.parametrize("prec,s", [(0, 8), (1, 8), (3, 15), (2, 12)])
+@pytest.mark.parametrize("graph", [0, 1])
+def test_carried_residual_cycles(gpu, prec, s, graph):
+    """Reliable updates: cycles start from the residual carried in the basis and the FP64
+    residual is formed only when it fell tenfold, or to verify convergence.  Same solutions
+    (oracle residuals below xi), about the same steps, far fewer FP64 residuals."""
+    lq = gpu
+    dims, m, xi = (6, 6, 6, 8), -1.7, 1e-9  # about 20 cycles: residuals fall slowly per cycle
+    print(f"carried residual prec={prec} s={s} graph={graph}", flush=True)
+    U = synth.su3_links(dims, 0.5, 5)
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    b = synth.random_spinors(dims, 6, 8).reshape(6, -1)
+    bt = torch.as_tensor(b).cuda()
+    runs = {}
+    for rel in (-1.0, 0.1):
+        c.kernel_times(mode=2)
+        x, st, _ = c.solve(bt, xi, prec=prec, restart=s, sstep=1, graph=graph, reliable=rel, maxit=40000)
+        kt = c.kernel_times(mode=3)
+        assert all(q[0] for q in st)
+        assert np.all(_relres(U, dims, m, b, x.cpu().numpy()) <= xi * 1.05)
+        runs[rel] = (sum(q[1] for q in st), kt["residual_fp64"][1], max(q[2] for q in st))
+    (it_every, nres_every, cyc), (it_carry, nres_carry, _) = runs[-1.0], runs[0.1]
+    print("steps every/carried", it_every, it_carry, "FP64 residuals", nres_every, nres_carry, flush=True)
+    assert it_carry <= 1.1 * it_every + 6 * s
+    assert nres_every == cyc and nres_carry <= 0.75 * nres_every
+    c.close()
+
+
+def test_reliable_option_limits(gpu):
+    lq = gpu
+    c = lq.Context((4, 4, 4, 4), 0.1)
+    c.set_gauge(synth.su3_links((4, 4, 4, 4), 0.3, 1))
+    z = c.probes(1, 1)
+    with pytest.raises(lq.LqtError) as e:
+        c.solve(z, 1e-8, prec=3, restart=8, sstep=1, reliable=1.5)
+    assert e.value.code == -1
+    c.close()

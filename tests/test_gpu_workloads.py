@@ -6,7 +6,7 @@ import torch
 
 import synth
 from oracle import core, prolongator as pr
-from paper_1909_12234_amd.workloads import WORKLOADS
+from paper_1909_12234_amd.workloads import PREC, WORKLOADS
 
 pytestmark = pytest.mark.gpu
 
@@ -17,24 +17,27 @@ def _relres(U, dims, m, b, x):
 
 
 def test_mixed_16x32_probe_solves(gpu):
-    """16^3x32, m = -1.90, BF16 inner s-step GMRES(8) with FP64 defect correction to 1e-8, in the
-    batched launch configuration of the benchmark (128 probes); 4 sampled solutions are
-    checked with the oracle operator and their samples z^T y against the oracle's dot."""
+    """16^3x32, m = -1.90, the workload's 16-bit inner s-step cycles with FP64 defect correction
+    to 1e-8, in the launch configuration of the benchmark (128 probes, autotuned operator
+    tiles); 4 sampled solutions are checked with the oracle operator and their samples z^T y
+    against the oracle's dot."""
     lq = gpu
     w = WORKLOADS["wilson16x32_mixed"]
     dims, m = w["dims"], w["mass"]
+    prec = PREC[w["inner_prec"]]
     print("16^3x32 mixed-precision probe solves", flush=True)
     U = synth.su3_links(dims, w["eps"], w["seed"])
     c = lq.Context(dims, m)
     c.set_gauge(U)
+    c.tune(prec, 128)
     z = c.probes(w["probe_seed"], 128)
-    y, st, _ = c.solve(z, w["xi"], prec=lq.BF16, restart=w["restart"], sstep=w.get("sstep", 0))
+    y, st, _ = c.solve(z, w["xi"], prec=prec, restart=w["restart"], sstep=w.get("sstep", 0))
     assert all(s[0] for s in st) and max(s[3] for s in st) <= w["xi"]
     pick = [0, 37, 90, 127]
     zs, ys = z[pick].cpu().numpy(), y[pick].cpu().numpy()
     assert np.array_equal(zs.real, core.probes(w["probe_seed"], 128, zs.shape[1])[pick])
     assert np.all(_relres(U, dims, m, zs, ys) <= w["xi"] * 1.05)
-    r = c.trace(128, w["probe_seed"], w["xi"], samples=True, prec=lq.BF16, restart=w["restart"], sstep=w.get("sstep", 0))
+    r = c.trace(128, w["probe_seed"], w["xi"], samples=True, prec=prec, restart=w["restart"], sstep=w.get("sstep", 0))
     t = r["samples"].numpy()[pick]
     assert np.max(np.abs(t - np.sum(zs * ys, axis=1))) <= 1e-6 * np.max(np.abs(t))
     c.close()
