@@ -333,11 +333,13 @@ int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const d
 
 /* Autotuner: time the candidate dslash tilings for (prec, nrhs) now and cache the choice in
  * the context.  Candidates: the vector-ALU kernel (kind 0: right-hand sides per thread 1/2/4,
- * block 64/128/256 threads, block order site-block major or chunks of 16/64 site blocks swept
- * per right-hand-side group); for FP16/BF16 storage the matrix-core kernel (kind 1: 1 or 2
+ * block 64/128/256 threads, block order site-block major or chunks of site blocks swept per
+ * right-hand-side group); for FP16/BF16 storage the matrix-core kernel (kind 1: 1 or 2
  * groups of 4 right-hand sides per lane, 16 sites per wave, same blocks and orders); for FP16
  * storage the vector kernel with packed half-precision arithmetic (kind 2: the half spinors
- * rounded to FP16, link products as FP16 dot products accumulated in FP32; tiles as kind 0).  *ms
+ * rounded to FP16, link products as FP16 dot products accumulated in FP32; tiles as kind 0).
+ * Block orders: chunks of 16, 64, 256 or 1024 site blocks (1024: the whole of most
+ * lattices, right-hand-side groups outermost).  *ms
  * receives the best time and tile[0..3] the chosen (rhs per thread or groups per lane, block,
  * chunk, kind); either may be NULL.  Also tunes the FP64 residual of the solvers' restarts
  * (r = b - A x with its norms; 1 or 2 right-hand sides per thread, block order) for nrhs

@@ -553,7 +553,7 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen) {
     LQT_HIP(hipMemsetAsync(a.p, 0, (size_t)n * nrhs * eb, c->stream));
     const int Rs[3] = {1, 2, 4};
     const int Bs[3] = {64, 128, 256};
-    const int Cs[3] = {0, 16, 64};
+    const int Cs[5] = {0, 16, 64, 256, 1024};  // 1024 site blocks: the whole of most lattices
     hipEvent_t e0, e1;
     LQT_HIP(hipEventCreate(&e0));
     LQT_HIP(hipEventCreate(&e1));
@@ -561,7 +561,7 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen) {
     Tuned bt = default_tile(prec, nrhs);
     // candidates: vector kernel (R right-hand sides per thread), for 16-bit storage the
     // matrix-core kernel (R groups of 4 right-hand sides per lane), for FP16 storage the
-    // vector kernel with packed half-precision arithmetic
+    // vector kernel with packed half-precision arithmetic (kind 2)
     std::vector<Tuned> cand;
     for (int kind = 0; kind < 3; kind++)
         for (int ri = 0; ri < 3; ri++) {
@@ -571,7 +571,7 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen) {
                               !dslash_mf_fits(c->g, Rs[ri], n, n)))
                 continue;
             for (int bi = 0; bi < 3; bi++)
-                for (int ci = 0; ci < 3; ci++) {
+                for (int ci = 0; ci < 5; ci++) {
                     Tuned t{Rs[ri], Bs[bi], Cs[ci]};
                     t.kind = kind;
                     cand.push_back(t);
@@ -667,7 +667,7 @@ double residual_tune(lqt_ctx* c, int nrhs) {
     LQT_HIP(hipEventCreate(&e1));
     double best = 1e30;
     Tuned bt{1, 256, 0};
-    const int Rs[2] = {1, 2}, Cs[3] = {0, 16, 64};
+    const int Rs[2] = {1, 2}, Cs[5] = {0, 16, 64, 256, 1024};
     for (int R : Rs) {
         if (R > nrhs) continue;
         for (int ch : Cs) {

@@ -19,7 +19,7 @@ from storage16 import stored
 pytestmark = pytest.mark.gpu
 
 SHAPES = [((4, 4, 4, 4), 0.3), ((3, 5, 4, 6), 0.5), ((8, 6, 4, 10), 0.5)]
-TILES = [(1, 64, 0, 2), (2, 256, 16, 2), (4, 128, 64, 2)]
+TILES = [(1, 64, 0, 2), (2, 256, 16, 2), (4, 128, 64, 2), (2, 256, 1024, 2)]
 U = 2.0 ** -11
 
 
@@ -42,6 +42,33 @@ def test_packed_half_dslash_matches_oracle(gpu, dims, eps, op, tile):
     for part in (np.real, np.imag):
         d = np.abs(part(out) - part(ref))
         assert np.all(d <= U * np.abs(part(ref)) + 8 * np.sqrt(3) * U * mpsi + 1e-5 * m), float(np.max(d / m))
+    c.close()
+
+
+def _check(out, ref, ps):
+    m, mpsi = np.max(np.abs(ref)), np.max(np.abs(ps))
+    for part in (np.real, np.imag):
+        d = np.abs(part(out) - part(ref))
+        assert np.all(d <= U * np.abs(part(ref)) + 8 * np.sqrt(3) * U * mpsi + 1e-5 * m), float(np.max(d / m))
+
+
+@pytest.mark.parametrize("tile", [(2, 256, 256, 2), (2, 256, 1024, 2)])
+def test_packed_half_full_size(gpu, tile):
+    """16^3x32 with 128 right-hand sides in the benchmark's launch shapes; sampled right-hand
+    sides against the oracle"""
+    lq = gpu
+    dims, nrhs = (16, 16, 16, 32), 128
+    print(f"packed FP16 dslash 16^3x32 tile={tile}", flush=True)
+    links = synth.su3_links(dims, 0.5, 1)
+    c = lq.Context(dims, -1.9)
+    c.set_gauge(links)
+    c.set_tile(2, nrhs, tile)
+    psi = synth.random_spinors(dims, nrhs, 3).reshape(nrhs, -1)
+    out = c.apply(torch.as_tensor(psi).to(torch.complex64).cuda(), op=0, prec=2).cpu().numpy().astype(np.complex128)
+    pick = [0, 17, 64, 127]
+    ps = stored(psi[pick], 2)
+    ref = core.apply(stored(links, 2, links=True), dims, -1.9, 0, ps)
+    _check(out[pick], ref, ps)
     c.close()
 
 
