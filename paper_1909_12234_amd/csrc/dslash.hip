@@ -162,32 +162,47 @@ __device__ __forceinline__ void load_link(const S* __restrict__ Um, uint32_t V, 
 // (projector signs swap for the adjoint)
 template <int MU, bool DAG, int R, typename S, typename C>
 __device__ __forceinline__ void hop_dir(const S* __restrict__ U, const S* const inb[R], uint32_t V, uint32_t s,
-                                        uint32_t sf, uint32_t sb, int nr, bool g5in, cpx<C> acc[R][12]) {
+                                        uint32_t sf, uint32_t sb, bool g5in, cpx<C> acc[R][12]) {
+    // the R neighbour spinors of a direction are loaded (as stored) before any of them is
+    // used; a group's unused right-hand sides read a valid field and are never stored
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     cpx<C> u[9], p[12], h0[3], h1[3], o0[3], o1[3];
+    S raw[R][12];
     const S* Um = U + (long long)MU * 9 * V;
     load_link<S, C>(Um, V, s, u);
 #pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) raw[r][c] = *at(inb[r], c * V + sf);
+#pragma unroll
     for (int r = 0; r < R; r++) {
-        if (r < nr) {
-            load_spinor<S, C>(inb[r], V, sf, g5in, p);
-            project<MU, SF>(p, h0, h1);
-            su3_mul<false>(u, h0, o0);
-            su3_mul<false>(u, h1, o1);
-            rebuild_add<MU, SF>(acc[r], o0, o1);
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            p[c] = ld_c<C>(&raw[r][c]);
+            if (g5in && c >= 6) p[c] = {-p[c].x, -p[c].y};
         }
+        project<MU, SF>(p, h0, h1);
+        su3_mul<false>(u, h0, o0);
+        su3_mul<false>(u, h1, o1);
+        rebuild_add<MU, SF>(acc[r], o0, o1);
     }
     load_link<S, C>(Um, V, sb, u);
 #pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) raw[r][c] = *at(inb[r], c * V + sb);
+#pragma unroll
     for (int r = 0; r < R; r++) {
-        if (r < nr) {
-            load_spinor<S, C>(inb[r], V, sb, g5in, p);
-            project<MU, SB>(p, h0, h1);
-            su3_mul<true>(u, h0, o0);
-            su3_mul<true>(u, h1, o1);
-            rebuild_add<MU, SB>(acc[r], o0, o1);
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            p[c] = ld_c<C>(&raw[r][c]);
+            if (g5in && c >= 6) p[c] = {-p[c].x, -p[c].y};
         }
+        project<MU, SB>(p, h0, h1);
+        su3_mul<true>(u, h0, o0);
+        su3_mul<true>(u, h1, o1);
+        rebuild_add<MU, SB>(acc[r], o0, o1);
     }
 }
 
@@ -251,54 +266,64 @@ __device__ __forceinline__ void pk_half(const hv2 u[9], const hv2 p[12], cpx<flo
     }
 }
 
-template <int MU, bool DAG, int R>
-__device__ __forceinline__ void hop_dir_pk(const h2* __restrict__ U, const h2* const inb[R], uint32_t V, uint32_t s,
-                                           uint32_t sf, uint32_t sb, int nr, bool g5in, cpx<float> acc[R][12]) {
-    constexpr int SF = DAG ? +1 : -1;
-    constexpr int SB = -SF;
-    const h2* Um = U + (long long)MU * 9 * V;
-    hv2 u[9], p[12];
+// All 8 hops of the packed FP16 operator with the loads of the next hop issued before the
+// products of the current one (two buffers of one link and R neighbour spinors).  Loads and
+// products run for all R right-hand sides: a group's unused ones read a valid field (the
+// pointers are clamped) and are never stored.
+template <int R>
+struct PkBuf {
+    hv2 u[9];
+    hv2 p[R][12];
+};
+template <int R>
+__device__ __forceinline__ void pk_load(PkBuf<R>& b, const h2* __restrict__ Um, const h2* const inb[R], uint32_t V,
+                                        uint32_t sl, uint32_t sn, bool g5in) {
+#pragma unroll
+    for (int i = 0; i < 9; i++) b.u[i] = ldh(Um, i * V + sl);
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            b.p[r][c] = ldh(inb[r], c * V + sn);
+            if (g5in && c >= 6) b.p[r][c] = -b.p[r][c];
+        }
+}
+template <int MU, int SG, bool BWD, int R>
+__device__ __forceinline__ void pk_comp(const PkBuf<R>& b, cpx<float> acc[R][12]) {
     cpx<float> o0[3], o1[3];
 #pragma unroll
-    for (int i = 0; i < 9; i++) u[i] = ldh(Um, i * V + s);
-#pragma unroll
     for (int r = 0; r < R; r++) {
-        if (r < nr) {
-#pragma unroll
-            for (int c = 0; c < 12; c++) {
-                p[c] = ldh(inb[r], c * V + sf);
-                if (g5in && c >= 6) p[c] = -p[c];
-            }
-            pk_half<MU, SF, false, 0>(u, p, o0);
-            pk_half<MU, SF, false, 1>(u, p, o1);
-            rebuild_add<MU, SF>(acc[r], o0, o1);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 9; i++) u[i] = ldh(Um, i * V + sb);
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        if (r < nr) {
-#pragma unroll
-            for (int c = 0; c < 12; c++) {
-                p[c] = ldh(inb[r], c * V + sb);
-                if (g5in && c >= 6) p[c] = -p[c];
-            }
-            pk_half<MU, SB, true, 0>(u, p, o0);
-            pk_half<MU, SB, true, 1>(u, p, o1);
-            rebuild_add<MU, SB>(acc[r], o0, o1);
-        }
+        pk_half<MU, SG, BWD, 0>(b.u, b.p[r], o0);
+        pk_half<MU, SG, BWD, 1>(b.u, b.p[r], o1);
+        rebuild_add<MU, SG>(acc[r], o0, o1);
     }
 }
-
-// one direction on the vector ALUs: FP32 arithmetic, or packed FP16 arithmetic (PKH, FP16 storage)
-template <int MU, bool DAG, int R, typename S, typename C, bool PKH>
-__device__ __forceinline__ void hop_any(const S* __restrict__ U, const S* const inb[R], uint32_t V, uint32_t s,
-                                        uint32_t sf, uint32_t sb, int nr, bool g5in, cpx<C> acc[R][12]) {
-    if constexpr (PKH)
-        hop_dir_pk<MU, DAG, R>(U, inb, V, s, sf, sb, nr, g5in, acc);
-    else
-        hop_dir<MU, DAG, R, S, C>(U, inb, V, s, sf, sb, nr, g5in, acc);
+template <bool DAG, int R>
+__device__ __forceinline__ void hop_all_pk(const h2* __restrict__ U, const h2* const inb[R], uint32_t V, uint32_t s,
+                                           const uint32_t nf[4], const uint32_t nb[4], bool g5in,
+                                           cpx<float> acc[R][12]) {
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const h2* U1 = U + 9ll * V;
+    const h2* U2 = U + 18ll * V;
+    const h2* U3 = U + 27ll * V;
+    PkBuf<R> A, B;
+    pk_load<R>(A, U, inb, V, s, nf[0], g5in);
+    pk_load<R>(B, U, inb, V, nb[0], nb[0], g5in);
+    pk_comp<0, SF, false, R>(A, acc);
+    pk_load<R>(A, U1, inb, V, s, nf[1], g5in);
+    pk_comp<0, SB, true, R>(B, acc);
+    pk_load<R>(B, U1, inb, V, nb[1], nb[1], g5in);
+    pk_comp<1, SF, false, R>(A, acc);
+    pk_load<R>(A, U2, inb, V, s, nf[2], g5in);
+    pk_comp<1, SB, true, R>(B, acc);
+    pk_load<R>(B, U2, inb, V, nb[2], nb[2], g5in);
+    pk_comp<2, SF, false, R>(A, acc);
+    pk_load<R>(A, U3, inb, V, s, nf[3], g5in);
+    pk_comp<2, SB, true, R>(B, acc);
+    pk_load<R>(B, U3, inb, V, nb[3], nb[3], g5in);
+    pk_comp<3, SF, false, R>(A, acc);
+    pk_comp<3, SB, true, R>(B, acc);
 }
 
 // EPI 0: out = op(in).  EPI 1 (FP64 only): out = b - A in, with per-block partial |out|^2.
@@ -381,10 +406,15 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
             const uint32_t zb = (z == 0) ? s + (L2 - 1) * s2 : s - s2;
             const uint32_t tf = (t == L3 - 1) ? s - (L3 - 1) * s3 : s + s3;
             const uint32_t tb = (t == 0) ? s + (L3 - 1) * s3 : s - s3;
-            hop_any<0, DAG, R, S, C, PKH>(U, inb, V, s, xf, xb, nr, g5in, acc);
-            hop_any<1, DAG, R, S, C, PKH>(U, inb, V, s, yf, yb, nr, g5in, acc);
-            hop_any<2, DAG, R, S, C, PKH>(U, inb, V, s, zf, zb, nr, g5in, acc);
-            hop_any<3, DAG, R, S, C, PKH>(U, inb, V, s, tf, tb, nr, g5in, acc);
+            if constexpr (PKH) {
+                const uint32_t nf[4] = {xf, yf, zf, tf}, nbk[4] = {xb, yb, zb, tb};
+                hop_all_pk<DAG, R>(U, inb, V, s, nf, nbk, g5in, acc);
+            } else {
+                hop_dir<0, DAG, R, S, C>(U, inb, V, s, xf, xb, g5in, acc);
+                hop_dir<1, DAG, R, S, C>(U, inb, V, s, yf, yb, g5in, acc);
+                hop_dir<2, DAG, R, S, C>(U, inb, V, s, zf, zb, g5in, acc);
+                hop_dir<3, DAG, R, S, C>(U, inb, V, s, tf, tb, g5in, acc);
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; r++) {
