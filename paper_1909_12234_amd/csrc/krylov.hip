@@ -679,51 +679,49 @@ __global__ __launch_bounds__(256) void k_sgram(const S* __restrict__ Vb, long lo
 // result: lane l, register v holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
 typedef __bf16 lqt_bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 lqt_h8 __attribute__((ext_vector_type(8)));
-typedef float lqt_f16v __attribute__((ext_vector_type(16)));
 
+typedef float lqt_f4v __attribute__((ext_vector_type(4)));
+
+// acc += X Y^T for two 16 x 32 tiles (row = vector, column = element): lane l holds row l % 16,
+// elements 8 (l / 16) .. 8 (l / 16) + 7 of both operands
 template <typename S>
-__device__ __forceinline__ lqt_f16v mfma_xxt(const uint32_t (&w)[8], int im, lqt_f16v acc) {
-    // w: 8 packed complex values (re low, im high 16 bits); pick one half of each
-    if constexpr (std::is_same<S, b2>::value) {
-        lqt_bf8 a;
-#pragma unroll
-        for (int t = 0; t < 8; t++) a[t] = __builtin_bit_cast(__bf16, (uint16_t)(im ? (w[t] >> 16) : (w[t] & 0xffffu)));
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, a, acc, 0, 0, 0);
-    } else {
-        lqt_h8 a;
-#pragma unroll
-        for (int t = 0; t < 8; t++)
-            a[t] = __builtin_bit_cast(_Float16, (uint16_t)(im ? (w[t] >> 16) : (w[t] & 0xffffu)));
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, a, acc, 0, 0, 0);
-    }
+__device__ __forceinline__ lqt_f4v mfma_rows(const uint32_t (&x)[4], const uint32_t (&y)[4], lqt_f4v acc) {
+    if constexpr (std::is_same<S, b2>::value)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(lqt_bf8, x), __builtin_bit_cast(lqt_bf8, y),
+                                                       acc, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(lqt_h8, x), __builtin_bit_cast(lqt_h8, y), acc,
+                                                      0, 0, 0);
 }
 
+// Gram partial sums of up to 16 stored 16-bit vectors of slot q on the matrix cores.  A pass of
+// a wave covers 32 consecutive elements of every vector: lane l loads elements 8 (l / 16) ..
+// + 7 of vector l % 16 (32 bytes, each element loaded once), splits them into real and
+// imaginary halves, and three 16 x 16 x 32 products accumulate RR = Re Re^T, II = Im Im^T and
+// RI = Re Im^T, so G = RR + II + i (RI - RI^T).  FP32 sums are flushed to FP64 every 64
+// passes; the block's four waves are summed in LDS.
 template <typename S>
 __global__ __launch_bounds__(256) void k_sgram_mf(const S* __restrict__ Vb, long long vstride, long long n, int nv,
                                                   double* __restrict__ part) {
     static_assert(sizeof(S) == 4, "16-bit complex storage only");
-    __shared__ double red[32][33];
+    __shared__ double red[3][16][17];
     const int q = blockIdx.y, nblk = gridDim.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row = lane & 31, half = lane >> 5;
-    const int vec = row & 15, im = row >> 4;
+    const int vec = lane & 15, kg = lane >> 4;
     const bool live = vec < nv;
     const uint32_t* base = (const uint32_t*)(Vb + (live ? vec : 0) * vstride + q * n);
-    // a wave takes GU consecutive groups of 16 elements per pass (256 contiguous bytes of each
-    // vector, all loads issued before the products)
+    // a wave takes GU consecutive chunks of 32 elements per pass, all loads before the products
     constexpr int GU = 4;
-    const long long ngroups = (n + 15) / 16;
+    const long long nch = (n + 31) / 32;
     const long long wid = (long long)blockIdx.x * 4 + wave, nw = (long long)nblk * 4;
-    lqt_f16v acc = {};
-    double accd[16];
-#pragma unroll
-    for (int v = 0; v < 16; v++) accd[v] = 0;
+    lqt_f4v arr = {}, aii = {}, ari = {};
+    double drr[4] = {0, 0, 0, 0}, dii[4] = {0, 0, 0, 0}, dri[4] = {0, 0, 0, 0};
     int cnt = 0;
-    for (long long g0 = wid * GU; g0 < ngroups; g0 += nw * GU) {
+    for (long long c0 = wid * GU; c0 < nch; c0 += nw * GU) {
         uint32_t w[GU][8];
 #pragma unroll
         for (int u = 0; u < GU; u++) {
-            const long long e = (g0 + u) * 16 + half * 8;
+            const long long e = (c0 + u) * 32 + kg * 8;
             if (live && e + 8 <= n) {
                 const uint4 a = *(const uint4*)(base + e), b = *(const uint4*)(base + e + 4);
                 w[u][0] = a.x, w[u][1] = a.y, w[u][2] = a.z, w[u][3] = a.w;
@@ -734,26 +732,42 @@ __global__ __launch_bounds__(256) void k_sgram_mf(const S* __restrict__ Vb, long
             }
         }
 #pragma unroll
-        for (int u = 0; u < GU; u++) acc = mfma_xxt<S>(w[u], im, acc);
+        for (int u = 0; u < GU; u++) {
+            // 8 complex values (re low, im high 16 bits) -> packed real and imaginary halves
+            uint32_t re[4], im[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                re[t] = __builtin_amdgcn_perm(w[u][2 * t + 1], w[u][2 * t], 0x05040100u);
+                im[t] = __builtin_amdgcn_perm(w[u][2 * t + 1], w[u][2 * t], 0x07060302u);
+            }
+            arr = mfma_rows<S>(re, re, arr);
+            aii = mfma_rows<S>(im, im, aii);
+            ari = mfma_rows<S>(re, im, ari);
+        }
         cnt += GU;
         if (cnt >= 64) {
 #pragma unroll
-            for (int v = 0; v < 16; v++) {
-                accd[v] += acc[v];
-                acc[v] = 0;
+            for (int v = 0; v < 4; v++) {
+                drr[v] += arr[v], dii[v] += aii[v], dri[v] += ari[v];
+                arr[v] = aii[v] = ari[v] = 0;
             }
             cnt = 0;
         }
     }
 #pragma unroll
-    for (int v = 0; v < 16; v++) accd[v] += acc[v];
-    // sum the four waves' tiles in LDS
-    for (int t = threadIdx.x; t < 32 * 33; t += 256) (&red[0][0])[t] = 0;
+    for (int v = 0; v < 4; v++) drr[v] += arr[v], dii[v] += aii[v], dri[v] += ari[v];
+    // sum the four waves' tiles in LDS: lane l holds rows 4 (l / 16) + v, column l % 16
+    for (int t = threadIdx.x; t < 3 * 16 * 17; t += 256) (&red[0][0][0])[t] = 0;
     __syncthreads();
     for (int wv = 0; wv < 4; wv++) {
         if (wave == wv)
 #pragma unroll
-            for (int v = 0; v < 16; v++) red[8 * (v / 4) + 4 * half + (v % 4)][row] += accd[v];
+            for (int v = 0; v < 4; v++) {
+                const int r = 4 * kg + v;
+                red[0][r][vec] += drr[v];
+                red[1][r][vec] += dii[v];
+                red[2][r][vec] += dri[v];
+            }
         __syncthreads();
     }
     const int NP = nv * (nv + 1) / 2;
@@ -764,10 +778,9 @@ __global__ __launch_bounds__(256) void k_sgram_mf(const S* __restrict__ Vb, long
             i++;
         }
         const int j = i + rem;
-        const double re = red[i][j] + red[16 + i][16 + j], imv = red[i][16 + j] - red[16 + i][j];
         double* o = part + ((long long)q * nblk + blockIdx.x) * 2 * NP;
-        o[2 * p] = re;
-        o[2 * p + 1] = imv;
+        o[2 * p] = red[0][i][j] + red[1][i][j];
+        o[2 * p + 1] = red[2][i][j] - red[2][j][i];
     }
 }
 
