@@ -319,6 +319,7 @@ struct Net {
     std::vector<float> w;  // FP32 master weights (complex pairs), host copy
     DBuf wf;               // the weights the kernels use (BF16-rounded values held as FP32)
     DBuf act;              // two FP32 activation fields for the hidden layers
+    DBuf wa;               // one layer's weights as matrix-product operands
     DBuf train[8];         // training workspace (weights, activations, deltas, Gram blocks)
 };
 

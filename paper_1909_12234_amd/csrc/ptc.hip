@@ -7,8 +7,9 @@
 //   T_0 = 1, (T_{1+2mu} v)(x) = U_mu(x) v(x+mu), (T_{2+2mu} v)(x) = U_mu(x-mu)^+ v(x-mu),
 // with the links of the operator (antiperiodic sign folded in), so the layer commutes with
 // gauge transformations.  The adjoint of a layer is a layer with path-swapped (+mu <-> -mu),
-// conjugate-transposed weights, which gives the backward pass.  Arithmetic is FP32; the
-// weights live on the device in BF16 (rounded once when set).
+// conjugate-transposed weights, which gives the backward pass.  Arithmetic is FP32: the
+// transports on the vector units, the channel mixing on the matrix cores; the weights live
+// on the device in BF16 (rounded once when set).
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -39,85 +40,220 @@ __device__ __forceinline__ void pst(S* p, float2 v) {
         io<S>::st(p, v);
 }
 
-// One layer, FI -> FO features, one thread per site, nrhs fields (grid.y).  Weights W
-// [9][FO][FI] complex FP32 in LDS.  The FP32 links are [mu][ab][V].
-template <int FI, int FO, typename SI, typename SO>
-__global__ __launch_bounds__(256) void k_ptc_layer(const float2* __restrict__ U, const SI* __restrict__ in,
-                                                   SO* __restrict__ out, const float2* __restrict__ Wg, int L0, int L1,
-                                                   int L2, int L3) {
-    __shared__ float2 W[9 * FO * FI];
-    for (int i = threadIdx.x; i < 9 * FO * FI; i += blockDim.x) W[i] = Wg[i];
-    __syncthreads();
-    const int V = L0 * L1 * L2 * L3;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
-    const int r = blockIdx.y;
-    const SI* vin = in + (long long)r * FI * 3 * V;
-    SO* vout = out + (long long)r * FO * 3 * V;
-    const int x = s % L0, y = (s / L0) % L1, z = (s / (L0 * L1)) % L2, t = s / (L0 * L1 * L2);
-    const int st[4] = {1, L0, L0 * L1, L0 * L1 * L2};
-    const int co[4] = {x, y, z, t};
-    const int Ls[4] = {L0, L1, L2, L3};
-    float2 acc[FO][3];
+typedef float pf4 __attribute__((ext_vector_type(4)));
+
+// 4 x 4 transpose of 16-lane rows over four registers: on return r[t] holds, in lane row q,
+// what r[q] held in lane row t (two 32-lane swaps, then two 16-lane swaps).
+__device__ __forceinline__ void rows_transpose4(float (&r)[4]) {
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(r[0]), __float_as_uint(r[2]), false, false);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(r[1]), __float_as_uint(r[3]), false, false);
+    auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+    auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+    r[0] = __uint_as_float(c[0]);
+    r[1] = __uint_as_float(c[1]);
+    r[2] = __uint_as_float(d[0]);
+    r[3] = __uint_as_float(d[1]);
+}
+
+// The A operand of the channel-mixing products of one layer, FI -> FO features:
+// WA[p][h][lane] = (A of product 2h, A of product 2h + 1) for path p, input-feature group h
+// (features 4h..4h+3) and the lane's matrix position (row lane % 16, K slot lane / 16).
+// Row 2f + oc is output feature f, re (oc = 0) or im (oc = 1), zero for f >= FO; K slot q of
+// product 2h + ic is input feature 4h + q, re (ic = 0) or im (ic = 1).  For the complex
+// weight w = W[p][f][g]: (re, re) and (im, im) take Re w, (re, im) -Im w, (im, re) Im w.
+template <int FI, int FO>
+__global__ __launch_bounds__(256) void k_ptc_aprep(const float2* __restrict__ Wg, float2* __restrict__ WA) {
+    constexpr int NH = FI / 4;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= 9 * NH * 64) return;
+    const int l = i % 64, h = (i / 64) % NH, p = i / (64 * NH);
+    const int f = (l & 15) >> 1, oc = l & 1, g = 4 * h + (l >> 4);
+    float a[2] = {0.f, 0.f};
+    if (f < FO) {
+        const float2 w = Wg[(p * FO + f) * FI + g];
+        for (int ic = 0; ic < 2; ic++) a[ic] = (oc == ic) ? w.x : (oc ? w.y : -w.y);
+    }
+    WA[i] = make_float2(a[0], a[1]);
+}
+
+// element i of an array through a wave-uniform base and a 32-bit byte offset (the load takes
+// a scalar base and a vector offset)
+template <typename S>
+__device__ __forceinline__ const S* ptc_at(const S* base, uint32_t i) {
+    return (const S*)((const char*)base + i * (uint32_t)sizeof(S));
+}
+
+// Neighbour of the lane's site sc along path p (1 + 2 mu: +mu, 2 + 2 mu: -mu; 0: sc itself),
+// from the boundary bits lo/hi (bit mu set where the coordinate is 0 / L_mu - 1).
+__device__ __forceinline__ uint32_t ptc_nbr(int p, uint32_t sc, uint32_t lo, uint32_t hi, const uint32_t (&st)[4],
+                                            const int (&Ls)[4]) {
+    if (p == 0) return sc;
+    const int mu = (p - 1) >> 1;
+    const uint32_t wrap = (uint32_t)(Ls[mu] - 1) * st[mu];
+    if (((p - 1) & 1) == 0) return ((hi >> mu) & 1u) ? sc - wrap : sc + st[mu];
+    return ((lo >> mu) & 1u) ? sc + wrap : sc - st[mu];
+}
+
+// the link of path p (1..8) at the lane's site: U_mu(x) forward, U_mu(x - mu) backward
+struct PtcLink {
+    float2 u[9];
+};
+__device__ __forceinline__ void ptc_load_link(PtcLink& L, int p, const float2* __restrict__ U, uint32_t V,
+                                              uint32_t sc, uint32_t ns) {
+    const int mu = (p - 1) >> 1;
+    const uint32_t ls = (((p - 1) & 1) == 0) ? sc : ns;
 #pragma unroll
-    for (int f = 0; f < FO; f++)
+    for (int k = 0; k < 9; k++) L.u[k] = *ptc_at(U, (uint32_t)(mu * 9 + k) * V + ls);
+}
+
+// 4 input features (the group that vb points at) at the neighbour ns, and the A operands wa
+// of the group's 2 products on path p
+template <typename SI>
+struct PtcVec {
+    float2 v[4][3];
+    float2 wa;
+};
+template <typename SI>
+__device__ __forceinline__ void ptc_load_vec(PtcVec<SI>& B, const SI* __restrict__ vb, uint32_t qoff, uint32_t V,
+                                             uint32_t ns, const float2* __restrict__ wa) {
 #pragma unroll
-        for (int a = 0; a < 3; a++) acc[f][a] = make_float2(0, 0);
-#pragma unroll 1
-    for (int p = 0; p < 9; p++) {
-        float2 tv[FI][3];
-        if (p == 0) {
+    for (int k = 0; k < 4; k++)
 #pragma unroll
-            for (int g = 0; g < FI; g++)
+        for (int b = 0; b < 3; b++) B.v[k][b] = pld<SI>(ptc_at(vb, qoff + (uint32_t)(3 * k + b) * V + ns));
+    B.wa = *wa;
+}
+
+// Transport and mix one feature group on path p: colour by colour, the 4 transported
+// features (path 0: the features themselves) go through the lane-row transpose into the 2
+// products (re, im) of each of the 4 fields.
+template <typename SI>
+__device__ __forceinline__ void ptc_comp(const PtcLink& L, const PtcVec<SI>& B, int p, pf4 (&acc)[4][3]) {
+    const bool fwd = ((p - 1) & 1) == 0;
 #pragma unroll
-                for (int a = 0; a < 3; a++) tv[g][a] = pld<SI>(vin + (long long)(3 * g + a) * V + s);
-        } else {
-            const int mu = (p - 1) >> 1;
-            const bool fwd = ((p - 1) & 1) == 0;
-            int ns;
-            if (fwd)
-                ns = (co[mu] == Ls[mu] - 1) ? s - (Ls[mu] - 1) * st[mu] : s + st[mu];
-            else
-                ns = (co[mu] == 0) ? s + (Ls[mu] - 1) * st[mu] : s - st[mu];
-            const int ls = fwd ? s : ns;
-            float2 u[9];
+    for (int a = 0; a < 3; a++) {
+        float2 tv[4];
 #pragma unroll
-            for (int i = 0; i < 9; i++) u[i] = U[(long long)(mu * 9 + i) * V + ls];
+        for (int k = 0; k < 4; k++) {
+            if (p == 0) {
+                tv[k] = B.v[k][a];
+            } else {
+                float re = 0.f, im = 0.f;
 #pragma unroll
-            for (int g = 0; g < FI; g++) {
-                float2 v[3];
-#pragma unroll
-                for (int b = 0; b < 3; b++) v[b] = pld<SI>(vin + (long long)(3 * g + b) * V + ns);
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    float re = 0, im = 0;
-#pragma unroll
-                    for (int b = 0; b < 3; b++) {
-                        // forward: U[a][b]; backward: conj(U[b][a])
-                        const float2 l = fwd ? u[3 * a + b] : make_float2(u[3 * b + a].x, -u[3 * b + a].y);
-                        re += l.x * v[b].x - l.y * v[b].y;
-                        im += l.x * v[b].y + l.y * v[b].x;
-                    }
-                    tv[g][a] = make_float2(re, im);
+                for (int b = 0; b < 3; b++) {
+                    // forward: U[a][b]; backward: conj(U[b][a])
+                    const float lx = fwd ? L.u[3 * a + b].x : L.u[3 * b + a].x;
+                    const float ly = fwd ? L.u[3 * a + b].y : -L.u[3 * b + a].y;
+                    re = fmaf(lx, B.v[k][b].x, fmaf(-ly, B.v[k][b].y, re));
+                    im = fmaf(lx, B.v[k][b].y, fmaf(ly, B.v[k][b].x, im));
                 }
+                tv[k] = make_float2(re, im);
             }
         }
 #pragma unroll
-        for (int f = 0; f < FO; f++)
+        for (int c = 0; c < 2; c++) {
+            float bt[4];
 #pragma unroll
-            for (int g = 0; g < FI; g++) {
-                const float2 w = W[(p * FO + f) * FI + g];
+            for (int k = 0; k < 4; k++) bt[k] = c ? tv[k].y : tv[k].x;
+            rows_transpose4(bt);
 #pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    acc[f][a].x += w.x * tv[g][a].x - w.y * tv[g][a].y;
-                    acc[f][a].y += w.x * tv[g][a].y + w.y * tv[g][a].x;
-                }
-            }
+            for (int k = 0; k < 4; k++)
+                acc[k][a] = __builtin_amdgcn_mfma_f32_16x16x4f32(c ? B.wa.y : B.wa.x, bt[k], acc[k][a], 0, 0, 0);
+        }
     }
+}
+
+// One layer, FI -> FO features.  A wave takes 16 consecutive sites (matrix column c = lane
+// % 16) of 4 fields (lane row q = lane / 16 is field 4 rg + q).  For each group of 4 input
+// features and each path, every lane transports the group of its own (site, field) on the
+// vector units (one link load serves the 4 fields); the channel mixing is a real matrix
+// product on the matrix cores, 16 x 16 x 4 in FP32, with
+//   rows 2f + c (output feature f, c = re/im; rows past 2 FO are zero),
+//   columns the 16 sites, one product chain per field and colour,
+//   K over (path, input feature, re/im): product 2h + c takes the features 4h + q in K slot q.
+// A 4 x 4 transpose of lane rows turns the per-(site, field) values into the B operands of
+// the 4 fields.  The accumulator of lane (c, q) for field t holds output features 2q, 2q + 1
+// (re, im) of site c.  Lanes past the lattice or the last field load from a valid clamped
+// (site, field): their values only reach matrix columns that are not stored.  Waves walk
+// (site chunk, field group) with the chunk fastest, and the blocks are renumbered so each
+// XCD takes a contiguous range: the neighbour rows a wave reads are those that concurrent
+// waves on the same L2 read as their own.  The loads of the next step are issued before the
+// current step computes.  FP32 links [mu][ab][V].  Byte offsets within 4
+// fields are 32-bit (4 * 3 FI * V * sizeof(SI) < 4 GiB, checked by the caller).
+template <int FI, int FO, typename SI, typename SO>
+__global__ __launch_bounds__(256) void k_ptc_layer(const float2* __restrict__ U, const SI* __restrict__ in,
+                                                   SO* __restrict__ out, const float2* __restrict__ WA, int nrhs,
+                                                   int L0, int L1, int L2, int L3) {
+    static_assert(FI == 4 || FI == 8, "4 or 8 input features");
+    static_assert(FO == 4 || FO == 8, "4 or 8 output features");
+    constexpr int NH = FI / 4;  // input-feature groups
+    const uint32_t V = (uint32_t)(L0 * L1 * L2 * L3);
+    const int nchunk = (int)((V + 15) >> 4);
+    const int lb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);  // gridDim.x % 8 == 0
+    const int task = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
+    const int rg = task / nchunk, chunk = task - rg * nchunk;
+    if (4 * rg >= nrhs) return;  // whole wave past the last field
+    const int lane = threadIdx.x & 63, q = lane >> 4;
+    const uint32_t s = (uint32_t)(chunk * 16 + (lane & 15));
+    const bool site_ok = s < V;
+    const uint32_t sc = site_ok ? s : 0u;
+    const uint32_t qoff = (4 * rg + q < nrhs ? (uint32_t)q : 0u) * (uint32_t)(FI * 3) * V;
+    const SI* vb = in + (long long)(4 * rg) * FI * 3 * V;
+    const int Ls[4] = {L0, L1, L2, L3};
+    const uint32_t st[4] = {1u, (uint32_t)L0, (uint32_t)(L0 * L1), (uint32_t)(L0 * L1 * L2)};
+    // per-lane boundary bits: bit mu of lo/hi set where the coordinate is 0 / L_mu - 1
+    uint32_t lo = 0, hi = 0;
+    {
+        uint32_t rem = sc;
 #pragma unroll
-    for (int f = 0; f < FO; f++)
+        for (int mu = 0; mu < 4; mu++) {
+            const uint32_t cm = rem % (uint32_t)Ls[mu];
+            rem /= (uint32_t)Ls[mu];
+            lo |= (cm == 0u) << mu;
+            hi |= (cm == (uint32_t)(Ls[mu] - 1)) << mu;
+        }
+    }
+    pf4 acc[4][3];
 #pragma unroll
-        for (int a = 0; a < 3; a++) pst<SO>(vout + (long long)(3 * f + a) * V + s, acc[f][a]);
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) acc[k][a] = pf4{0.f, 0.f, 0.f, 0.f};
+    // paths p = 0..8, each over the NH feature groups; the next (path, group)'s loads are in
+    // flight while the current one computes, the links loaded once per path
+    PtcLink L[2];
+    PtcVec<SI> B[2];
+    ptc_load_vec<SI>(B[0], vb, qoff, V, sc, WA + lane);
+#pragma unroll
+    for (int p = 0; p < 9; p++) {
+        const PtcLink& Lc = L[p & 1];
+        const uint32_t nn = ptc_nbr(p + 1 < 9 ? p + 1 : 0, sc, lo, hi, st, Ls);
+        if (NH == 2) {
+            ptc_load_vec<SI>(B[1], vb + 12 * V, qoff, V, ptc_nbr(p, sc, lo, hi, st, Ls), WA + (p * 2 + 1) * 64 + lane);
+            ptc_comp<SI>(Lc, B[0], p, acc);
+            if (p + 1 < 9) {
+                ptc_load_link(L[(p + 1) & 1], p + 1, U, V, sc, nn);
+                ptc_load_vec<SI>(B[0], vb, qoff, V, nn, WA + (p + 1) * 2 * 64 + lane);
+            }
+            ptc_comp<SI>(Lc, B[1], p, acc);
+        } else {
+            if (p + 1 < 9) {
+                ptc_load_link(L[(p + 1) & 1], p + 1, U, V, sc, nn);
+                ptc_load_vec<SI>(B[(p + 1) & 1], vb, qoff, V, nn, WA + (p + 1) * 64 + lane);
+            }
+            ptc_comp<SI>(Lc, B[p & 1], p, acc);
+        }
+    }
+    if (2 * q < FO && site_ok) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (4 * rg + k >= nrhs) break;
+            SO* vo = out + (long long)(4 * rg + k) * FO * 3 * V;
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int hh = 0; hh < 2; hh++)
+                    pst<SO>(vo + (3 * (2 * q + hh) + a) * V + s, make_float2(acc[k][a][2 * hh], acc[k][a][2 * hh + 1]));
+        }
+    }
 }
 
 // Transport only, all nine paths: out[p][g] = T_p in_g (FP64 fields [g][colour][V] in,
@@ -217,9 +353,19 @@ void ptc_set(lqt_ctx* c, const float* w, bool round_bf16) {
 template <int FI, int FO, typename SI, typename SO>
 static void layer_launch(lqt_ctx* c, const float2* W, const SI* in, SO* out, int nrhs) {
     const Geom& g = c->g;
-    dim3 grid((g.V + 255) / 256, nrhs);
-    hipLaunchKernelGGL((k_ptc_layer<FI, FO, SI, SO>), grid, dim3(256), 0, c->stream, c->U[LQT_F32].as<float2>(), in,
-                       out, W, g.L[0], g.L[1], g.L[2], g.L[3]);
+    constexpr int nwa = 9 * (FI / 4) * 64;
+    c->net.wa.ensure(sizeof(float2) * 9 * 2 * 64);  // the largest layer: never reallocated between layers
+    float2* WA = c->net.wa.as<float2>();
+    hipLaunchKernelGGL((k_ptc_aprep<FI, FO>), dim3((nwa + 255) / 256), dim3(256), 0, c->stream, W, WA);
+    LQT_HIP(hipGetLastError());
+    // 4 waves per block, one wave per (16-site chunk, group of 4 fields); a multiple of 8 blocks
+    const long long tasks = (long long)((g.V + 15) / 16) * ((nrhs + 3) / 4);
+    const long long nb = ((tasks + 3) / 4 + 7) / 8 * 8;
+    if (nb > 0x7fffffffLL) throw Error{LQT_EINVAL, "net layer launch too large"};
+    if ((double)4 * 3 * FI * g.V * sizeof(SI) >= 4294967296.0)
+        throw Error{LQT_EINVAL, "lattice too large for the net layer's 32-bit offsets"};
+    hipLaunchKernelGGL((k_ptc_layer<FI, FO, SI, SO>), dim3((unsigned)nb), dim3(256), 0, c->stream,
+                       c->U[LQT_F32].as<float2>(), in, out, (const float2*)WA, nrhs, g.L[0], g.L[1], g.L[2], g.L[3]);
     LQT_HIP(hipGetLastError());
 }
 
