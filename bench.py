@@ -76,7 +76,12 @@ def cpu_baseline(U, dims, mass, iters_per_probe, budget_s=15.0):
     }
 
 
-VALU_PEAK_TFLOPS = 78.6  # FP32/FP64 FMA on the vector ALUs without packed FP32
+VALU_PEAK_TFLOPS = 78.6  # FP32/FP64 FMA on the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak of the MI355X
+# useful flops of one transport-net application per site and field: channel mixing
+# 9 paths x (4*8 + 8*8 + 8*8 + 8*4) complex products x 3 colours, transports 8 paths x
+# (4 + 8 + 8 + 8) input features x 9 complex products, 8 flops per complex product
+NET_FLOPS_PER_SITE_FIELD = 8 * (9 * (32 + 64 + 64 + 32) * 3 + 8 * 28 * 9)
 
 
 def dslash_flops(byt, calls, sites, b):
@@ -122,6 +127,15 @@ def _roofline(kt, sites=None, b=None, tile=None):
         tf = dslash_flops(byt, calls, sites, b) / (ms * 1e-3) / 1e12
         base.update({"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tf / VALU_PEAK_TFLOPS, 4),
+                     "hbm_algorithmic_gbps": round(byt / (ms * 1e-3) / 1e9, 1)})
+        return base
+    if fam == "net" and sites and b:
+        # the timer counts 12 (2b) bytes in and out per site and field, 4 FP32 activation
+        # fields of 24 complex numbers and the FP32 links of each of the 4 layers
+        site_fields = (byt - 4.0 * 72 * 4 * sites * calls) / (48.0 * b + 768.0)
+        tf = NET_FLOPS_PER_SITE_FIELD * site_fields / (ms * 1e-3) / 1e12
+        base.update({"bound": "mfma", "achieved": round(tf, 2), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / MFMA_F32_PEAK_TFLOPS, 4),
                      "hbm_algorithmic_gbps": round(byt / (ms * 1e-3) / 1e9, 1)})
         return base
     achieved = byt / (ms * 1e-3) / 1e9
@@ -239,8 +253,8 @@ def run_net(a, w):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); probes are independent, see the "
-              "sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the probes are independent "
+              "solves, so several GPUs would each take a share of them", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

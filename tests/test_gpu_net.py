@@ -33,7 +33,7 @@ def _ctx(lq, dims, mass, eps=0.5, seed=1):
     return c, U
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 4, 6), (8, 6, 4, 10)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 4, 6), (8, 6, 4, 10), (8, 8, 4, 6)])
 def test_forward_matches_oracle(gpu, dims):
     lq = gpu
     print(f"net forward dims={dims}", flush=True)
