@@ -34,6 +34,10 @@ def parse():
     ap.add_argument("--nprobes", type=int, default=None, help="override the probe count (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GMRES comparison")
+    ap.add_argument("--dslash-sweep", action="store_true",
+                    help="only time the Wilson operator at its tuned tile for every storage precision and "
+                         "n in {1, 8, 16, 32, 64} right-hand sides on 16^3x32 and 32^3x64, beside a device copy, "
+                         "one JSON line per case, and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration) and exit")
     ap.add_argument("--inner-prec", choices=["f32", "f16", "bf16"], default=None,
@@ -250,6 +254,60 @@ def run_net(a, w):
            "train_pairs": w.get("train_pairs", 256), "train_loss": loss})
 
 
+def run_dslash_sweep(a):
+    """The Wilson operator alone: for each lattice, storage precision and number of right-hand
+    sides, the autotuner's tile, then 5 launches timed by the library's HIP events; algorithmic
+    bytes V (72 b + 48 b n) per launch against 8 TB/s and against a plain device copy (4 GiB
+    read + 4 GiB written, timed with events on the current stream)."""
+    import torch
+
+    import paper_1909_12234_amd as lq
+    import synth
+
+    torch.cuda.set_device(0)
+    nb = 1 << 30
+    src = torch.ones(nb, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * 4 * nb / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    print(json.dumps({"copy_gbps": round(copy_gbs, 1), "copy_bytes": 8 * nb}), flush=True)
+    names = {lq.F64: "f64", lq.F32: "f32", lq.F16: "f16", lq.BF16: "bf16"}
+    for dims in [(16, 16, 16, 32), (32, 32, 32, 64)]:
+        U = synth.su3_links(dims, 0.5, 1)
+        ctx = lq.Context(dims, -1.9)
+        ctx.set_gauge(U)
+        del U
+        N = ctx.N
+        for prec in (lq.F64, lq.F32, lq.F16, lq.BF16):
+            for n in (1, 8, 16, 32, 64):
+                dt = torch.complex128 if prec == lq.F64 else torch.complex64
+                x = torch.randn((n, N), dtype=dt, device="cuda")
+                ms_tune, tile = ctx.tune(prec, n, return_tile=True)
+                ctx.apply(x, prec=prec)
+                torch.cuda.synchronize()
+                ctx.kernel_times(mode=2)
+                for _ in range(5):
+                    y = ctx.apply(x, prec=prec)
+                torch.cuda.synchronize()
+                ms, calls, byt = ctx.kernel_times(mode=3)["dslash"]
+                gbs = byt / (ms * 1e-3) / 1e9
+                print(json.dumps({"lattice": list(dims), "prec": names[prec], "nrhs": n, "tile": list(tile),
+                                  "us_per_launch": round(ms * 1e3 / calls, 2), "alg_bytes": round(byt / calls),
+                                  "gbps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                  "frac_copy": round(gbs / copy_gbs, 4), "tuner_us": round(ms_tune * 1e3, 2)}),
+                      flush=True)
+                del x, y
+        ctx.close()
+        torch.cuda.empty_cache()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -259,6 +317,8 @@ def main():
     import numpy as np
     import torch
 
+    if a.dslash_sweep:
+        return run_dslash_sweep(a)
     if a.calibrate_copy:
         n = a.calibrate_copy * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")
