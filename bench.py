@@ -38,6 +38,9 @@ def parse():
                     help="only time the Wilson operator at its tuned tile for every storage precision and "
                          "n in {1, 8, 16, 32, 64} right-hand sides on 16^3x32 and 32^3x64, beside a device copy, "
                          "one JSON line per case, and exit")
+    ap.add_argument("--dslash-tile", default=None, metavar="R,BLOCK,CHUNK,KIND",
+                    help="use this operator tile for the inner storage instead of the autotuner's choice "
+                         "(for counter runs of a given tile)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration) and exit")
     ap.add_argument("--inner-prec", choices=["f32", "f16", "bf16"], default=None,
@@ -97,22 +100,26 @@ def dslash_flops(byt, calls, sites, b):
 
 
 def _measured_traffic(family, tile=None):
-    """HBM bytes per launch of a kernel family from the recorded counter runs, or None when
-    the kernel's source has changed since they were taken (hash mismatch), the tuned tile is
-    not the one measured, or none exist."""
+    """HBM bytes per launch of a kernel family from the recorded counter runs (one record per
+    measured tile), or None when the kernel's source has changed since they were taken (hash
+    mismatch), the tuned tile is none of those measured, or none exist."""
     import hashlib
 
     try:
         with open(os.path.join(ROOT, "paper_1909_12234_amd", "traffic.json")) as f:
-            rec = json.load(f)["kernels"].get(family)
-        if rec is None:
+            recs = json.load(f)["kernels"].get(family)
+        if recs is None:
             return None
-        if tile is not None and "tile" in rec and list(rec["tile"]) != list(tile):
-            return None
-        with open(os.path.join(ROOT, "paper_1909_12234_amd", rec["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_16"]:
-                return None
-        return rec["fetch_bytes"] + rec["write_bytes"]
+        if isinstance(recs, dict):
+            recs = [recs]
+        for rec in recs:
+            if tile is not None and "tile" in rec and list(rec["tile"]) != list(tile):
+                continue
+            with open(os.path.join(ROOT, "paper_1909_12234_amd", rec["source"]), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_16"]:
+                    return None
+            return rec["fetch_bytes"] + rec["write_bytes"]
+        return None
     except (OSError, KeyError, ValueError):
         return None
 
@@ -120,8 +127,8 @@ def _measured_traffic(family, tile=None):
 def _roofline(kt, sites=None, b=None, tile=None):
     """Dominant kernel family by device time among those with algorithmic bytes.  The
     reduced-precision Wilson operator with FP32 arithmetic on the vector ALUs (tile kind 0) is
-    reported against their FMA peak; the packed-FP16 and matrix-core operators (kinds 2, 1)
-    and the other families against HBM."""
+    reported against their FMA peak; the packed-FP16 and matrix-core operators (kinds 2, 3, 1)
+    and the other families against HBM; the transport net against the FP32 matrix peak."""
     kind = tile[3] if tile else 0
     fam = max((f for f in kt if kt[f][2] > 0), key=lambda f: kt[f][0])
     ms, calls, byt = kt[fam]
@@ -351,6 +358,9 @@ def main():
     ctx = lq.Context(dims, mass)
     ctx.set_gauge(U)
     _, tile = ctx.tune(prec, nprobes, return_tile=True)
+    if a.dslash_tile:
+        tile = tuple(int(v) for v in a.dslash_tile.split(","))
+        ctx.set_tile(prec, nprobes, tile)
     ctx.tune(0, 1)
     t_basis = time.perf_counter()
     basis = (ctx.basis_eig(w["k"], xi=1e-2, prec=lq.F32, verbose=1, outer_maxit=a.basis_iters)
@@ -398,7 +408,7 @@ def main():
         "vs_baseline": None,
         "dtype": w["inner_prec"],
         "dtype_detail": f"{w['inner_prec']} links and Krylov vectors, fp32 accumulate, fp64 defect correction"
-                        + (" (operator half spinors in packed fp16)" if tile[3] == 2 else ""),
+                        + (" (operator half spinors in packed fp16)" if tile[3] in (2, 3) else ""),
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: Wilson-Dirac {dims[0]}^3x{dims[3]}, eps={eps}, m={mass}, "
                                f"{nprobes} Rademacher probes, xi={w['xi']}, oblique g5 deflation k={w.get('k', 0)}, "
@@ -409,7 +419,8 @@ def main():
         "dslash_frac_of_peak": round(dslash_gbs / HBM_PEAK_GBS, 4) if dslash_gbs else None,
         "roofline": roof,
         "dslash_tile": {"per_thread_or_lane": tile[0], "block": tile[1], "chunk": tile[2],
-                        "kernel": {0: "vector ALUs, fp32", 1: "matrix cores", 2: "vector ALUs, packed fp16"}[tile[3]]},
+                        "kernel": {0: "vector ALUs, fp32", 1: "matrix cores", 2: "vector ALUs, packed fp16",
+                                   3: "vector ALUs, packed fp16, links staged in LDS for 8 groups"}[tile[3]]},
         "kernel_ms": {f: round(kt[f][0], 2) for f in kt},
         "iters_per_probe_mixed": round(iters_mixed, 1),
         "estimate": {"trace": results[-1]["trace_re"], "var_sample": results[-1]["var_sample"],

@@ -275,11 +275,24 @@ struct PkBuf {
     hv2 u[9];
     hv2 p[R][12];
 };
-template <int R>
+// The links of a block's sites staged in LDS by the staged-link operator: word i of
+// direction mu of site s0 + j at [(9 mu + i) 256 + j] (dynamic shared memory, 36 KB).
+extern __shared__ hv2 lqt_staged_links[];
+
+// With LDSU the forward link (direction MU at the thread's own site sl) comes from the
+// staged links; backward links (at a neighbour) are read from memory, where those of the
+// block's own sites are in the lines the staging has just read.
+template <int R, bool LDSU = false, int MU = 0, bool BWD = false>
 __device__ __forceinline__ void pk_load(PkBuf<R>& b, const h2* __restrict__ Um, const h2* const inb[R], uint32_t V,
-                                        uint32_t sl, uint32_t sn, bool g5in) {
+                                        uint32_t sl, uint32_t sn, bool g5in, uint32_t s0 = 0) {
+    if constexpr (LDSU && !BWD) {
+        const uint32_t li = (9 * MU) * 256 + (sl - s0);
 #pragma unroll
-    for (int i = 0; i < 9; i++) b.u[i] = ldh(Um, i * V + sl);
+        for (int i = 0; i < 9; i++) b.u[i] = lqt_staged_links[i * 256 + li];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; i++) b.u[i] = ldh(Um, i * V + sl);
+    }
 #pragma unroll
     for (int r = 0; r < R; r++)
 #pragma unroll
@@ -298,30 +311,41 @@ __device__ __forceinline__ void pk_comp(const PkBuf<R>& b, cpx<float> acc[R][12]
         rebuild_add<MU, SG>(acc[r], o0, o1);
     }
 }
-template <bool DAG, int R>
+template <bool DAG, int R, bool LDSU = false>
 __device__ __forceinline__ void hop_all_pk(const h2* __restrict__ U, const h2* const inb[R], uint32_t V, uint32_t s,
                                            const uint32_t nf[4], const uint32_t nb[4], bool g5in,
-                                           cpx<float> acc[R][12]) {
+                                           cpx<float> acc[R][12], uint32_t s0 = 0) {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     const h2* U1 = U + 9ll * V;
     const h2* U2 = U + 18ll * V;
     const h2* U3 = U + 27ll * V;
+    // with staged links the scheduler would pull every LDS read to the top (one hop's reads
+    // in flight is the design): a scheduling fence after each hop's products
+    auto fence = [] {
+        if constexpr (LDSU) __builtin_amdgcn_sched_barrier(0);
+    };
     PkBuf<R> A, B;
-    pk_load<R>(A, U, inb, V, s, nf[0], g5in);
-    pk_load<R>(B, U, inb, V, nb[0], nb[0], g5in);
+    pk_load<R, LDSU, 0>(A, U, inb, V, s, nf[0], g5in, s0);
+    pk_load<R, LDSU, 0, true>(B, U, inb, V, nb[0], nb[0], g5in, s0);
     pk_comp<0, SF, false, R>(A, acc);
-    pk_load<R>(A, U1, inb, V, s, nf[1], g5in);
+    fence();
+    pk_load<R, LDSU, 1>(A, U1, inb, V, s, nf[1], g5in, s0);
     pk_comp<0, SB, true, R>(B, acc);
-    pk_load<R>(B, U1, inb, V, nb[1], nb[1], g5in);
+    fence();
+    pk_load<R, LDSU, 1, true>(B, U1, inb, V, nb[1], nb[1], g5in, s0);
     pk_comp<1, SF, false, R>(A, acc);
-    pk_load<R>(A, U2, inb, V, s, nf[2], g5in);
+    fence();
+    pk_load<R, LDSU, 2>(A, U2, inb, V, s, nf[2], g5in, s0);
     pk_comp<1, SB, true, R>(B, acc);
-    pk_load<R>(B, U2, inb, V, nb[2], nb[2], g5in);
+    fence();
+    pk_load<R, LDSU, 2, true>(B, U2, inb, V, nb[2], nb[2], g5in, s0);
     pk_comp<2, SF, false, R>(A, acc);
-    pk_load<R>(A, U3, inb, V, s, nf[3], g5in);
+    fence();
+    pk_load<R, LDSU, 3>(A, U3, inb, V, s, nf[3], g5in, s0);
     pk_comp<2, SB, true, R>(B, acc);
-    pk_load<R>(B, U3, inb, V, nb[3], nb[3], g5in);
+    fence();
+    pk_load<R, LDSU, 3, true>(B, U3, inb, V, nb[3], nb[3], g5in, s0);
     pk_comp<3, SF, false, R>(A, acc);
     pk_comp<3, SB, true, R>(B, acc);
 }
@@ -329,7 +353,7 @@ __device__ __forceinline__ void hop_all_pk(const h2* __restrict__ U, const h2* c
 // EPI 0: out = op(in).  EPI 1 (FP64 only): out = b - A in, with per-block partial |out|^2.
 // Right-hand side r of a group is field act[r0 + r] (act may be null: r0 + r) of in and b,
 // and field r0 + r of out.  Sites of the lattice table tab; padding sites get zeros.
-template <typename S, int R, int OPK, int EPI, bool PKH = false>
+template <typename S, int R, int OPK, int EPI, bool PKH = false, int G = 1>
 __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S* __restrict__ in, S* __restrict__ out,
                                                 const S* __restrict__ bvec, double* __restrict__ part,
                                                 const int* __restrict__ act, LatTab tab, int nrhs, long long in_stride,
@@ -338,24 +362,26 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
     constexpr bool g5in = OPK == LQT_A_G5, g5out = OPK == LQT_G5_A;
     using C = typename acc_of<S>::type;
     const uint32_t V = (uint32_t)tab.off[tab.nlat];
+    static_assert(G == 1 || (PKH && EPI == 0), "groups looped in the block: packed FP16 operator only");
     const int nsb = (int)((V + blockDim.x - 1) / blockDim.x);
     const int ngrp = (nrhs + R - 1) / R;
-    const int lb = xcd_block(nsb * ngrp);
+    const int ngb = (ngrp + G - 1) / G;  // blocks of G groups
+    const int lb = xcd_block(nsb * ngb);
     if (lb < 0) return;
     // Block order.  chunk = 0: site block major (a thread's R links serve every group in
     // turn).  chunk > 0: the sites are cut into chunks of `chunk` site blocks; each chunk is
     // swept once per right-hand-side group, so the +-t and +-z neighbours of a block are
     // read while they are still in the XCD's L2.
-    int sblk, grp;
+    int sblk, gblk;
     if (chunk <= 0) {
-        sblk = lb / ngrp;
-        grp = lb - sblk * ngrp;
+        sblk = lb / ngb;
+        gblk = lb - sblk * ngb;
     } else {
-        const int ch = lb / (chunk * ngrp);
+        const int ch = lb / (chunk * ngb);
         const int cs = min(chunk, nsb - ch * chunk);
-        const int rem = lb - ch * chunk * ngrp;
-        grp = rem / cs;
-        sblk = ch * chunk + (rem - grp * cs);
+        const int rem = lb - ch * chunk * ngb;
+        gblk = rem / cs;
+        sblk = ch * chunk + (rem - gblk * cs);
     }
     // lattice of this block (uniform: blocks never straddle lattices)
     const uint32_t s0 = (uint32_t)sblk * blockDim.x;
@@ -369,82 +395,104 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
     // out = scale * ((4 + m_k - shift) in - 1/2 hop(in)): shift 0, scale 1 is the operator itself
     const C diag = (C)((tab.diag[k] - shift) * scale);
     const C hs = (C)(-0.5 * scale);
-    const uint32_t s = s0 + threadIdx.x;
-    const int r0 = grp * R;
-    const int nr = min(R, nrhs - r0);
-    const S* inb[R];
-    const S* bb[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int rr = min(r0 + r, nrhs - 1);
-        const long long f = act ? act[rr] : rr;
-        inb[r] = in + f * in_stride;
-        bb[r] = (EPI == 1) ? bvec + f * in_stride : nullptr;
+    const uint32_t s_blk = s0 + threadIdx.x;
+    // G > 1: the block's links (direction mu, element i at [mu][i][256]) are staged in LDS once
+    // and serve the G groups of right-hand sides the block loops over
+    if constexpr (G > 1) {
+#pragma unroll 4
+        for (int k = 0; k < 36; k++)
+            lqt_staged_links[k * 256 + threadIdx.x] =
+                s_blk < V ? ldh((const h2*)U, k * V + s_blk) : hv2{(_Float16)0, (_Float16)0};
+        __syncthreads();
     }
     double nrm[R];
 #pragma unroll
     for (int r = 0; r < R; r++) nrm[r] = 0;
-    if (s < V) {
-        const uint32_t sl = s - base;  // site within lattice k
-        cpx<C> acc[R][12];
-#pragma unroll
-        for (int r = 0; r < R; r++)
-#pragma unroll
-            for (int c = 0; c < 12; c++) acc[r][c] = {0, 0};
-        const bool pad = sl >= Vk;
-        if (!pad) {
-            const int x = sl % L0;
-            const int y = (sl / L0) % L1;
-            const int z = (sl / (L0 * L1)) % L2;
-            const int t = sl / (L0 * L1 * L2);
-            const int s1 = L0, s2 = L0 * L1, s3 = L0 * L1 * L2;
-            const uint32_t xf = (x == L0 - 1) ? s - (L0 - 1) : s + 1;
-            const uint32_t xb = (x == 0) ? s + (L0 - 1) : s - 1;
-            const uint32_t yf = (y == L1 - 1) ? s - (L1 - 1) * s1 : s + s1;
-            const uint32_t yb = (y == 0) ? s + (L1 - 1) * s1 : s - s1;
-            const uint32_t zf = (z == L2 - 1) ? s - (L2 - 1) * s2 : s + s2;
-            const uint32_t zb = (z == 0) ? s + (L2 - 1) * s2 : s - s2;
-            const uint32_t tf = (t == L3 - 1) ? s - (L3 - 1) * s3 : s + s3;
-            const uint32_t tb = (t == 0) ? s + (L3 - 1) * s3 : s - s3;
-            if constexpr (PKH) {
-                const uint32_t nf[4] = {xf, yf, zf, tf}, nbk[4] = {xb, yb, zb, tb};
-                hop_all_pk<DAG, R>(U, inb, V, s, nf, nbk, g5in, acc);
-            } else {
-                hop_dir<0, DAG, R, S, C>(U, inb, V, s, xf, xb, g5in, acc);
-                hop_dir<1, DAG, R, S, C>(U, inb, V, s, yf, yb, g5in, acc);
-                hop_dir<2, DAG, R, S, C>(U, inb, V, s, zf, zb, g5in, acc);
-                hop_dir<3, DAG, R, S, C>(U, inb, V, s, tf, tb, g5in, acc);
-            }
-        }
+#pragma unroll 1
+    for (int gi = 0; gi < G; gi++) {
+        const int grp = gblk * G + gi;
+        if (grp >= ngrp) break;  // uniform over the block
+        // the site index is made opaque per group so that no load is hoisted out of the loop
+        // (hoisted, a site's 72 link words would live in registers across the groups)
+        uint32_t s = s_blk;
+        if constexpr (G > 1) asm volatile("" : "+v"(s));
+        const int r0 = grp * R;
+        const int nr = min(R, nrhs - r0);
+        const S* inb[R];
+        const S* bb[R];
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            if (r < nr) {
-                cpx<C> p[12];
-                if (!pad)
-                    load_spinor<S, C>(inb[r], V, s, g5in, p);
-                else
+            const int rr = min(r0 + r, nrhs - 1);
+            const long long f = act ? act[rr] : rr;
+            inb[r] = in + f * in_stride;
+            bb[r] = (EPI == 1) ? bvec + f * in_stride : nullptr;
+        }
+        if (s < V) {
+            const uint32_t sl = s - base;  // site within lattice k
+            cpx<C> acc[R][12];
 #pragma unroll
-                    for (int c = 0; c < 12; c++) p[c] = {0, 0};
-                S* o = out + (long long)(r0 + r) * out_stride;  // uniform
+            for (int r = 0; r < R; r++)
 #pragma unroll
-                for (int c = 0; c < 12; c++) {
-                    cpx<C> v = {fm(diag, p[c].x, hs * acc[r][c].x), fm(diag, p[c].y, hs * acc[r][c].y)};
-                    if (g5out && c >= 6) {
-                        v.x = -v.x;
-                        v.y = -v.y;
+                for (int c = 0; c < 12; c++) acc[r][c] = {0, 0};
+            const bool pad = sl >= Vk;
+            if (!pad) {
+                const int x = sl % L0;
+                const int y = (sl / L0) % L1;
+                const int z = (sl / (L0 * L1)) % L2;
+                const int t = sl / (L0 * L1 * L2);
+                const int s1 = L0, s2 = L0 * L1, s3 = L0 * L1 * L2;
+                const uint32_t xf = (x == L0 - 1) ? s - (L0 - 1) : s + 1;
+                const uint32_t xb = (x == 0) ? s + (L0 - 1) : s - 1;
+                const uint32_t yf = (y == L1 - 1) ? s - (L1 - 1) * s1 : s + s1;
+                const uint32_t yb = (y == 0) ? s + (L1 - 1) * s1 : s - s1;
+                const uint32_t zf = (z == L2 - 1) ? s - (L2 - 1) * s2 : s + s2;
+                const uint32_t zb = (z == 0) ? s + (L2 - 1) * s2 : s - s2;
+                const uint32_t tf = (t == L3 - 1) ? s - (L3 - 1) * s3 : s + s3;
+                const uint32_t tb = (t == 0) ? s + (L3 - 1) * s3 : s - s3;
+                if constexpr (PKH) {
+                    const uint32_t nf[4] = {xf, yf, zf, tf}, nbk[4] = {xb, yb, zb, tb};
+                    if constexpr (G > 1)
+                        hop_all_pk<DAG, R, true>((const h2*)U, (const h2* const*)inb, V, s, nf, nbk, g5in, acc, s0);
+                    else
+                        hop_all_pk<DAG, R>(U, inb, V, s, nf, nbk, g5in, acc);
+                } else {
+                    hop_dir<0, DAG, R, S, C>(U, inb, V, s, xf, xb, g5in, acc);
+                    hop_dir<1, DAG, R, S, C>(U, inb, V, s, yf, yb, g5in, acc);
+                    hop_dir<2, DAG, R, S, C>(U, inb, V, s, zf, zb, g5in, acc);
+                    hop_dir<3, DAG, R, S, C>(U, inb, V, s, tf, tb, g5in, acc);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (r < nr) {
+                    cpx<C> p[12];
+                    if (!pad)
+                        load_spinor<S, C>(inb[r], V, s, g5in, p);
+                    else
+#pragma unroll
+                        for (int c = 0; c < 12; c++) p[c] = {0, 0};
+                    S* o = out + (long long)(r0 + r) * out_stride;  // uniform
+#pragma unroll
+                    for (int c = 0; c < 12; c++) {
+                        cpx<C> v = {fm(diag, p[c].x, hs * acc[r][c].x), fm(diag, p[c].y, hs * acc[r][c].y)};
+                        if (g5out && c >= 6) {
+                            v.x = -v.x;
+                            v.y = -v.y;
+                        }
+                        if (EPI == 1) {
+                            const cpx<C> b = ld_c<C>(at(bb[r], c * V + s));
+                            v.x = b.x - v.x;
+                            v.y = b.y - v.y;
+                            nrm[r] += (double)v.x * v.x + (double)v.y * v.y;
+                        }
+                        st_c<C>(at(o, c * V + s), v);
                     }
-                    if (EPI == 1) {
-                        const cpx<C> b = ld_c<C>(at(bb[r], c * V + s));
-                        v.x = b.x - v.x;
-                        v.y = b.y - v.y;
-                        nrm[r] += (double)v.x * v.x + (double)v.y * v.y;
-                    }
-                    st_c<C>(at(o, c * V + s), v);
                 }
             }
         }
-    }
+    }  // groups of the block
     if (EPI == 1) {
+        const int r0 = gblk * R;  // G == 1
         // deterministic block reduction of |r|^2 per right-hand side
         __shared__ double red[256];
 #pragma unroll
@@ -461,15 +509,17 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
     }
 }
 
-template <typename S, int R, bool PKH = false>
+template <typename S, int R, bool PKH = false, int G = 1>
 static void launch_R(lqt_ctx* c, int op, const S* U, const S* in, S* out, int nrhs, long long is, long long os,
                      int bs, int chunk, double shift, double scale) {
     const Geom& g = c->g;
     int nsb = (g.V + bs - 1) / bs;
     int ngrp = (nrhs + R - 1) / R;
-    int nl = nsb * ngrp;
+    int nl = nsb * ((ngrp + G - 1) / G);
+    if (G > 1) LQT_CHECK(bs == 256, LQT_EINVAL, "staged-link operator: 256-site blocks only");
 #define LQT_DSLASH_OP(OPK)                                                                                   \
-    hipLaunchKernelGGL((k_dslash<S, R, OPK, 0, PKH>), dim3(xcd_grid(nl)), dim3(bs), 0, c->stream, U, in, out,   \
+    hipLaunchKernelGGL((k_dslash<S, R, OPK, 0, PKH, G>), dim3(xcd_grid(nl)), dim3(bs), G > 1 ? 36 * 256 * 4 : 0,     \
+                       c->stream, U, in, out,                                                                    \
                        (const S*)nullptr, (double*)nullptr, (const int*)nullptr, g.lat, nrhs, is, os, chunk, shift,  \
                        scale)
     switch (op) {
@@ -525,18 +575,19 @@ static Tuned default_tile(int prec, int nrhs) {
     return t;
 }
 
+template <int G>
 static void launch_pkh(lqt_ctx* c, int op, const void* in, void* out, int nrhs, long long is, long long os,
                        const Tuned& t, double shift, double scale) {
     const h2* U = gauge_of<h2>(c);
     switch (t.rhs_per_thread) {
         case 1:
-            launch_R<h2, 1, true>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
+            launch_R<h2, 1, true, G>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
             break;
         case 2:
-            launch_R<h2, 2, true>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
+            launch_R<h2, 2, true, G>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
             break;
         default:
-            launch_R<h2, 4, true>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
+            launch_R<h2, 4, true, G>(c, op, U, (const h2*)in, (h2*)out, nrhs, is, os, t.block, t.chunk, shift, scale);
             break;
     }
 }
@@ -547,9 +598,12 @@ static void dslash_cfg(lqt_ctx* c, int prec, int op, const void* in, void* out, 
         dslash_mf(c, prec, op, in, out, nrhs, is, os, t, shift, scale);
         return;
     }
-    if (t.kind == 2) {
+    if (t.kind == 2 || t.kind == 3) {
         LQT_CHECK(prec == LQT_F16, LQT_EINVAL, "packed half-precision dslash: FP16 storage only");
-        launch_pkh(c, op, in, out, nrhs, is, os, t, shift, scale);
+        if (t.kind == 2)
+            launch_pkh<1>(c, op, in, out, nrhs, is, os, t, shift, scale);
+        else
+            launch_pkh<8>(c, op, in, out, nrhs, is, os, t, shift, scale);
         return;
     }
     switch (prec) {
@@ -591,17 +645,20 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen) {
     Tuned bt = default_tile(prec, nrhs);
     // candidates: vector kernel (R right-hand sides per thread), for 16-bit storage the
     // matrix-core kernel (R groups of 4 right-hand sides per lane), for FP16 storage the
-    // vector kernel with packed half-precision arithmetic (kind 2)
+    // vector kernel with packed half-precision arithmetic (kind 2) and the same with the
+    // block's links staged in LDS for 8 groups of right-hand sides (kind 3, 256-site blocks)
     std::vector<Tuned> cand;
-    for (int kind = 0; kind < 3; kind++)
+    for (int kind = 0; kind < 4; kind++)
         for (int ri = 0; ri < 3; ri++) {
             if (kind == 0 && (Rs[ri] > nrhs || (prec == LQT_F64 && Rs[ri] > 2))) continue;
-            if (kind == 2 && (prec != LQT_F16 || Rs[ri] > nrhs)) continue;
+            if ((kind == 2 || kind == 3) && (prec != LQT_F16 || Rs[ri] > nrhs)) continue;
+            if (kind == 3 && nrhs <= Rs[ri]) continue;  // one group: nothing to share
             if (kind == 1 && (prec == LQT_F64 || prec == LQT_F32 || Rs[ri] > 2 || (Rs[ri] == 2 && nrhs <= 4) ||
                               !dslash_mf_fits(c->g, Rs[ri], n, n)))
                 continue;
             for (int bi = 0; bi < 3; bi++)
                 for (int ci = 0; ci < 5; ci++) {
+                    if (kind == 3 && Bs[bi] != 256) continue;
                     Tuned t{Rs[ri], Bs[bi], Cs[ci]};
                     t.kind = kind;
                     cand.push_back(t);

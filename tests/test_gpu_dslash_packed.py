@@ -1,5 +1,5 @@
-"""The FP16 Wilson operator with packed half-precision arithmetic (tuner kind 2) against the
-oracle.
+"""The FP16 Wilson operator with packed half-precision arithmetic (tuner kinds 2 and 3; kind 3
+stages each 256-site block's links in LDS for 8 right-hand-side groups) against the oracle.
 
 Inputs and links as the library stores them (tests/storage16.py).  The kernel rounds each
 half spinor h = p_a + c p_b (c = +-1, +-i) to FP16 (|dh| <= u |h|, u = 2^-11 per real), then
@@ -19,7 +19,8 @@ from storage16 import stored
 pytestmark = pytest.mark.gpu
 
 SHAPES = [((4, 4, 4, 4), 0.3), ((3, 5, 4, 6), 0.5), ((8, 6, 4, 10), 0.5)]
-TILES = [(1, 64, 0, 2), (2, 256, 16, 2), (4, 128, 64, 2), (2, 256, 1024, 2)]
+TILES = [(1, 64, 0, 2), (2, 256, 16, 2), (4, 128, 64, 2), (2, 256, 1024, 2),
+         (1, 256, 0, 3), (2, 256, 16, 3), (4, 256, 64, 3)]
 U = 2.0 ** -11
 
 
@@ -52,7 +53,7 @@ def _check(out, ref, ps):
         assert np.all(d <= U * np.abs(part(ref)) + 8 * np.sqrt(3) * U * mpsi + 1e-5 * m), float(np.max(d / m))
 
 
-@pytest.mark.parametrize("tile", [(2, 256, 256, 2), (2, 256, 1024, 2)])
+@pytest.mark.parametrize("tile", [(2, 256, 256, 2), (2, 256, 1024, 2), (2, 256, 0, 3), (2, 256, 64, 3)])
 def test_packed_half_full_size(gpu, tile):
     """16^3x32 with 128 right-hand sides in the benchmark's launch shapes; sampled right-hand
     sides against the oracle"""
@@ -69,6 +70,46 @@ def test_packed_half_full_size(gpu, tile):
     ps = stored(psi[pick], 2)
     ref = core.apply(stored(links, 2, links=True), dims, -1.9, 0, ps)
     _check(out[pick], ref, ps)
+    c.close()
+
+
+@pytest.mark.parametrize("nrhs,tile", [(20, (2, 256, 0, 3)), (37, (1, 256, 16, 3)), (9, (4, 256, 0, 3))])
+def test_staged_links_several_group_blocks(gpu, nrhs, tile):
+    """kind 3 with more right-hand-side groups than one block loops over (8), a partial last
+    block of groups and a partial last group; every right-hand side against the oracle"""
+    lq = gpu
+    dims = (8, 6, 4, 10)
+    print(f"staged-link FP16 dslash nrhs={nrhs} tile={tile}", flush=True)
+    links = synth.su3_links(dims, 0.5, 4)
+    c = lq.Context(dims, -0.4)
+    c.set_gauge(links)
+    c.set_tile(2, nrhs, tile)
+    psi = synth.random_spinors(dims, nrhs, 6).reshape(nrhs, -1)
+    for op in (0, 2):
+        out = c.apply(torch.as_tensor(psi).to(torch.complex64).cuda(), op=op, prec=2).cpu().numpy()
+        ps = stored(psi, 2)
+        ref = core.apply(stored(links, 2, links=True), dims, -0.4, op, ps)
+        _check(out.astype(np.complex128), ref, ps)
+    c.close()
+
+
+def test_staged_links_several_lattices(gpu):
+    """kind 3 over three lattices in one launch, each against the oracle"""
+    lq = gpu
+    lats, masses = [(4, 4, 4, 4), (2, 4, 6, 4), (6, 4, 4, 8)], [-0.4, 0.1, -0.2]
+    links = [synth.su3_links(d, 0.5, 1 + k) for k, d in enumerate(lats)]
+    c = lq.Context(lats, masses)
+    c.set_gauge(np.concatenate([u.ravel() for u in links]))
+    nrhs = 19
+    psi = np.concatenate([synth.random_spinors(d, nrhs, 7 + k).reshape(nrhs, -1) for k, d in enumerate(lats)], axis=1)
+    c.set_tile(2, nrhs, (2, 256, 0, 3))
+    out = c.apply(torch.as_tensor(psi).to(torch.complex64).cuda(), op=0, prec=2).cpu().numpy().astype(np.complex128)
+    o = 0
+    for k, d in enumerate(lats):
+        n = 12 * int(np.prod(d))
+        ps = stored(psi[:, o:o + n], 2)
+        _check(out[:, o:o + n], core.apply(stored(links[k], 2, links=True), d, masses[k], 0, ps), ps)
+        o += n
     c.close()
 
 
@@ -93,7 +134,12 @@ def test_packed_half_rejects_other_storage(gpu):
     lq = gpu
     c = lq.Context((4, 4, 4, 4), 0.1)
     for prec in (0, 1, 3):
+        for kind in (2, 3):
+            with pytest.raises(lq.LqtError) as e:
+                c.set_tile(prec, 8, (1, 256, 0, kind))
+            assert e.value.code == -1
+    for bs in (64, 128):  # the staged-link kernel takes 256-thread blocks only
         with pytest.raises(lq.LqtError) as e:
-            c.set_tile(prec, 8, (1, 256, 0, 2))
+            c.set_tile(2, 8, (1, bs, 0, 3))
         assert e.value.code == -1
     c.close()

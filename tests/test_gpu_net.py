@@ -49,6 +49,27 @@ def test_forward_matches_oracle(gpu, dims):
     c.close()
 
 
+def test_forward_full_size_256_fields(gpu):
+    """16^3x32 with 256 fields in one application (the grid of the learned-preconditioner
+    workload: 64 groups of 4 fields, 8192 site chunks); the first and last fields are checked
+    in full against the oracle forward pass."""
+    lq = gpu
+    dims = (16, 16, 16, 32)
+    print("net forward 16^3x32, 256 fields", flush=True)
+    c, U = _ctx(lq, dims, -1.9, eps=0.5, seed=1)
+    w = _random_weights(5)
+    c.precond_set(torch.as_tensor(w))
+    z = c.probes(1003, 256)
+    out = c.precond_apply(z)
+    pick = [0, 255]
+    got = out[pick].cpu().numpy()
+    zs = z[pick].cpu().numpy()
+    del out, z
+    ref = ptc.forward(U, dims, _bf16(w), zs)
+    assert np.max(np.abs(got - ref)) <= FWD_TOL * np.max(np.abs(ref))
+    c.close()
+
+
 def test_network_with_gamma_weights_is_the_wilson_operator(gpu):
     """First layer = the Wilson operator on features 0..3, then identities: M = A exactly in
     BF16 weights (4+m = 3.5, 1/2 and the gamma entries are BF16 numbers)."""
