@@ -38,6 +38,13 @@ def parse():
                     help="only time the Wilson operator at its tuned tile for every storage precision and "
                          "n in {1, 8, 16, 32, 64} right-hand sides on 16^3x32 and 32^3x64, beside a device copy, "
                          "one JSON line per case, and exit")
+    ap.add_argument("--train-pairs", type=int, default=None,
+                    help="transport-net workload: training pairs (default: the workload's)")
+    ap.add_argument("--train-epochs", type=int, default=None,
+                    help="transport-net workload: training epochs (default: the workload's)")
+    ap.add_argument("--pair-xi", type=float, default=None,
+                    help="transport-net workload: errors of the training pairs from FP32 solves of Gaussian fields "
+                         "to this tolerance (0: the Gaussian fields themselves; default: the workload's)")
     ap.add_argument("--dslash-tile", default=None, metavar="R,BLOCK,CHUNK,KIND",
                     help="use this operator tile for the inner storage instead of the autotuner's choice "
                          "(for counter runs of a given tile)")
@@ -229,8 +236,10 @@ def run_net(a, w):
     ctx.tune(lq.BF16, nprobes)
     ctx.tune(lq.F64, 1)
     t_train = time.perf_counter()
-    loss = ctx.precond_train(w.get("train_pairs", 256), seed=5, epochs=w.get("train_epochs", 4), lr=3e-3, batch=8,
-                             verbose=1)
+    npairs = a.train_pairs or w.get("train_pairs", 256)
+    epochs = a.train_epochs or w.get("train_epochs", 4)
+    pair_xi = a.pair_xi if a.pair_xi is not None else w.get("pair_xi", 0.0)
+    loss = ctx.precond_train(npairs, seed=5, epochs=epochs, lr=3e-3, batch=8, pair_xi=pair_xi, verbose=1)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t_train
     res = {}
@@ -258,7 +267,37 @@ def run_net(a, w):
            "iters_per_probe_net": rr[-1]["iters_total"] / rr[-1]["nsolves"],
            "iters_per_probe_plain": rp[-1]["iters_total"] / rp[-1]["nsolves"],
            "plain_same_probes_solves_per_s": round(okp / elp, 3), "train_s": round(t_train, 2),
-           "train_pairs": w.get("train_pairs", 256), "train_loss": loss})
+           "train_pairs": npairs, "train_epochs": epochs, "train_pair_xi": pair_xi, "train_loss": loss,
+           **({} if a.no_fp64 else fp64_plain(ctx, w, ok / el, w.get("restart", 32)))})
+
+
+def fp64_plain(ctx, w, value, restart):
+    """Plain FP64 GMRES, one right-hand side at a time, on a sample of 4 of the workload's
+    probes, with the timed path's restart length, 8 and 32; the fastest is the reference of
+    `speedup_vs_fp64_plain`."""
+    import numpy as np
+    import torch
+
+    import paper_1909_12234_amd as lq
+
+    out = {}
+    zs = ctx.probes(w["probe_seed"], 4)
+    restarts = sorted({restart, 8, 32})
+    for m in restarts:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its = []
+        for j in range(zs.shape[0]):
+            _, st, _ = ctx.solve(zs[j:j + 1], w["xi"], prec=lq.F64, restart=m)
+            its.append(st[0][1])
+        torch.cuda.synchronize()
+        rate = zs.shape[0] / (time.perf_counter() - t1)
+        out[f"fp64_plain_gmres{m}_solves_per_s"] = round(rate, 3)
+        out[f"fp64_plain_gmres{m}_iters_per_probe"] = float(np.mean(its))
+    fp64_rate = max(out[f"fp64_plain_gmres{m}_solves_per_s"] for m in restarts)
+    out["fp64_plain_iters_per_probe"] = out["fp64_plain_gmres32_iters_per_probe"]
+    out["speedup_vs_fp64_plain"] = round(value / fp64_rate, 2)
+    return out
 
 
 def run_dslash_sweep(a):
@@ -433,24 +472,7 @@ def main():
     }
 
     if not a.no_fp64:
-        # plain FP64 GMRES, one right-hand side at a time, same probes (a sample of 4), with the
-        # restart length of the timed path, 8 and 32; the fastest is the reference
-        zs = ctx.probes(w["probe_seed"], 4)
-        restarts = sorted({w.get("restart", 32), 8, 32})
-        for m in restarts:
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            its = []
-            for j in range(zs.shape[0]):
-                _, st, _ = ctx.solve(zs[j:j + 1], w["xi"], prec=lq.F64, restart=m)
-                its.append(st[0][1])
-            torch.cuda.synchronize()
-            rate = zs.shape[0] / (time.perf_counter() - t1)
-            out[f"fp64_plain_gmres{m}_solves_per_s"] = round(rate, 3)
-            out[f"fp64_plain_gmres{m}_iters_per_probe"] = float(np.mean(its))
-        fp64_rate = max(out[f"fp64_plain_gmres{m}_solves_per_s"] for m in restarts)
-        out["fp64_plain_iters_per_probe"] = out["fp64_plain_gmres32_iters_per_probe"]
-        out["speedup_vs_fp64_plain"] = round(value / fp64_rate, 2)
+        out.update(fp64_plain(ctx, w, value, w.get("restart", 32)))
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(U, dims, mass, out.get("fp64_plain_iters_per_probe", 604.0))
     print(json.dumps(out), flush=True)

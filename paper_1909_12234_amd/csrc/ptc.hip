@@ -179,8 +179,10 @@ __device__ __forceinline__ void ptc_comp(const PtcLink& L, const PtcVec<SI>& B, 
 // waves on the same L2 read as their own.  The loads of the next step are issued before the
 // current step computes.  FP32 links [mu][ab][V].  Byte offsets within 4
 // fields are 32-bit (4 * 3 FI * V * sizeof(SI) < 4 GiB, checked by the caller).
+// 4 waves per SIMD for the inference layers (FP32/16-bit fields: 128 registers, no spills);
+// 3 for the FP64-activation training layers, which would spill at 4
 template <int FI, int FO, typename SI, typename SO>
-__global__ __launch_bounds__(256) void k_ptc_layer(const float2* __restrict__ U, const SI* __restrict__ in,
+__global__ __launch_bounds__(256, (sizeof(SI) == 16 || sizeof(SO) == 16) ? 3 : 4) void k_ptc_layer(const float2* __restrict__ U, const SI* __restrict__ in,
                                                    SO* __restrict__ out, const float2* __restrict__ WA, int nrhs,
                                                    int L0, int L1, int L2, int L3) {
     static_assert(FI == 4 || FI == 8, "4 or 8 input features");

@@ -24,8 +24,10 @@ WORKLOADS = {
     "wilson_batched3": dict(lattices=[((8, 8, 8, 8), 1), ((12, 12, 12, 24), 2), ((16, 16, 16, 32), 3)], eps=0.4,
                             mass=0.1, nprobes=192, probe_seed=1002, xi=1e-8, inner_prec="f32"),
     # 16^3x32 with the learned preconditioner, 256 probes
+    # the net is trained before the timed region on 1024 pairs (e = the FP32 solver's output for a
+    # Gaussian field at 1e-2, r = A e) in 4 epochs
     "wilson16x32_net": dict(dims=(16, 16, 16, 32), eps=0.5, seed=1, mass=-1.90, nprobes=256, probe_seed=1003,
-                            xi=1e-8, inner_prec="bf16"),
+                            xi=1e-8, inner_prec="bf16", train_pairs=1024, train_epochs=4, pair_xi=1e-2),
     # 32^3x64 prolongator deflation, 4^4 aggregates, 24 null vectors per chirality, k = 256
     "wilson32x64_mg": dict(dims=(32, 32, 32, 64), eps=0.5, seed=1, mass=-1.90, nprobes=256, probe_seed=1004,
                            xi=1e-8, block=(4, 4, 4, 4), nv=24, k=256, inner_prec="bf16"),
