@@ -80,6 +80,19 @@ def cpu_baseline(U, dims, mass, iters_per_probe, budget_s=15.0):
         dt = time.perf_counter() - t0
     per_iter = dt / its
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the oracle's FP64 operator on one right-hand side, by the operator's algorithmic bytes
+    V = int(np.prod(dims))
+    napp = 10
+    t0 = time.perf_counter()
+    for _ in range(napp):
+        core.apply(U, dims, mass, core.OP_A, z)
+    dt_op = (time.perf_counter() - t0) / napp
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": 1.0 / (per_iter * iters_per_probe),
         "unit": "probe solves/s",
@@ -87,6 +100,9 @@ def cpu_baseline(U, dims, mass, iters_per_probe, budget_s=15.0):
         "kind": "oracle",
         "sample": f"{its} Arnoldi steps of FP64 GMRES(32) on one probe ({dt:.1f} s, {per_iter*1e3:.1f} ms/step), "
                   f"scaled by the {iters_per_probe:.0f} steps per probe the same algorithm takes on the device",
+        "dslash_fp64_ms": round(dt_op * 1e3, 2),
+        "dslash_fp64_gbps": round(V * (72 * 8 + 48 * 8) / dt_op / 1e9, 2),
+        "cpu_model": model,
     }
 
 
