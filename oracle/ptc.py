@@ -48,8 +48,9 @@ def forward(links, dims, w, v, feats=FEATURES, antiperiodic=True):
 
 
 def loss(links, dims, mass, w, e, feats=FEATURES, antiperiodic=True):
-    """Mean over the fields e of ||M_W (A e) - e||^2 / ||e||^2 (Section on the learned
-    preconditioner: the network is trained to map residuals to errors)."""
+    """Mean over the fields e of ||M_W (A e) - e||^2 / ||e||^2: the training objective of the
+    learned preconditioner (an addition to the paper's method), which maps residuals to
+    errors."""
     e = np.asarray(e, dtype=np.complex128).reshape(-1, 12 * core.volume(dims))
     r = core.apply(links, dims, mass, core.OP_A, e, antiperiodic)
     m = forward(links, dims, w, r, feats, antiperiodic)

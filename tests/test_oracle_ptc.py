@@ -92,3 +92,33 @@ def test_fd_gradient_matches_the_closed_form_of_a_site_local_layer():
     # a hop weight's gradient is not the site-local one: nonzero and finite
     fd_hop = ptc.loss_grad_fd(U, dims, m, W.ravel(), e, [16, 40], feats=(4, 4))
     assert np.all(np.isfinite(fd_hop)) and np.max(np.abs(fd_hop)) > 0
+
+
+def _identity_weights():
+    w = []
+    for fi, fo in zip(ptc.FEATURES[:-1], ptc.FEATURES[1:]):
+        W = np.zeros((9, fo, fi), dtype=np.complex128)
+        W[0] = np.eye(fo, fi)
+        w.append(W.ravel())
+    return np.concatenate(w)
+
+
+def test_loss_of_the_zero_network_is_one():
+    """M = 0 maps every residual to 0: each pair contributes ||e||^2 / ||e||^2 = 1"""
+    dims = (2, 4, 2, 4)
+    U = synth.su3_links(dims, 0.5, 6)
+    e = synth.random_spinors(dims, 3, 7).reshape(3, -1)
+    assert abs(ptc.loss(U, dims, -0.2, np.zeros(ptc.weight_count(), dtype=np.complex128), e) - 1.0) < 1e-14
+
+
+def test_loss_of_the_identity_network():
+    """M = 1: the loss is the mean over the pairs of ||A e - e||^2 / ||e||^2, the mean taken
+    pair by pair (two fields of very different norms)"""
+    dims = (2, 4, 2, 4)
+    U = synth.su3_links(dims, 0.5, 8)
+    m = -0.2
+    e = synth.random_spinors(dims, 2, 9).reshape(2, -1)
+    e[1] *= 1e3
+    ae = core.apply(U, dims, m, core.OP_A, e)
+    per = [np.sum(np.abs(ae[q] - e[q]) ** 2) / np.sum(np.abs(e[q]) ** 2) for q in range(2)]
+    assert abs(ptc.loss(U, dims, m, _identity_weights(), e) - 0.5 * (per[0] + per[1])) <= 1e-12 * max(per)
