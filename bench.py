@@ -313,6 +313,16 @@ def fp64_plain(ctx, w, value, restart):
     fp64_rate = max(out[f"fp64_plain_gmres{m}_solves_per_s"] for m in restarts)
     out["fp64_plain_iters_per_probe"] = out["fp64_plain_gmres32_iters_per_probe"]
     out["speedup_vs_fp64_plain"] = round(value / fp64_rate, 2)
+    # FP64 batched: 32 of the workload's probes in one lock-step GMRES(8) solve (FP64 operator
+    # and Krylov vectors), which separates the gain of batching from that of reduced storage
+    zb = ctx.probes(w["probe_seed"], 32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, st, _ = ctx.solve(zb, w["xi"], prec=lq.F64, restart=8)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    out["fp64_batched32_gmres8_solves_per_s"] = round(sum(1 for s in st if s[0]) / dt, 3)
+    out["fp64_batched32_gmres8_iters_per_probe"] = float(np.mean([s[1] for s in st]))
     return out
 
 
@@ -427,7 +437,7 @@ def main():
 
     def step():
         return ctx.trace(nprobes, w["probe_seed"], w["xi"], basis=basis, prec=prec, restart=w.get("restart", 32),
-                         sstep=w.get("sstep", 0))
+                         sstep=w.get("sstep", 0), rank_curve=basis is not None)
 
     for _ in range(a.warmup):
         step()
@@ -480,6 +490,15 @@ def main():
         "iters_per_probe_mixed": round(iters_mixed, 1),
         "estimate": {"trace": results[-1]["trace_re"], "var_sample": results[-1]["var_sample"],
                      "jackknife_err": results[-1]["jackknife_err"], "nfailed": results[-1]["nfailed"]},
+        # the same probes' samples without the deflation correction (rank 0 of the rank curve)
+        "estimate_undeflated": ({"trace": float(results[-1]["rank_curve"][0, 0]),
+                                 "var_sample": float(results[-1]["rank_curve"][0, 1]),
+                                 "jackknife_err": float(results[-1]["rank_curve"][0, 2])}
+                                if basis is not None else None),
+        # a-posteriori rank (Section 2.2): the prefix of the basis with the smallest sample variance
+        "rank_min_var": ({"rank": int(np.argmin(results[-1]["rank_curve"][:, 1].numpy())),
+                          "var_sample": float(np.min(results[-1]["rank_curve"][:, 1].numpy()))}
+                         if basis is not None else None),
         "setup_s": round(t_setup, 2),
         "basis_s": round(t_basis, 2),
         "basis_min_abs_lambda": float(np.min(np.abs(lam))),
