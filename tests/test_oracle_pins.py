@@ -241,3 +241,65 @@ def test_jackknife_of_mean_equals_standard_error():
     t = np.random.default_rng(0).standard_normal(50) + 0j
     r = estimator.summarize(t)
     assert np.isclose(r["jackknife_err"], np.sqrt(r["var_sample"] / 50))
+
+
+# ---------------------------------------------------------------- exact statistics by enumeration
+def _every_sign_vector(n):
+    """All 2^n real +-1 vectors of length n, one per row."""
+    bits = (np.arange(2 ** n)[:, None] >> np.arange(n)[None, :]) & 1
+    return 1.0 - 2.0 * bits
+
+
+def test_hutchinson_mean_and_variance_over_every_probe():
+    """Eq. (1) is unbiased and its one-probe variance is the symmetrised form of Eq. (2):
+    averaging over all 4096 sign vectors of length 12 gives both exactly (no sampling)."""
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12))
+    Z = _every_sign_vector(12)
+    t = estimator.hutchinson_samples(Z, (B @ Z.T).T)
+    assert abs(t.mean() - np.trace(B)) < 1e-12 * np.abs(B).sum()
+    v = estimator.exact_variances(B)
+    assert np.isclose(np.mean(np.abs(t - np.trace(B)) ** 2), v["exact"], rtol=1e-12)
+    assert np.isclose(np.mean((t.real - np.trace(B).real) ** 2), v["re"], rtol=1e-12)
+    # a non-symmetric B: Eq. (2) as printed overstates the variance of real probes
+    assert v["printed"] > 1.05 * v["exact"]
+    # for a complex-symmetric B the printed form is exact
+    Bs = B + B.T
+    vs = estimator.exact_variances(Bs)
+    assert np.isclose(vs["printed"], vs["exact"], rtol=1e-12)
+
+
+def test_deflated_estimator_over_every_probe():
+    """Section 2.1 with K = g5 on a g5-Hermitian 12 x 12 operator (one lattice site): over all
+    sign vectors the corrected samples average to trace(A^{-1}) - t0, and their variance is the
+    exact variance of A^{-1}(I - P).  A sign error or a missing Lambda^{-1} in the per-probe
+    correction breaks the first; a wrong projector breaks the second."""
+    rng = np.random.default_rng(22)
+    g5 = g5diag(12)
+    H = rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12))
+    H = H + H.conj().T + 0.3 * np.eye(12)
+    A = g5[:, None] * H  # g5 A = H is Hermitian
+    Ai = np.linalg.inv(A)
+    X = rng.standard_normal((3, 12)) + 1j * rng.standard_normal((3, 12))
+    Ub, lam, ug5u, t0 = estimator.oblique_setup(X, (A @ X.T).T)
+    Z = _every_sign_vector(12)
+    t = estimator.hutchinson_samples(Z, (Ai @ Z.T).T) - estimator.oblique_corrections(Z, Ub, lam)
+    assert abs(t0 + t.mean() - np.trace(Ai)) < 1e-11 * np.abs(Ai).sum()
+    D = Ai @ (np.eye(12) - estimator.oblique_projector_dense(A, Ub, lam))
+    assert np.isclose(np.mean(np.abs(t - np.trace(D)) ** 2), estimator.exact_variances(D)["exact"], rtol=1e-10)
+    # every prefix of the basis gives an unbiased estimator too (the rank curve of Section 2.2)
+    base = estimator.hutchinson_samples(Z, (Ai @ Z.T).T)
+    for kk in range(4):
+        c = estimator.oblique_corrections(Z, Ub, lam, kk) if kk else 0.0
+        assert abs(np.sum(ug5u[:kk] / lam[:kk]) + np.mean(base - c) - np.trace(Ai)) < 1e-11 * np.abs(Ai).sum()
+
+
+def test_mass_tuner_finds_the_free_field_spectral_edge():
+    """Unit links, m = 0, 2^3 x 4 with antiperiodic time: the leftmost eigenvalues of A are
+    sum_mu (1 - cos p_mu) +- i |sin p| at p = (0, 0, 0, +-pi/4)."""
+    from oracle import tune_mass
+
+    dims = (2, 2, 2, 4)
+    w = tune_mass.leftmost_eigenvalues(synth.unit_links(dims), dims, k=6)
+    assert np.allclose(w.real, 1 - np.cos(np.pi / 4), atol=1e-6)
+    assert np.allclose(np.abs(w.imag), np.sin(np.pi / 4), atol=1e-6)
