@@ -57,3 +57,9 @@ def test_more_than_one_gpu_exits_before_touching_a_device():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=60)
     assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_prolongator_workload_has_no_timed_path():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "wilson32x64_mg"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2 and "no timed path" in p.stderr and p.stdout == ""
