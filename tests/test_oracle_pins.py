@@ -147,6 +147,24 @@ def test_gmres_true_residual_and_maxit():
     assert abs(np.linalg.norm(r) / np.linalg.norm(b) - rel) < 1e-12
 
 
+
+def test_gmres_solves_a_plane_wave_in_closed_form():
+    """Free field on 8^3 x 16 (N = 98304, beyond dense LU): b = e^{ipx} u has the solution
+    e^{ipx} A(p)^{-1} u with A(p) = m + sum(1 - cos p) + i sum gamma_mu sin p_mu, for A and,
+    with the transposed-conjugate symbol, for A^+."""
+    dims, m = (8, 8, 8, 16), 0.2
+    n = [1, 2, 7, 3]
+    p = [2 * np.pi * n[0] / 8, 2 * np.pi * n[1] / 8, 2 * np.pi * n[2] / 8, (2 * n[3] + 1) * np.pi / 16]
+    u = np.random.default_rng(4).standard_normal((4, 3)) + 1j * np.random.default_rng(5).standard_normal((4, 3))
+    Ap = (m + sum(1 - np.cos(q) for q in p)) * np.eye(4) + 1j * sum(core.gamma(mu) * np.sin(p[mu]) for mu in range(4))
+    b = synth.plane_wave(dims, p, u).reshape(-1)
+    for op, sym in ((core.OP_A, Ap), (core.OP_ADAG, Ap.conj().T)):
+        x, conv, its, rel = core.gmres(synth.unit_links(dims), dims, m, b, 1e-11, m=16, op=op)
+        assert conv and rel <= 1e-11
+        xe = synth.plane_wave(dims, p, np.linalg.solve(sym, u)).reshape(-1)
+        assert np.linalg.norm(x - xe) / np.linalg.norm(xe) <= 1e-9
+
+
 # ---------------------------------------------------------------- probes
 def test_splitmix64_known_answers():
     vals = [int(l) for l in open(os.path.join(HERE, "golden", "splitmix64_seed1234567.txt")) if l.strip()[:1].isdigit()]
