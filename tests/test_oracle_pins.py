@@ -321,3 +321,20 @@ def test_mass_tuner_finds_the_free_field_spectral_edge():
     w = tune_mass.leftmost_eigenvalues(synth.unit_links(dims), dims, k=6)
     assert np.allclose(w.real, 1 - np.cos(np.pi / 4), atol=1e-6)
     assert np.allclose(np.abs(w.imag), np.sin(np.pi / 4), atol=1e-6)
+
+
+def test_small_pipeline_estimates_bracket_the_exact_trace(capsys):
+    """The 4^4 oracle pipeline (64 probes, k = 16 exact A g5 eigenvectors): both estimates lie
+    within 4 jackknife errors of the exact trace, and the exact variance falls with the rank."""
+    import json
+
+    from oracle import pipeline_small
+
+    pipeline_small.main([])
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    exact = out["trace_exact"][0]
+    for key in ("estimate_undeflated", "estimate_deflated"):
+        assert abs(out[key]["trace"] - exact) <= 4 * out[key]["jackknife_err"], key
+    v = [out["var_exact_by_rank"][r] for r in ("0", "16", "64", "256", "1024")]
+    assert all(a > b for a, b in zip(v, v[1:]))
+    assert out["var_exact_by_rank"]["16"] == out["var_exact_deflated"]
