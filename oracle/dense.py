@@ -31,3 +31,30 @@ def free_field_closed_form(dims, mass, antiperiodic=True):
     tr = np.sum(12 * a / (a * a + s2))
     fro = np.sum(12 / (a * a + s2))
     return float(tr), float(fro)
+
+
+def free_field_solve(z, dims, mass, antiperiodic=True):
+    """y = A^{-1} z for unit links at any lattice size, in momentum space.
+
+    A plane wave e^{ipx} u is mapped to e^{ipx} A(p) u with A(p) = m + sum(1 - cos p_mu)
+    + i sum gamma_mu sin p_mu, so y is the sum over momenta of e^{ipx} A(p)^{-1} z(p).  The
+    antiperiodic time momenta (2n+1) pi / L_t are reached from the periodic ones of the FFT
+    by the phase e^{i pi t / L_t}.  z has shape (12 V,) or (nrhs, 12 V), index
+    12 * site + 3 * spin + colour with x fastest."""
+    lx, ly, lz, lt = (int(d) for d in dims)
+    z = np.asarray(z, dtype=np.complex128)
+    single = z.ndim == 1
+    zz = z.reshape(-1, lt, lz, ly, lx, 4, 3)
+    shift = np.pi / lt if antiperiodic else 0.0
+    tw = np.exp(1j * shift * np.arange(lt)).reshape(1, lt, 1, 1, 1, 1, 1)
+    zk = np.fft.fftn(zz / tw, axes=(1, 2, 3, 4))
+    kt, kz, ky, kx = (2 * np.pi * np.fft.fftfreq(L) for L in (lt, lz, ly, lx))
+    T, Z, Y, X = np.meshgrid(kt + shift, kz, ky, kx, indexing="ij")
+    P = (X, Y, Z, T)  # mu = 0..3 <-> x, y, z, t
+    a = mass + sum(1 - np.cos(p) for p in P)
+    Ap = a[..., None, None] * np.eye(4) + 1j * sum(np.sin(P[mu])[..., None, None] * core.gamma(mu)
+                                                   for mu in range(4))
+    yk = np.linalg.solve(Ap[None], zk)
+    y = np.fft.ifftn(yk, axes=(1, 2, 3, 4)) * tw
+    y = y.reshape(z.shape[0] if not single else 1, -1)
+    return y[0] if single else y
