@@ -288,9 +288,10 @@ def run_net(a, w):
 
 
 def fp64_plain(ctx, w, value, restart):
-    """Plain FP64 GMRES, one right-hand side at a time, on a sample of 4 of the workload's
-    probes, with the timed path's restart length, 8 and 32; the fastest is the reference of
-    `speedup_vs_fp64_plain`."""
+    """Plain FP64 GPU GMRES legs: one right-hand side at a time on a sample of 4 of the
+    workload's probes, with the timed path's restart length, 8 and 32, and 32 probes batched in
+    one lock-step GMRES(8) solve.  `speedup_vs_fp64_plain` divides by the fastest of all of
+    them; `speedup_vs_fp64_single_rhs` by the fastest one-at-a-time leg."""
     import numpy as np
     import torch
 
@@ -310,9 +311,8 @@ def fp64_plain(ctx, w, value, restart):
         rate = zs.shape[0] / (time.perf_counter() - t1)
         out[f"fp64_plain_gmres{m}_solves_per_s"] = round(rate, 3)
         out[f"fp64_plain_gmres{m}_iters_per_probe"] = float(np.mean(its))
-    fp64_rate = max(out[f"fp64_plain_gmres{m}_solves_per_s"] for m in restarts)
+    single_rate = max(out[f"fp64_plain_gmres{m}_solves_per_s"] for m in restarts)
     out["fp64_plain_iters_per_probe"] = out["fp64_plain_gmres32_iters_per_probe"]
-    out["speedup_vs_fp64_plain"] = round(value / fp64_rate, 2)
     # FP64 batched: 32 of the workload's probes in one lock-step GMRES(8) solve (FP64 operator
     # and Krylov vectors), which separates the gain of batching from that of reduced storage
     zb = ctx.probes(w["probe_seed"], 32)
@@ -323,6 +323,10 @@ def fp64_plain(ctx, w, value, restart):
     dt = time.perf_counter() - t1
     out["fp64_batched32_gmres8_solves_per_s"] = round(sum(1 for s in st if s[0]) / dt, 3)
     out["fp64_batched32_gmres8_iters_per_probe"] = float(np.mean([s[1] for s in st]))
+    best = max(single_rate, out["fp64_batched32_gmres8_solves_per_s"])
+    out["fp64_plain_best_solves_per_s"] = best
+    out["speedup_vs_fp64_plain"] = round(value / best, 2)
+    out["speedup_vs_fp64_single_rhs"] = round(value / single_rate, 2)
     return out
 
 

@@ -97,6 +97,17 @@ typedef struct {
                         times the last formed one, meets the tolerance, or is not finite;
                         other cycles start from the carried residual (reliable updates).
                         Values in (0, 1); negative: form it at every restart [0.1]      */
+    int fallback;    /* 1: a system whose solve stalls continues from its current x with
+                        more robust settings, dropping in turn the network preconditioner,
+                        the s-step cycles, 16-bit storage (to FP32) and reduced storage (to
+                        FP64 GMRES); maxit applies to each level.  A solve has stalled when
+                        stall_window FP64 residuals in a row fail to fall 0.1 % below the
+                        smallest before them, when a cycle can take no step (an s-step
+                        Gram matrix of rank one: the start vector is an eigenvector of A),
+                        or when its residual is not finite (that level restarts from x = 0).
+                        0: no fallback; a cycle that takes no step ends its system as failed
+                        and other systems run to maxit [0]                                 */
+    int stall_window;/* FP64 residuals without a 0.1 % decrease that count as a stall [2]  */
 } lqt_solver_opts;
 
 /* Per right-hand side solve statistics. */
@@ -105,6 +116,8 @@ typedef struct {
     int iters;     /* Arnoldi steps (operator applications inside cycles)               */
     int cycles;    /* restart cycles = FP64 residual recomputations                      */
     double relres; /* final FP64 true relative residual                                  */
+    int fallback;  /* fallback level the system finished at (0: the settings asked for;
+                      each level drops one of net, s-step, 16-bit, reduced storage)       */
 } lqt_solve_stats;
 
 /* Trace estimate, Section 1 and Algorithms 1/2.  All values are FP64. */
@@ -120,6 +133,7 @@ typedef struct {
     long long iters_total;     /* Arnoldi steps summed over the probe solves             */
     double seconds_solve;      /* device time of the probe solves                         */
     double seconds_setup;      /* device time of probe generation and projections         */
+    int nfallback;             /* probe solves that finished at a fallback level (opts->fallback) */
 } lqt_trace_result;
 
 /* Options of the learned-preconditioner training (lqt_precond_train). */

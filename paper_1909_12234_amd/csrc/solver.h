@@ -17,6 +17,8 @@ struct SolveOpts {
     int graph = 0;
     int sstep = 0;
     double reliable = 0.1;  // 0: the FP64 residual at every restart
+    int fallback = 0;       // 1: stalled systems continue down the fallback chain (stall.h)
+    int stall_window = 2;   // FP64 residuals without a decrease that count as a stall
 };
 
 SolveOpts make_opts(const lqt_solver_opts* u);

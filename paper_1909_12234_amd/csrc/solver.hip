@@ -17,6 +17,7 @@
 #include "lqt_internal.h"
 #include "ptc.h"
 #include "solver.h"
+#include "stall.h"
 
 namespace lqt {
 
@@ -81,10 +82,14 @@ void kry_step_orth(lqt_ctx* c, void* basis, long long vstride, int j, int na, co
     c->timer.end(c->stream);
 }
 
-// Solve nb systems b[0..nb) -> x[0..nb) (device layout FP64, contiguous).
+// Solve nb systems b[0..nb) -> x[0..nb) (device layout FP64, contiguous), from x = 0 or, with
+// warm, from the x given.  stalled (host, nb flags, may be null): systems that stalled (see
+// stall.h) are set to 1 there and left for the caller's fallback instead of being counted as
+// failed; without it only a cycle that took no step ends a system (as failed), and the
+// others run until they converge or reach maxit.
 template <typename S>
 int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, double xi, const SolveOpts& o,
-                lqt_solve_stats* stats) {
+                lqt_solve_stats* stats, bool warm = false, int* stalled = nullptr) {
     const long long n = 12LL * c->g.V;
     const int m = o.restart;
     const size_t eb = sizeof(S);
@@ -138,7 +143,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     std::vector<double> bnorm(nb);
     c->timer.begin(c->stream, KT_KRYLOV);
     norm2_fields(c, b, nb, bn2);
-    LQT_HIP(hipMemsetAsync(x, 0, sizeof(double2) * (size_t)nb * n, c->stream));
+    if (!warm) LQT_HIP(hipMemsetAsync(x, 0, sizeof(double2) * (size_t)nb * n, c->stream));
     c->timer.end(c->stream);
     LQT_HIP(hipMemcpyAsync(h_rn2, bn2, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
     LQT_HIP(hipStreamSynchronize(c->stream));
@@ -163,7 +168,11 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     } graphs;
     std::vector<int> act(nb), its(nb, 0), cyc(nb, 0), done(nb, 0);
     std::vector<double> rel(nb, 1.0), rlast(nb, 0.0);
-    for (int i = 0; i < nb; i++) act[i] = i;
+    std::vector<StallWatch> watch(nb);
+    for (int i = 0; i < nb; i++) {
+        act[i] = i;
+        watch[i].window = stalled ? o.stall_window : 0;  // no fallback: only zero-step cycles end a system
+    }
     int nfail = 0;
     bool carried = false;  // the basis start vectors hold the residuals carried from the last cycle
 
@@ -225,9 +234,12 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
                     }
                     rel[i] = (rr == rr) ? worst : rr;
                 }
-                if (!(rel[i] == rel[i])) {
+                if (!(rel[i] == rel[i])) {  // not finite: the fallback restarts it from zero
                     done[i] = 1;
-                    nfail++;
+                    if (stalled)
+                        stalled[i] = 2;
+                    else
+                        nfail++;
                     continue;
                 }
                 if (rel[i] <= xi) {
@@ -237,6 +249,14 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
                 if (its[i] >= o.maxit) {
                     done[i] = 1;
                     nfail++;
+                    continue;
+                }
+                if (watch[i].formed(rr)) {  // stalled: hand over to the fallback, else failed
+                    done[i] = 1;
+                    if (stalled)
+                        stalled[i] = 1;
+                    else
+                        nfail++;
                     continue;
                 }
                 nact.push_back(i);
@@ -345,9 +365,16 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
         LQT_HIP(hipMemcpyAsync(h_flags, sb.st.kdim, sizeof(int) * nn, hipMemcpyDeviceToHost, c->stream));
         if (carry) LQT_HIP(hipMemcpyAsync(h_rn2c, rn2c, sizeof(double) * nn, hipMemcpyDeviceToHost, c->stream));
         LQT_HIP(hipStreamSynchronize(c->stream));
-        for (int k = 0; k < nn; k++) its[nact[k]] += h_flags[k];
+        // a cycle that took no step would repeat unchanged: its system gets an FP64 residual
+        // next, where the stall watch ends it; at least one step is charged against maxit
+        bool any_zero = false;
+        for (int k = 0; k < nn; k++) {
+            its[nact[k]] += std::max(h_flags[k], 1);
+            watch[nact[k]].cycle(h_flags[k]);
+            any_zero = any_zero || h_flags[k] <= 0;
+        }
         act = nact;
-        carried = carry;
+        carried = carry && !any_zero;
     }
     if (stats)
         for (int i = 0; i < nb; i++) {
@@ -360,6 +387,93 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
 }
 
 }  // namespace
+
+// Solve with storage type chosen by prec (see solve_batch).
+static int solve_dispatch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, double xi, const SolveOpts& o,
+                          lqt_solve_stats* stats, bool warm, int* stalled) {
+    switch (prec) {
+        case LQT_F64: return solve_batch<double2>(c, prec, b, x, nb, xi, o, stats, warm, stalled);
+        case LQT_F32: return solve_batch<float2>(c, prec, b, x, nb, xi, o, stats, warm, stalled);
+        case LQT_F16: return solve_batch<h2>(c, prec, b, x, nb, xi, o, stats, warm, stalled);
+        default: return solve_batch<b2>(c, prec, b, x, nb, xi, o, stats, warm, stalled);
+    }
+}
+
+// The fallback chain for the systems of one batch flagged in `stalled` (1: restart from the
+// current x, 2: from zero): each level of the chain (stall.h) solves them again, gathered
+// into a contiguous batch, and scatters the solutions back; steps and cycles add up in the
+// statistics, whose `fallback` field gets the level.  maxit applies to each level.
+// Returns the systems that still missed the tolerance.
+static int run_fallback(lqt_ctx* c, const double2* b, double2* x, int nb, double xi, const SolveOpts& o0,
+                        lqt_solve_stats* stats, std::vector<int>& stalled) {
+    const long long n = 12LL * c->g.V;
+    const size_t fb = sizeof(double2) * (size_t)n;
+    std::vector<int> idx, how;
+    for (int i = 0; i < nb; i++)
+        if (stalled[i]) {
+            idx.push_back(i);
+            how.push_back(stalled[i]);
+        }
+    ChainCfg cur{o0.prec, o0.use_net, o0.sstep};
+    int level = 0, nfail = 0;
+    while (!idx.empty()) {
+        ChainCfg nx;
+        if (!chain_next(cur, nx)) {  // plain FP64 GMRES stalled as well
+            nfail += (int)idx.size();
+            break;
+        }
+        cur = nx;
+        level++;
+        SolveOpts o = o0;
+        o.prec = cur.prec;
+        o.use_net = cur.net;
+        o.sstep = cur.sstep;
+        const int ns = (int)idx.size();
+        if (o0.verbose) {
+            fprintf(stderr, "[lqtrace] solve: %d stalled system(s) continue at fallback level %d (storage %d%s%s)\n",
+                    ns, level, o.prec, o.use_net ? ", net" : "", o.sstep ? ", s-step" : "");
+            fflush(stderr);
+        }
+        DBuf bs, xs;
+        bs.ensure(fb * ns);
+        xs.ensure(fb * ns);
+        for (int k = 0; k < ns; k++) {
+            LQT_HIP(hipMemcpyAsync((char*)bs.p + fb * k, b + (size_t)idx[k] * n, fb, hipMemcpyDeviceToDevice,
+                                   c->stream));
+            if (how[k] == 2)
+                LQT_HIP(hipMemsetAsync((char*)xs.p + fb * k, 0, fb, c->stream));
+            else
+                LQT_HIP(hipMemcpyAsync((char*)xs.p + fb * k, x + (size_t)idx[k] * n, fb, hipMemcpyDeviceToDevice,
+                                       c->stream));
+        }
+        std::vector<lqt_solve_stats> sub(ns);
+        std::vector<int> st2(ns, 0);
+        nfail += solve_dispatch(c, o.prec, bs.as<double2>(), xs.as<double2>(), ns, xi, o, sub.data(), true,
+                                st2.data());
+        for (int k = 0; k < ns; k++)
+            LQT_HIP(hipMemcpyAsync(x + (size_t)idx[k] * n, (char*)xs.p + fb * k, fb, hipMemcpyDeviceToDevice,
+                                   c->stream));
+        LQT_HIP(hipStreamSynchronize(c->stream));
+        std::vector<int> nidx, nhow;
+        for (int k = 0; k < ns; k++) {
+            if (stats) {
+                lqt_solve_stats& t = stats[idx[k]];
+                t.converged = sub[k].converged;
+                t.iters += sub[k].iters;
+                t.cycles += sub[k].cycles;
+                t.relres = sub[k].relres;
+                t.fallback = level;
+            }
+            if (st2[k]) {
+                nidx.push_back(idx[k]);
+                nhow.push_back(st2[k]);
+            }
+        }
+        idx.swap(nidx);
+        how.swap(nhow);
+    }
+    return nfail;
+}
 
 SolveOpts make_opts(const lqt_solver_opts* u) {
     SolveOpts o;
@@ -376,6 +490,8 @@ SolveOpts make_opts(const lqt_solver_opts* u) {
         o.graph = u->graph;
         o.sstep = u->sstep;
         o.reliable = u->reliable < 0 ? 0.0 : (u->reliable > 0 ? u->reliable : 0.1);
+        o.fallback = u->fallback;
+        o.stall_window = u->stall_window > 0 ? u->stall_window : 2;
     }
     return o;
 }
@@ -408,12 +524,11 @@ int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, 
         const double2* bb = b + (size_t)b0 * n;
         double2* xx = x + (size_t)b0 * n;
         lqt_solve_stats* ss = stats ? stats + b0 : nullptr;
-        switch (o.prec) {
-            case LQT_F64: nfail += solve_batch<double2>(c, o.prec, bb, xx, nb, xi, o, ss); break;
-            case LQT_F32: nfail += solve_batch<float2>(c, o.prec, bb, xx, nb, xi, o, ss); break;
-            case LQT_F16: nfail += solve_batch<h2>(c, o.prec, bb, xx, nb, xi, o, ss); break;
-            default: nfail += solve_batch<b2>(c, o.prec, bb, xx, nb, xi, o, ss); break;
-        }
+        if (ss)
+            for (int i = 0; i < nb; i++) ss[i].fallback = 0;
+        std::vector<int> stalled(o.fallback ? nb : 0, 0);
+        nfail += solve_dispatch(c, o.prec, bb, xx, nb, xi, o, ss, false, o.fallback ? stalled.data() : nullptr);
+        if (o.fallback) nfail += run_fallback(c, bb, xx, nb, xi, o, ss, stalled);
     }
     return nfail;
 }

@@ -417,10 +417,11 @@ int lqt_trace_lattices(lqt_ctx* c, int nprobes, uint64_t seed, double xi, const 
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         long long iters = 0;
-        int nf = 0;
+        int nf = 0, nfb = 0;
         for (auto& x : st) {
             iters += x.iters;
             nf += x.converged ? 0 : 1;
+            nfb += x.fallback > 0 ? 1 : 0;
         }
         for (int l = 0; l < nlat; l++) {
             std::vector<zd> tl(s);
@@ -436,6 +437,7 @@ int lqt_trace_lattices(lqt_ctx* c, int nprobes, uint64_t seed, double xi, const 
             R.var_re_only = S.var_re;
             R.nsolves = s;
             R.nfailed = nf;
+            R.nfallback = nfb;
             R.iters_total = iters;
             R.seconds_solve = t_solve;
             R.seconds_setup = 0;
@@ -573,10 +575,12 @@ int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64
         res->var_re_only = S.var_re;
         res->nsolves = s;
         res->nfailed = 0;
+        res->nfallback = 0;
         res->iters_total = 0;
         for (auto& x : st) {
             res->iters_total += x.iters;
             res->nfailed += x.converged ? 0 : 1;
+            res->nfallback += x.fallback > 0 ? 1 : 0;
         }
         res->seconds_solve = t_solve;
         res->seconds_setup = t_setup;

@@ -28,12 +28,13 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("inner_prec", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("use_net", ctypes.c_int), ("max_batch", ctypes.c_int), ("cgs2", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("verbose", ctypes.c_int), ("outer_maxit", ctypes.c_int),
-                ("graph", ctypes.c_int), ("sstep", ctypes.c_int), ("reliable", ctypes.c_double)]
+                ("graph", ctypes.c_int), ("sstep", ctypes.c_int), ("reliable", ctypes.c_double),
+                ("fallback", ctypes.c_int), ("stall_window", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int), ("iters", ctypes.c_int), ("cycles", ctypes.c_int),
-                ("relres", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("fallback", ctypes.c_int)]
 
 
 class TraceResult(ctypes.Structure):
@@ -41,7 +42,7 @@ class TraceResult(ctypes.Structure):
                 ("t0_im", ctypes.c_double), ("var_sample", ctypes.c_double), ("var_mean", ctypes.c_double),
                 ("jackknife_err", ctypes.c_double), ("var_re_only", ctypes.c_double), ("nsolves", ctypes.c_int),
                 ("nfailed", ctypes.c_int), ("iters_total", ctypes.c_longlong), ("seconds_solve", ctypes.c_double),
-                ("seconds_setup", ctypes.c_double)]
+                ("seconds_setup", ctypes.c_double), ("nfallback", ctypes.c_int)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -119,10 +120,36 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _dev(t, dtype, per, what):
+    """Contiguous device tensor check before its pointer reaches a kernel: a CUDA (HIP)
+    tensor of `dtype` whose element count is a positive multiple of `per`.  Raises
+    TypeError or ValueError; nothing is passed to the library otherwise."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise TypeError(f"{what}: expected a device tensor, got one on {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if per and (t.numel() == 0 or t.numel() % per):
+        raise ValueError(f"{what}: {t.numel()} elements is not a positive multiple of {per}")
+    return t.contiguous()
+
+
+def _host(t, dtype, numel, what):
+    """Host tensor check for buffers the library writes or reads on the CPU side."""
+    if t.is_cuda or t.dtype != dtype or t.numel() != numel:
+        raise TypeError(f"{what}: expected a host {dtype} tensor of {numel} elements")
+    return t.contiguous()
+
+
+# complex dtype of the canonical fields lqt_apply takes for each precision
+_APPLY_DTYPE = {0: torch.complex128, 1: torch.complex64, 2: torch.complex64, 3: torch.complex64}
+
+
 def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0, verbose=0,
-          outer_maxit=0, graph=0, sstep=0, reliable=0.0):
+          outer_maxit=0, graph=0, sstep=0, reliable=0.0, fallback=0, stall_window=0):
     return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit, graph, sstep,
-                      reliable)
+                      reliable, fallback, stall_window)
 
 
 class Context:
@@ -186,21 +213,23 @@ class Context:
         return self._check(lib().lqt_set_mass(self._h, float(mass)))
 
     def apply(self, x, op=A, prec=F64):
-        x = x.contiguous()
+        if int(prec) not in _APPLY_DTYPE:
+            raise ValueError(f"unknown precision {prec}")
+        x = _dev(x, _APPLY_DTYPE[int(prec)], self.N, "apply input")
         out = torch.empty_like(x)
         nrhs = x.numel() // self.N
         self._check(lib().lqt_apply(self._h, int(op), int(prec), _ptr(x), _ptr(out), nrhs))
         return out
 
     def solve(self, b, xi, raise_on_fail=True, **opts):
-        b = b.contiguous()
+        b = _dev(b, torch.complex128, self.N, "solve right-hand sides")
         x = torch.empty_like(b)
         nrhs = b.numel() // self.N
         st = (SolveStats * max(nrhs, 1))()
         o = _opts(**opts)
         rc = lib().lqt_solve(self._h, _ptr(b), _ptr(x), nrhs, float(xi), ctypes.byref(o), st)
         self._check(rc, allow=() if raise_on_fail else (LQT_ENOTCONV,))
-        return x, [(s.converged, s.iters, s.cycles, s.relres) for s in st[:nrhs]], rc
+        return x, [(s.converged, s.iters, s.cycles, s.relres, s.fallback) for s in st[:nrhs]], rc
 
     def probes(self, seed, nprobes, j0=0):
         out = torch.empty((nprobes, self.N), dtype=torch.complex128, device="cuda")
@@ -234,15 +263,16 @@ class Context:
 
     # -- dense building blocks
     def gram(self, X, Y):
-        ka, kb = X.shape[0], Y.shape[0]
-        X, Y = X.contiguous(), Y.contiguous()
+        X = _dev(X, torch.complex128, self.N, "gram X")
+        Y = _dev(Y, torch.complex128, self.N, "gram Y")
+        ka, kb = X.numel() // self.N, Y.numel() // self.N
         out = torch.empty((ka, kb), dtype=torch.complex128)
         self._check(lib().lqt_gram(self._h, _ptr(X), ka, _ptr(Y), kb, _ptr(out)))
         return out
 
     def project_probes(self, X, seed, j0, s):
-        ka = X.shape[0]
-        X = X.contiguous()
+        X = _dev(X, torch.complex128, self.N, "project_probes X")
+        ka = X.numel() // self.N
         cup = torch.empty((ka, s), dtype=torch.complex128)
         cdn = torch.empty((ka, s), dtype=torch.complex128)
         self._check(lib().lqt_project_probes(self._h, _ptr(X), ka, ctypes.c_uint64(seed), int(j0), int(s),
@@ -251,10 +281,14 @@ class Context:
 
     def combine(self, X, C, Y=None, beta=0.0, alpha=1.0):
         ka, kb = C.shape
-        X = X.contiguous()
+        X = _dev(X, torch.complex128, self.N, "combine X")
+        if X.numel() // self.N != ka:
+            raise ValueError("combine: X must hold as many fields as C has rows")
         C = torch.as_tensor(C, dtype=torch.complex128).contiguous().cpu()
         if Y is None:
             Y = torch.zeros((kb, self.N), dtype=torch.complex128, device="cuda")
+        elif not (Y.is_cuda and Y.dtype == torch.complex128 and Y.is_contiguous() and Y.numel() == kb * self.N):
+            raise TypeError("combine: Y must be a contiguous complex128 device tensor of kb fields")
         self._check(lib().lqt_combine(self._h, _ptr(X), ka, _ptr(C), kb, float(beta), float(alpha), _ptr(Y)))
         return Y
 
@@ -283,17 +317,19 @@ class Context:
     def basis_prolongator_from(self, block, nv, W, coarse=None):
         h = ctypes.c_void_p()
         b = (ctypes.c_int * 4)(*block)
-        W = W.contiguous()
+        W = _dev(W, torch.complex128, self.N * int(nv), "prolongator W")
+        if W.numel() != self.N * int(nv):
+            raise ValueError("prolongator W must hold nv * N entries")
         k = 0 if coarse is None else coarse.shape[0]
-        cv = None if coarse is None else coarse.contiguous()
+        cv = None if coarse is None else _dev(coarse, torch.complex128, 0, "coarse vectors")
         self._check(lib().lqt_basis_prolongator_from(self._h, b, int(nv), _ptr(W), _ptr(cv), int(k),
                                                      ctypes.byref(h)))
         return Basis(self, h, nv=nv)
 
     def basis_from_vectors(self, X):
         h = ctypes.c_void_p()
-        X = X.contiguous()
-        self._check(lib().lqt_basis_from_vectors(self._h, _ptr(X), int(X.shape[0]), ctypes.byref(h)))
+        X = _dev(X, torch.complex128, self.N, "basis vectors")
+        self._check(lib().lqt_basis_from_vectors(self._h, _ptr(X), X.numel() // self.N, ctypes.byref(h)))
         return Basis(self, h)
 
     # -- learned preconditioner
@@ -307,7 +343,7 @@ class Context:
         return w
 
     def precond_apply(self, x):
-        x = x.contiguous()
+        x = _dev(x, torch.complex128, self.N, "precond_apply input")
         out = torch.empty_like(x)
         self._check(lib().lqt_precond_apply(self._h, _ptr(x), _ptr(out), x.numel() // self.N))
         return out
@@ -315,7 +351,7 @@ class Context:
     def precond_loss_grad(self, e):
         """Mean loss ||M A e - e||^2/||e||^2 over the fields e and its gradient dL/dconj(W)
         (complex128 array of the 1728 weights) at the current FP32 master weights."""
-        e = e.contiguous()
+        e = _dev(e, torch.complex128, self.N, "precond_loss_grad errors")
         npairs = e.numel() // self.N
         g = torch.empty(2 * WEIGHT_COUNT, dtype=torch.float64)
         loss = ctypes.c_double(0)
@@ -389,7 +425,7 @@ class Basis:
         return out
 
     def restrict(self, fine):
-        fine = fine.contiguous()
+        fine = _dev(fine, torch.complex128, self.ctx.N, "restrict input")
         nrhs = fine.numel() // self.ctx.N
         nc = ctypes.c_longlong(0)
         self.ctx._check(lib().lqt_prolongator_get(self._h, None, ctypes.byref(nc)))
@@ -398,8 +434,10 @@ class Basis:
         return out
 
     def prolong(self, coarse):
-        coarse = coarse.contiguous()
-        nrhs = coarse.shape[0]
+        nc = ctypes.c_longlong(0)
+        self.ctx._check(lib().lqt_prolongator_get(self._h, None, ctypes.byref(nc)))
+        coarse = _dev(coarse, torch.complex128, nc.value, "prolong input")
+        nrhs = coarse.numel() // nc.value
         out = torch.empty((nrhs, self.ctx.N), dtype=torch.complex128, device="cuda")
         self.ctx._check(lib().lqt_prolong(self.ctx._h, self._h, _ptr(coarse), _ptr(out), nrhs))
         return out
