@@ -78,7 +78,7 @@ typedef struct {
     double inner_tol;/* relative reduction asked of one inner cycle [0: one full cycle]  */
     int verbose;     /* 1: progress lines on stderr from long calls (eigensolver, setup) */
     int outer_maxit; /* cap on eigensolver iterations (lqt_basis_eig / the coarse
-                        eigensolve of lqt_basis_prolongator) [60]                       */
+                        eigensolve of lqt_basis_prolongator) [200]                       */
     int graph;       /* 1: capture each inner cycle (all m Arnoldi steps, the small
                         Hessenberg updates and the solution update) in a HIP graph once
                         per batch size and replay it; cycles always run all m steps (the
@@ -108,6 +108,10 @@ typedef struct {
                         0: no fallback; a cycle that takes no step ends its system as failed
                         and other systems run to maxit [0]                                 */
     int stall_window;/* FP64 residuals without a 0.1 % decrease that count as a stall [2]  */
+    int eig_degree;  /* degree in H^2 of the Chebyshev filter of the eigensolvers
+                        (lqt_basis_eig, the coarse eigensolve of lqt_basis_prolongator) [128] */
+    double eig_xi;   /* acceptance tolerance of the coarse eigensolve of
+                        lqt_basis_prolongator [0: null_xi]                                */
 } lqt_solver_opts;
 
 /* Per right-hand side solve statistics. */
@@ -196,12 +200,16 @@ int lqt_solve(lqt_ctx *ctx, const double *d_b, double *d_x, int nrhs, double xi,
 /* ---- deflation bases ---------------------------------------------------------------- */
 
 /* Algorithm 1, first step: the k eigenpairs of the Hermitian operator H = A g5 with the
- * smallest |lambda| (its eigenvectors are left singular vectors of A).  Subspace iteration
- * on T = H^{-1} with k + max(8, k/2) vectors (FP64 Rayleigh-Ritz, MINRES inner solves of H
- * to xi/10, at most min(opts->maxit, 4000) steps each), accepting a pair (mu, v) of T once
- * ||T v - mu v|| <= xi max|mu| (the convergence test of the paper's Table 1); lambda =
- * 1/mu.  Returns LQT_ENOTCONV (with the basis in *out) if not all k pairs pass within
- * opts->outer_maxit iterations (default 60).
+ * smallest |lambda| (the largest of H^{-1} = g5 A^{-1}; its eigenvectors are left singular
+ * vectors of A).  Chebyshev-filtered subspace iteration on H^2 with a block of 2k vectors
+ * (the filter, of degree opts->eig_degree in H^2, runs with FP32 links and vectors when
+ * xi >= 1e-5, FP64 otherwise, one multi-RHS operator launch per application; at most
+ * opts->outer_maxit filtered iterations,
+ * default 200), harmonic Rayleigh-Ritz extraction with target 0 and a final Rayleigh-Ritz of
+ * H in the span of the k accepted vectors (FP64 Gram matrices and eigenproblems).  A pair
+ * (theta, q) is accepted when ||H q - theta q|| <= xi |theta|, which implies the convergence
+ * test of the paper's Table 1, ||H^{-1} q - q/theta|| <= xi ||H^{-1}||.  Returns
+ * LQT_ENOTCONV (with the basis in *out) if not all k pairs pass.
  * tau must be 0 (the i*tau*g5 shift of Section 3.2 is not implemented; LQT_EINVAL).
  * *out receives a basis owned by the caller (free with lqt_basis_free); the context
  * must outlive it. */
@@ -213,8 +221,8 @@ int lqt_basis_eig(lqt_ctx *ctx, int k, double xi, double tau, const lqt_solver_o
  * with A e = A y0 solved to null_xi or null_maxit Arnoldi steps), blocked on
  * block[0..3]-site aggregates and split by chirality (spins {0,1} and {2,3}), orthonormalised
  * per (aggregate, chirality) by two passes of modified Gram-Schmidt; then the k eigenvectors
- * of the Hermitian coarse operator g5^W W^+ A W with the smallest |lambda| (subspace
- * iteration on its inverse, MINRES inner solves, accepted at null_xi as in lqt_basis_eig),
+ * of the Hermitian coarse operator g5^W W^+ A W with the smallest |lambda| (the eigensolver
+ * of lqt_basis_eig in FP64 on the coarse vectors, accepted at opts->eig_xi, default null_xi),
  * rotated so that U^+ g5^W W^+ A W U is diagonal.  The coarse vectors U_c are kept; the
  * fine basis is U = W U_c.  Block extents must divide the lattice; 1 <= nv <= 64; k may be
  * 0 (prolongator only).  Returns LQT_ENOTCONV (with the basis in *out) if the coarse
@@ -227,6 +235,11 @@ int lqt_basis_prolongator(lqt_ctx *ctx, const int block[4], int nv, int k, doubl
  * forms M = X^+ g5 A X, diagonalises it and rotates U = X U_hat.  For LQT_ORTH the columns
  * are orthonormalised first. */
 int lqt_basis_from_vectors(lqt_ctx *ctx, const double *d_vectors, int k, lqt_basis **out);
+
+/* Largest singular value of A (the conditioning of the solves, Section 1: the solution
+ * error of A^{-1}_xi is bounded by kappa(A) xi): square root of the largest Ritz value of
+ * 40 Lanczos steps on A A^+ = (A g5)^2, FP64.  Single-lattice contexts. */
+int lqt_sigma_max(lqt_ctx *ctx, double *h_sigma);
 
 /* Eigenvalues lambda_i of U^+ g5 A U (ascending |lambda|) and the rank k.  lambda may be
  * NULL to query k; otherwise it must hold 2*k doubles (complex). */

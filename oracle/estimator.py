@@ -49,14 +49,20 @@ def oblique_setup(X, AX):
     return U, lam, ug5u, t0
 
 
+def oblique_correction_terms(Z, U, lam):
+    """(s, k) array of the per-mode terms (z_j^T u_i) lambda_i^{-1} (u_i^+ g5 z_j) of each
+    probe's correction; summing the first k' columns gives the rank-k' correction."""
+    N = Z.shape[1]
+    g5 = g5_vec(N)
+    ZU = Z @ U.T                    # (s, k): z_j^T u_i
+    UgZ = np.conj(U) @ (g5 * Z).T   # (k, s): u_i^+ g5 z_j
+    return ZU * (UgZ.T / lam[None, :])
+
+
 def oblique_corrections(Z, U, lam, rank=None):
     """c_j = (z_j^T U) Lambda^{-1} (U^+ g5 z_j) for the first `rank` basis vectors."""
     k = U.shape[0] if rank is None else rank
-    N = Z.shape[1]
-    g5 = g5_vec(N)
-    ZU = Z @ U[:k].T                    # (s, k): z_j^T u_i
-    UgZ = np.conj(U[:k]) @ (g5 * Z).T   # (k, s): u_i^+ g5 z_j
-    return np.einsum("ji,i,ij->j", ZU, 1.0 / lam[:k], UgZ)
+    return oblique_correction_terms(Z, U[:k], lam[:k]).sum(axis=1)
 
 
 def summarize(t, t0=0.0):

@@ -18,7 +18,7 @@
 #include "gemm.h"
 #include "hostla.h"
 #include "lqt_internal.h"
-#include "minres.h"
+#include "eigcheb.h"
 #include "prolong.h"
 #include "solver.h"
 
@@ -464,8 +464,9 @@ int lqt_basis_prolongator(lqt_ctx* c, const int block[4], int nv, int k, double 
                 lqt::HermOp H = [c, B](const double2* in, double2* o2, int nf) { lqt::coarse_herm(c, B, in, o2, nf); };
                 DBuf Qb;
                 std::vector<double> theta, resT;
-                int conv = lqt::eig_subspace(c, nc, H, k, null_xi, o.outer_maxit, std::min(o.maxit, 4000), o.verbose,
-                                             Qb, theta, resT);
+                const double exi = o.eig_xi > 0 ? o.eig_xi : null_xi;
+                int conv = lqt::eig_chebyshev(c, nc, H, nullptr, lqt::wilson_norm_bound(c), k, exi, o.outer_maxit,
+                                              o.eig_degree, o.verbose, Qb, theta, resT);
                 // third step: rotate so that U^+ g5^W W^+ A W U is diagonal
                 lqt::coarse_oblique_setup(c, B, Qb.as<double2>(), k);
                 B->theta.assign(theta.begin(), theta.begin() + k);

@@ -13,12 +13,14 @@ struct SolveOpts {
     int cgs2 = 0;
     double inner_tol = 0.0;
     int verbose = 0;
-    int outer_maxit = 60;
+    int outer_maxit = 200;
     int graph = 0;
     int sstep = 0;
     double reliable = 0.1;  // 0: the FP64 residual at every restart
     int fallback = 0;       // 1: stalled systems continue down the fallback chain (stall.h)
     int stall_window = 2;   // FP64 residuals without a decrease that count as a stall
+    int eig_degree = 128;   // Chebyshev filter degree of the eigensolvers
+    double eig_xi = 0.0;    // acceptance tolerance of the coarse eigensolve (0: null_xi)
 };
 
 SolveOpts make_opts(const lqt_solver_opts* u);

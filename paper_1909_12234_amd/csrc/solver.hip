@@ -486,12 +486,14 @@ SolveOpts make_opts(const lqt_solver_opts* u) {
         o.cgs2 = u->cgs2;
         o.inner_tol = u->inner_tol > 0 ? u->inner_tol : 0.0;
         o.verbose = u->verbose;
-        o.outer_maxit = u->outer_maxit > 0 ? u->outer_maxit : 60;
+        o.outer_maxit = u->outer_maxit > 0 ? u->outer_maxit : 200;
         o.graph = u->graph;
         o.sstep = u->sstep;
         o.reliable = u->reliable < 0 ? 0.0 : (u->reliable > 0 ? u->reliable : 0.1);
         o.fallback = u->fallback;
         o.stall_window = u->stall_window > 0 ? u->stall_window : 2;
+        o.eig_degree = u->eig_degree > 0 ? u->eig_degree : 128;
+        o.eig_xi = u->eig_xi > 0 ? u->eig_xi : 0.0;
     }
     return o;
 }

@@ -9,10 +9,11 @@
 // Only the k x s products U^+ z and U^+ g5 z are kept, which is what lets the estimate be
 // recomputed for every deflation rank after the solves (Section 2.2).
 //
-// Bases: from caller vectors, or from block subspace iteration on (A g5)^{-1}_xi =
-// g5 A^{-1}_xi with FP64 Rayleigh-Ritz (Algorithm 1, first step; the eigenvectors of A g5
-// are left singular vectors of A).  For the oblique projector an A g5 eigenbasis Q enters
-// as X = g5 Q, for which the oblique projector is Q Q^+ when Q is exact.
+// Bases: from caller vectors, or the k eigenpairs of A g5 with the smallest |lambda| (the
+// largest of (A g5)^{-1} = g5 A^{-1}: Algorithm 1, first step; the eigenvectors of A g5 are
+// left singular vectors of A), by Chebyshev-filtered subspace iteration (eigcheb.hip).
+// For the oblique projector an A g5 eigenbasis Q enters as X = g5 Q, for which the oblique
+// projector is Q Q^+ when Q is exact.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -24,7 +25,7 @@
 #include "gemm.h"
 #include "hostla.h"
 #include "lqt_internal.h"
-#include "minres.h"
+#include "eigcheb.h"
 #include "prolong.h"
 #include "solver.h"
 
@@ -105,96 +106,27 @@ void fine_oblique_setup(lqt_ctx* c, lqt_basis* B, const double2* X, int k) {
     }
 }
 
-// Largest singular value of A (= largest |eigenvalue| of the Hermitian A g5), power iteration.
+// Upper bound of ||A|| (and of ||A g5||, ||g5^W W^+ A W|| for orthonormal W): each
+// direction's hop 2 (P- U psi(x+mu) + P+ U^+ psi(x-mu)) with the orthogonal spin projectors
+// P-+ = (1 -+ g_mu)/2 has norm <= 2 sqrt(2), so ||A|| <= |4 + m| + (1/2) 4 (2 sqrt(2)).
+double wilson_norm_bound(const lqt_ctx* c) {
+    double d = 0;
+    for (int l = 0; l < c->g.lat.nlat; l++) d = std::max(d, std::fabs(c->g.lat.diag[l]));
+    return d + 4.0 * std::sqrt(2.0);
+}
+
+// Largest singular value of A: the square root of the largest Ritz value of 40 Lanczos
+// steps on (A g5)^2 = A A^+ (accurate to well below a percent for the extreme eigenvalue).
 double sigma_max(lqt_ctx* c) {
     if (c->sigma_max > 0) return c->sigma_max;
     const long long n = 12LL * c->g.V;
-    DBuf v, w;
-    v.ensure(sizeof(double2) * n);
-    w.ensure(sizeof(double2) * n);
-    gaussian_fields(c, 0x5151, n, 1, v.as<double2>());
-    c->scratch[9].ensure(64);
-    double nv = 0, nw = 0, est = 0;
-    for (int it = 0; it < 40; it++) {
-        dslash(c, LQT_F64, LQT_A_G5, v.p, w.p, 1, n, n);
-        norm2_fields(c, v.as<double2>(), 1, c->scratch[9].as<double>());
-        norm2_fields(c, w.as<double2>(), 1, c->scratch[9].as<double>() + 1);
-        double h[2];
-        d2h(c, h, c->scratch[9].p, 16);
-        nv = std::sqrt(h[0]);
-        nw = std::sqrt(h[1]);
-        est = nw / nv;
-        std::swap(v.p, w.p);
-    }
-    c->sigma_max = est;
-    return est;
+    HermOp H = [c, n](const double2* in, double2* outv, int nf) { dslash(c, LQT_F64, LQT_A_G5, in, outv, nf, n, n); };
+    double bound = 0;
+    const double ritz = lanczos_h2(c, n, H, 40, &bound);
+    c->sigma_max = std::sqrt(ritz);
+    return c->sigma_max;
 }
 
-
-int eig_subspace(lqt_ctx* c, long long n, const HermOp& H, int k, double xi, int maxit, int inner_maxit,
-                 int verbose, DBuf& Qout, std::vector<double>& theta, std::vector<double>& resT) {
-    // Subspace iteration with Rayleigh-Ritz on T = H^{-1}_xi (exterior eigenvalues of T, so
-    // no spurious interior Ritz values): V orthonormal (kk = k + guard vectors), Y = T V by
-    // batched MINRES (solves to xi/10), K = V^+ Y = E diag(mu) E^+ with |mu| descending.
-    // Ritz pair i, (V E_i, theta_i = 1/mu_i), passes the test of the paper's Table 1 when
-    // ||Y E_i - mu_i V E_i|| <= xi ||T||, ||T|| ~ max |mu|; otherwise V <- orth(Y E).  Each
-    // step solves Y = T V afresh, so the inexactness of the solves cannot accumulate.
-    const int kk = (int)std::min<long long>(n / 4, k + std::max(8, k / 2));
-    DBuf Vb, Yb;
-    Vb.ensure(sizeof(double2) * (size_t)kk * n);
-    Yb.ensure(sizeof(double2) * (size_t)kk * n);
-    Qout.ensure(sizeof(double2) * (size_t)kk * n);
-    double2 *Vv = Vb.as<double2>(), *Y = Yb.as<double2>(), *T = Qout.as<double2>();
-    gaussian_fields(c, 0xE16E5EEDull, n, kk, Vv);
-    int r = orthonormalize(c, Vv, kk, T, n);
-    LQT_CHECK(r >= k, LQT_ENOTCONV, "eigensolver start block lost rank");
-    theta.assign(kk, 0.0);
-    resT.assign(kk, 0.0);
-    std::vector<double> mu(kk, 0.0), res(kk, 0.0);
-    int conv = 0;
-    auto t_start = std::chrono::steady_clock::now();
-    for (int it = 0; it < maxit; it++) {
-        std::vector<int> its;
-        minres(c, n, H, Vv, Y, r, 0.1 * xi, inner_maxit, &its);
-        std::vector<zd> K = gram_host(c, Vv, r, Y, r, n);
-        std::vector<double> w;
-        std::vector<zd> E;
-        heev(r, K, w, E, true);  // ascending |mu|: reverse to descending
-        std::vector<zd> Ed((size_t)r * r);
-        for (int j = 0; j < r; j++) {
-            mu[j] = w[r - 1 - j];
-            for (int i = 0; i < r; i++) Ed[(size_t)i * r + j] = E[(size_t)i * r + (r - 1 - j)];
-        }
-        combine_host(c, Vv, r, Ed, r, 0.0, 1.0, T, n);  // Ritz vectors of T
-        combine_host(c, Y, r, Ed, r, 0.0, 1.0, Vv, n);  // T times them
-        c->scratch[9].ensure(sizeof(double) * 2 * r);
-        double* th = c->scratch[9].as<double>();
-        h2d(c, th, mu.data(), sizeof(double) * r);
-        eig_residual_norms(c, Vv, T, th, n, r, th + r);
-        d2h(c, res.data(), th + r, sizeof(double) * r);
-        const double tnorm = std::fabs(mu[0]);
-        conv = 0;
-        for (int i = 0; i < k; i++)
-            if (std::sqrt(res[i]) <= xi * tnorm) conv++;
-        for (int i = 0; i < r; i++) {
-            theta[i] = mu[i] != 0 ? 1.0 / mu[i] : 0.0;
-            resT[i] = std::sqrt(res[i]);
-        }
-        if (verbose) {
-            long long tot = 0;
-            for (int x : its) tot += x;
-            double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-            fprintf(stderr, "[lqtrace] eig it %d: %d/%d pass, |theta| %.3e..%.3e, %lld MINRES steps per solve, %.1f s\n",
-                    it, conv, k, std::fabs(theta[0]), std::fabs(theta[k - 1]), tot / std::max(r, 1), el);
-            fflush(stderr);
-        }
-        if (conv >= k || it + 1 == maxit) break;
-        int r2 = orthonormalize(c, Vv, r, Y, n);  // next block: orth(T V E)
-        LQT_CHECK(r2 >= k, LQT_ENOTCONV, "eigensolver lost rank");
-        r = r2;
-    }
-    return conv;
-}
 
 }  // namespace lqt
 
@@ -293,28 +225,22 @@ int lqt_basis_eig(lqt_ctx* c, int k, double xi, double tau, const lqt_solver_opt
         const long long n = 12LL * c->g.V;
         LQT_CHECK(k <= n / 8, LQT_EINVAL, "k too large for the lattice");
         lqt::SolveOpts o = lqt::make_opts(opts);
-        // Algorithm 1, first step: eigenpairs of g5 A^{-1}_xi = (A g5)^{-1}_xi of largest
-        // magnitude, i.e. the smallest |lambda| of the Hermitian A g5.
+        // Algorithm 1, first step: eigenpairs of g5 A^{-1} = (A g5)^{-1} of largest magnitude,
+        // i.e. the smallest |lambda| of the Hermitian A g5
         lqt::HermOp H = [c, n](const double2* in, double2* outv, int nf) {
             lqt::dslash(c, LQT_F64, LQT_A_G5, in, outv, nf, n, n);
         };
+        lqt::HermOp32 H32 = [c, n](const float2* in, float2* outv, int nf) {
+            lqt::dslash(c, LQT_F32, LQT_A_G5, in, outv, nf, n, n);
+        };
+        const int kk = (int)std::min<long long>(n / 4, 2LL * k);
+        if (xi >= 1e-5 && c->tuned.find(lqt::tune_key(LQT_F32, kk)) == c->tuned.end()) lqt::dslash_tune(c, LQT_F32, kk);
         DBuf Qb;
-        std::vector<double> theta, resT;
-        const int conv = lqt::eig_subspace(c, n, H, k, xi, o.outer_maxit, std::min(o.maxit, 4000), o.verbose, Qb,
-                                           theta, resT);
+        std::vector<double> theta, resid;
+        // the FP32 filter suffices while the accepted residuals are well above FP32 rounding
+        const int conv = lqt::eig_chebyshev(c, n, H, xi >= 1e-5 ? &H32 : nullptr, lqt::wilson_norm_bound(c), k, xi,
+                                            o.outer_maxit, o.eig_degree, o.verbose, Qb, theta, resid);
         double2* Q = Qb.as<double2>();
-        // eigen-residuals ||A g5 q - theta q|| of the returned Ritz vectors
-        std::vector<double> eres(k, 0.0);
-        {
-            DBuf Wq;
-            Wq.ensure(sizeof(double2) * (size_t)k * n);
-            lqt::dslash(c, LQT_F64, LQT_A_G5, Q, Wq.p, k, n, n);
-            c->scratch[9].ensure(sizeof(double) * 2 * k);
-            double* th = c->scratch[9].as<double>();
-            lqt::h2d(c, th, theta.data(), sizeof(double) * k);
-            lqt::eig_residual_norms(c, Wq.as<double2>(), Q, th, n, k, th + k);
-            lqt::d2h(c, eres.data(), th + k, sizeof(double) * k);
-        }
         lqt_basis* B = new lqt_basis();
         B->ctx = c;
         try {
@@ -323,8 +249,7 @@ int lqt_basis_eig(lqt_ctx* c, int k, double xi, double tau, const lqt_solver_opt
             LQT_HIP(hipMemcpyAsync(B->Q.p, Q, sizeof(double2) * (size_t)k * n, hipMemcpyDeviceToDevice, c->stream));
             B->orthonormal = true;
             B->theta.assign(theta.begin(), theta.begin() + k);
-            B->resid.resize(k);
-            for (int i = 0; i < k; i++) B->resid[i] = std::sqrt(eres[i]);
+            B->resid.assign(resid.begin(), resid.begin() + k);
             lqt::gamma5_fields(c, Q, k);  // X = g5 Q (B->Q keeps Q)
             lqt::fine_oblique_setup(c, B, Q, k);
             LQT_HIP(hipStreamSynchronize(c->stream));
@@ -337,6 +262,15 @@ int lqt_basis_eig(lqt_ctx* c, int k, double xi, double tau, const lqt_solver_opt
             c->err = "eigensolver: " + std::to_string(conv) + " of " + std::to_string(k) + " pairs converged";
             throw Error{LQT_ENOTCONV, c->err};
         }
+    });
+}
+
+int lqt_sigma_max(lqt_ctx* c, double* h_sigma) {
+    if (!c || !h_sigma) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
+        need_gauge(c);
+        *h_sigma = lqt::sigma_max(c);
     });
 }
 

@@ -29,7 +29,8 @@ class SolverOpts(ctypes.Structure):
                 ("use_net", ctypes.c_int), ("max_batch", ctypes.c_int), ("cgs2", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("verbose", ctypes.c_int), ("outer_maxit", ctypes.c_int),
                 ("graph", ctypes.c_int), ("sstep", ctypes.c_int), ("reliable", ctypes.c_double),
-                ("fallback", ctypes.c_int), ("stall_window", ctypes.c_int)]
+                ("fallback", ctypes.c_int), ("stall_window", ctypes.c_int), ("eig_degree", ctypes.c_int),
+                ("eig_xi", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -73,6 +74,7 @@ _SIGS = {
     "lqt_basis_prolongator": ([_P, _P, _I, _I, _D, _I, _P, ctypes.POINTER(_P)], _I),
     "lqt_basis_from_vectors": ([_P, _P, _I, ctypes.POINTER(_P)], _I),
     "lqt_basis_eigenvalues": ([_P, _P, ctypes.POINTER(_I)], _I),
+    "lqt_sigma_max": ([_P, ctypes.POINTER(_D)], _I),
     "lqt_basis_vectors": ([_P, _P], _I),
     "lqt_basis_free": ([_P], None),
     "lqt_precond_set": ([_P, _P, ctypes.c_size_t], _I),
@@ -147,9 +149,9 @@ _APPLY_DTYPE = {0: torch.complex128, 1: torch.complex64, 2: torch.complex64, 3: 
 
 
 def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0, verbose=0,
-          outer_maxit=0, graph=0, sstep=0, reliable=0.0, fallback=0, stall_window=0):
+          outer_maxit=0, graph=0, sstep=0, reliable=0.0, fallback=0, stall_window=0, eig_degree=0, eig_xi=0.0):
     return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit, graph, sstep,
-                      reliable, fallback, stall_window)
+                      reliable, fallback, stall_window, eig_degree, eig_xi)
 
 
 class Context:
@@ -260,6 +262,12 @@ class Context:
         byt = (ctypes.c_double * nf)()
         self._check(lib().lqt_kernel_times(self._h, ms, calls, byt, int(mode)))
         return {f: (ms[i], calls[i], byt[i]) for i, f in enumerate(self.KERNEL_FAMILIES)}
+
+    def sigma_max(self):
+        """Largest singular value of A (Lanczos on A A^+)."""
+        v = ctypes.c_double(0)
+        self._check(lib().lqt_sigma_max(self._h, ctypes.byref(v)))
+        return v.value
 
     # -- dense building blocks
     def gram(self, X, Y):

@@ -1,0 +1,71 @@
+"""The benchmark's configuration against the oracle: 16^3x32, m = -1.90, 128 probes, FP16
+s-step GMRES(15) with FP64 defect correction to 1e-8, oblique g5 deflation with a k = 64
+basis from the library's A g5 eigensolver.
+
+The deflation split of Section 2.1 holds for any basis X, so the oracle's estimator is applied
+to the basis vectors the library returns: it forms its own M = X^+ g5 A X with its own
+operator, its eigen-decomposition, t0 and the corrections (z^T U) Lambda^{-1} (U^+ g5 z) of
+every probe and every rank prefix.  The library's corrections are the difference of its
+undeflated and deflated samples of the same probes (the solves of the two calls are bitwise
+identical: fixed reduction orders, same batch)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import core, estimator
+from paper_1909_12234_amd.workloads import PREC, WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+
+def test_headline_deflated_estimate_against_oracle(gpu):
+    lq = gpu
+    w = WORKLOADS["wilson16x32_mixed"]
+    dims, m, s, seed, xi = w["dims"], w["mass"], w["nprobes"], w["probe_seed"], w["xi"]
+    prec = PREC[w["inner_prec"]]
+    N = 12 * int(np.prod(dims))
+    print("headline 16^3x32: eigensolver basis k=64, two traces", flush=True)
+    U = synth.su3_links(dims, w["eps"], w["seed"])
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    c.tune(prec, s)
+    # a partly converged basis is a valid deflation basis for the split (12 filtered iterations)
+    B = c.basis_eig(w["k"], xi=1e-2, outer_maxit=12)
+    opts = dict(prec=prec, restart=w["restart"], sstep=w["sstep"])
+    r0 = c.trace(s, seed, xi, samples=True, **opts)
+    rB = c.trace(s, seed, xi, basis=B, samples=True, rank_curve=True, **opts)
+    assert r0["nfailed"] == 0 and rB["nfailed"] == 0
+    X = B.vectors().cpu().numpy()
+    lam_gpu = B.eigenvalues().numpy()
+    B.close()
+    c.close()
+    print("oracle: A X, M = X^+ g5 A X, corrections", flush=True)
+    AX = core.apply(U, dims, m, core.OP_A, X)
+    Uo, lam, ug5u, t0 = estimator.oblique_setup(X, AX)
+    del AX
+    assert np.allclose(np.sort(np.abs(lam_gpu.real)), np.sort(np.abs(lam)), rtol=1e-9)
+    t0_gpu = complex(rB["t0_re"], rB["t0_im"])
+    assert abs(t0_gpu - t0) <= 1e-9 * abs(t0), (t0_gpu, t0)
+    Z = core.probes(seed, s, N)
+    terms = estimator.oblique_correction_terms(Z, Uo, lam)  # (s, k)
+    del Uo
+    corr_orc = terms.sum(axis=1)
+    corr_gpu = r0["samples"].numpy() - rB["samples"].numpy()
+    scale = np.max(np.abs(corr_orc))
+    # FP64 on both sides; the samples themselves are about 1e6, so their differences carry
+    # about 1e-10 of absolute rounding
+    assert np.max(np.abs(corr_gpu - corr_orc)) <= 1e-9 * scale + 1e-8, np.max(np.abs(corr_gpu - corr_orc))
+    # rank prefixes k' = 0..k (Section 2.2): estimate, one-probe variance and jackknife error of
+    # t0(k') + mean(t - corr(k')) on the library's undeflated samples
+    base = r0["samples"].numpy()
+    curve = rB["rank_curve"].numpy()
+    cum = np.concatenate([np.zeros((s, 1)), np.cumsum(terms, axis=1)], axis=1)
+    t0k = np.concatenate([[0.0], np.cumsum(ug5u / lam)])
+    for kk in range(len(lam) + 1):
+        ref = estimator.summarize(base - cum[:, kk], t0k[kk])
+        assert abs(curve[kk, 0] - ref["estimate"].real) <= 1e-9 * abs(ref["estimate"])
+        assert abs(curve[kk, 1] - ref["var_sample"]) <= 1e-7 * ref["var_sample"]
+        assert abs(curve[kk, 2] - ref["jackknife_err"]) <= 1e-7 * ref["jackknife_err"]
+    assert abs(rB["trace_re"] - curve[-1, 0]) <= 1e-9 * abs(curve[-1, 0])
+    print(f"t0 {t0.real:.6e}, estimate {rB['trace_re']:.6e} +- {rB['jackknife_err']:.3e}, "
+          f"undeflated {r0['trace_re']:.6e} +- {r0['jackknife_err']:.3e}", flush=True)

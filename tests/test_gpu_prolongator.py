@@ -4,6 +4,7 @@ import pytest
 import torch
 
 import synth
+from eigcheck import check_smallest_abs_pairs
 from oracle import core, dense, estimator, prolongator as pr
 
 pytestmark = pytest.mark.gpu
@@ -97,14 +98,39 @@ def test_prolongator_basis_from_near_null_vectors(gpu):
     Wr = _W(dims, block, nv)
     Pr = pr.dense_prolongator(Wr, dims, block)
     assert np.linalg.norm(A @ P) < 0.9 * np.linalg.norm(A @ Pr)
-    # coarse eigenvalues: each within its residual of an eigenvalue of the coarse operator
+    # coarse eigenpairs: the returned coarse vectors U_c = W^+ U are orthonormal, each pair
+    # meets ||H_c u - theta u|| <= xi |theta| on the dense coarse operator
     g5c = pr.coarse_g5(W.shape[0], nv)
     Hc = g5c[:, None] * (P.conj().T @ A @ P)
-    wex = np.linalg.eigvalsh(Hc)
     lam = B.eigenvalues().numpy().real
-    for th in lam:
-        assert np.min(np.abs(wex - th)) <= 1e-2 * np.max(np.abs(wex))
+    Uc = B.restrict(B.vectors()).cpu().numpy()
+    thc = np.einsum("in,in->i", Uc.conj(), (Hc @ Uc.T).T).real
+    assert np.allclose(thc, lam, rtol=1e-8, atol=1e-12)
+    check_smallest_abs_pairs(Hc, thc, Uc, xi=1e-2, tight=False)
     r = c.trace(64, 1000, 1e-10, basis=B)
     assert abs(r["trace_re"] - np.trace(Ai).real) <= 4 * np.sqrt(r["var_mean"])
+    B.close()
+    c.close()
+
+
+def test_coarse_eigensolver_returns_smallest_pairs(gpu):
+    """The coarse eigensolve of Algorithm 2 at a tight tolerance on 4^4 (2^4 aggregates,
+    nv = 6, nc = 192, k = 12): the k smallest |lambda| of the dense g5^W W^+ A W, with the
+    sin-theta bound on the subspace."""
+    lq = gpu
+    dims, block, nv, m, k = (4, 4, 4, 4), (2, 2, 2, 2), 6, 0.1, 12
+    U = synth.su3_links(dims, 0.3, 1)
+    A = dense.dense_operator(U, dims, m)
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    B = c.basis_prolongator(block, nv, k, null_xi=1e-2, null_maxit=200, eig_xi=1e-9, outer_maxit=200)
+    W = B.prolongator().cpu().numpy().reshape(-1, 2, nv, 6 * 16)
+    P = pr.dense_prolongator(W, dims, block)
+    g5c = pr.coarse_g5(W.shape[0], nv)
+    Hc = g5c[:, None] * (P.conj().T @ A @ P)
+    Uc = B.restrict(B.vectors()).cpu().numpy()
+    thc = np.einsum("in,in->i", Uc.conj(), (Hc @ Uc.T).T).real
+    r2, sin, delta = check_smallest_abs_pairs(Hc, thc, Uc, xi=2e-9)
+    print(f"coarse ||R|| {r2:.2e} sin angle {sin:.2e} gap {delta:.2e}", flush=True)
     B.close()
     c.close()

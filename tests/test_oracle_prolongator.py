@@ -89,3 +89,74 @@ def test_prolongator_deflation_identity():
     uc = Ub[:, idx]
     assert np.allclose(np.sort(np.einsum("ni,n,ni->i", uc.conj(), g5c, uc).real),
                        np.sort(np.einsum("in,n,in->i", X.conj(), estimator.g5_vec(N), X).real), atol=1e-12)
+
+
+def test_aggregate_geometry_free_field_coarse_stencil():
+    """Pins the aggregate map itself (the other prolongator pins hold for any partition of the
+    sites).  Unit links and near-null vectors constant over each block make W^+ A W a Wilson
+    operator of the coarse lattice, in closed form from the operator's definition: with the
+    block extents b_mu, a block couples to itself with (4 + m - sum_mu (b_mu - 1)/b_mu) 1 (the
+    internal forward and backward hops cancel their gamma parts), to the next block in +mu
+    with -(1 - g_mu)/(2 b_mu) and in -mu with -(1 + g_mu)/(2 b_mu) (the face carries 1/b_mu of
+    the block's sites), with the antiperiodic -1 on the time hops that wrap, and to no other
+    block.  Extents differ per direction, so a strided or permuted map, swapped directions
+    or a wrong face weight fail it."""
+    dims, block, m = (6, 9, 3, 6), (2, 3, 1, 2), 0.3
+    lx, ly, lz, lt = dims
+    nco = [d // b for d, b in zip(dims, block)]  # (3, 3, 3, 3)
+    V = lx * ly * lz * lt
+    N = 12 * V
+    # 6 near-null vectors: for spin s2 in {0, 1} and colour col, 1 on spins s2 and 2 + s2
+    Y = np.zeros((6, N), dtype=np.complex128)
+    for s2 in range(2):
+        for col in range(3):
+            for sp in (s2, 2 + s2):
+                Y[s2 * 3 + col, np.arange(V) * 12 + 3 * sp + col] = 1.0
+    W = pr.block_orthonormalize(Y, dims, block)
+    P = pr.dense_prolongator(W, dims, block)
+    U = synth.unit_links(dims)
+    AP = core.apply(U, dims, m, core.OP_A, P.T.copy()).T
+    Ac = P.conj().T @ AP
+    nagg = int(np.prod(nco))
+    # closed form, coarse index (a, c, v), v = s2 * 3 + colour, spin = 2 c + s2
+    G = [core.gamma(mu) for mu in range(4)]
+    I4 = np.eye(4)
+
+    def spin_block(S):
+        out = np.zeros((12, 12), dtype=np.complex128)
+        for c in range(2):
+            for s2 in range(2):
+                for cp in range(2):
+                    for s2p in range(2):
+                        for col in range(3):
+                            out[c * 6 + s2 * 3 + col, cp * 6 + s2p * 3 + col] = S[2 * c + s2, 2 * cp + s2p]
+        return out
+
+    ref = np.zeros((nagg * 12, nagg * 12), dtype=np.complex128)
+    diag = (4 + m - sum((b - 1) / b for b in block)) * I4
+    for a in range(nagg):
+        ac = [a % nco[0], (a // nco[0]) % nco[1], (a // (nco[0] * nco[1])) % nco[2], a // (nco[0] * nco[1] * nco[2])]
+        ref[a * 12:(a + 1) * 12, a * 12:(a + 1) * 12] += spin_block(diag)
+        for mu in range(4):
+            for step, S in ((+1, -(I4 - G[mu]) / (2 * block[mu])), (-1, -(I4 + G[mu]) / (2 * block[mu]))):
+                bc = list(ac)
+                bc[mu] = (ac[mu] + step) % nco[mu]
+                wraps = mu == 3 and (ac[mu] + step) % nco[mu] != ac[mu] + step
+                b = bc[0] + nco[0] * (bc[1] + nco[1] * (bc[2] + nco[2] * bc[3]))
+                ref[a * 12:(a + 1) * 12, b * 12:(b + 1) * 12] += spin_block(-S if wraps else S)
+    assert np.max(np.abs(Ac - ref)) <= 1e-13
+    # a strided map (aggregate a = sites with index = a mod nagg) is not that stencil
+    site = np.arange(V).reshape(V // nagg, nagg).T
+    idx = np.empty((nagg, 2, 6 * site.shape[1]), dtype=np.int64)
+    for c in range(2):
+        for bs in range(site.shape[1]):
+            for s2 in range(2):
+                for col in range(3):
+                    idx[:, c, bs * 6 + s2 * 3 + col] = 12 * site[:, bs] + 3 * (2 * c + s2) + col
+    Ps = np.zeros_like(P)
+    for a in range(nagg):
+        for c in range(2):
+            for v in range(6):
+                Ps[idx[a, c], (a * 2 + c) * 6 + v] = W[a, c, v]
+    Acs = Ps.conj().T @ core.apply(U, dims, m, core.OP_A, Ps.T.copy()).T
+    assert np.max(np.abs(Acs - ref)) > 1e-2
