@@ -202,7 +202,7 @@ int lqt_solve(lqt_ctx *ctx, const double *d_b, double *d_x, int nrhs, double xi,
 /* Algorithm 1, first step: the k eigenpairs of the Hermitian operator H = A g5 with the
  * smallest |lambda| (the largest of H^{-1} = g5 A^{-1}; its eigenvectors are left singular
  * vectors of A).  Chebyshev-filtered subspace iteration on H^2 with a block of 2k vectors
- * (the filter, of degree opts->eig_degree in H^2, runs with FP32 links and vectors when
+ * (the filter, of degree at most opts->eig_degree in H^2, runs with FP32 links and vectors when
  * xi >= 1e-5, FP64 otherwise, one multi-RHS operator launch per application; at most
  * opts->outer_maxit filtered iterations,
  * default 200), harmonic Rayleigh-Ritz extraction with target 0 and a final Rayleigh-Ritz of

@@ -22,8 +22,8 @@ double wilson_norm_bound(const lqt_ctx* c);
 double lanczos_h2(lqt_ctx* c, long long n, const HermOp& H, int steps, double* bound);
 
 // The k eigenpairs of H with the smallest |theta|, for H of length-n vectors with
-// ||H|| <= hbound.  Block of 2k vectors (at most n/4); `degree` applications of H^2 per
-// filter; at most maxit filtered iterations.  On return Q (device) holds k orthonormal
+// ||H|| <= hbound.  Block of 2k vectors (at most n/4); at most `degree` applications of H^2
+// per filter (fewer while the filter's growth at 0 would exceed 1e4); at most maxit filtered iterations.  On return Q (device) holds k orthonormal
 // vectors, theta their Ritz values (ascending |theta|) and resid ||H q - theta q||.  A pair
 // passes when resid <= xi |theta|; returns the number of pairs that pass.  H32 (may be null)
 // runs the filter in FP32.

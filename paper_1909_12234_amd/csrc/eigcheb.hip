@@ -236,21 +236,27 @@ int eig_chebyshev(lqt_ctx* c, long long n, const HermOp& H, const HermOp32* H32,
     long long napp = 0;
     for (int it = 0; it <= maxit; it++) {
         if (it > 0) {
+            // degree of this filter: at most `degree`, and low enough that the growth at the
+            // bottom of the spectrum, T_d((b + a)/(b - a)), stays below 1e4, so the block keeps
+            // every wanted direction above the orthonormalisation's rank threshold (the first
+            // iterations, whose cut lies far above the wanted eigenvalues, get short filters)
+            const double x0 = (b + a) / (b - a);
+            const int deg = (int)std::min<double>(degree, std::max(4.0, std::acosh(1e4) / std::acosh(x0)));
             // filter the block (FP32 when an FP32 operator is given), then orthonormalise
             if (f32) {
                 float2* F = Fb.as<float2>();
                 hipLaunchKernelGGL(k_to_f32, grid_of(m), dim3(256), 0, c->stream, V, F, m);
                 LQT_HIP(hipGetLastError());
-                float2* out = cheb_filter<float2>(c, *H32, n, kk, degree, a, b, F);
+                float2* out = cheb_filter<float2>(c, *H32, n, kk, deg, a, b, F);
                 hipLaunchKernelGGL(k_to_f64, grid_of(m), dim3(256), 0, c->stream, out, V, m);
                 LQT_HIP(hipGetLastError());
             } else {
                 double2* F = Fb.as<double2>();
                 LQT_HIP(hipMemcpyAsync(F, V, sizeof(double2) * (size_t)m, hipMemcpyDeviceToDevice, c->stream));
-                double2* out = cheb_filter<double2>(c, H, n, kk, degree, a, b, F);
+                double2* out = cheb_filter<double2>(c, H, n, kk, deg, a, b, F);
                 LQT_HIP(hipMemcpyAsync(V, out, sizeof(double2) * (size_t)m, hipMemcpyDeviceToDevice, c->stream));
             }
-            napp += 2LL * degree * kk;
+            napp += 2LL * deg * kk;
             orth_full(c, V, kk, W, n, 0xC4EB0000ull + 97ull * it);
         }
         H(V, W, kk);

@@ -124,16 +124,17 @@ def _ptr(t):
 
 def _dev(t, dtype, per, what):
     """Contiguous device tensor check before its pointer reaches a kernel: a CUDA (HIP)
-    tensor of `dtype` whose element count is a positive multiple of `per`.  Raises
-    TypeError or ValueError; nothing is passed to the library otherwise."""
+    tensor of `dtype` whose element count is a multiple of `per` (zero fields is the
+    library's no-op).  Raises TypeError or ValueError; nothing is passed to the library
+    otherwise."""
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
     if not t.is_cuda:
         raise TypeError(f"{what}: expected a device tensor, got one on {t.device}")
     if t.dtype != dtype:
         raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
-    if per and (t.numel() == 0 or t.numel() % per):
-        raise ValueError(f"{what}: {t.numel()} elements is not a positive multiple of {per}")
+    if per and t.numel() % per:
+        raise ValueError(f"{what}: {t.numel()} elements is not a multiple of {per}")
     return t.contiguous()
 
 

@@ -27,8 +27,9 @@ def check_smallest_abs_pairs(H, theta, Q, xi=None, tight=True):
     order = np.argsort(np.abs(w), kind="stable")
     want, rest = order[:k], order[k:]
     delta = np.min(np.abs(theta[:, None] - w[rest][None, :])) if rest.size else np.inf
-    c = np.linalg.svd(E[:, want].conj().T @ Qc, compute_uv=False)
-    sin = np.sqrt(max(0.0, 1.0 - np.min(c) ** 2))
+    # sine of the largest angle: the norm of Q's component outside the wanted eigenspace
+    # (computed directly; sqrt(1 - cos^2) would floor at sqrt(2 eps))
+    sin = np.linalg.norm(E[:, rest].conj().T @ Qc, 2) if rest.size else 0.0
     if tight:
         # no unwanted eigenvalue within ||R|| of a returned value: the matches are the wanted ones
         assert delta > r2, (delta, r2)

@@ -53,8 +53,8 @@ def test_apply_rejects_dtype_of_other_precision(ctx):
 def test_apply_rejects_partial_field(ctx):
     with pytest.raises(ValueError, match="multiple"):
         ctx.apply(_dev(ctx.N + 3, torch.complex128))
-    with pytest.raises(ValueError, match="multiple"):
-        ctx.apply(_dev(0, torch.complex128))
+    # zero fields pass the check (the library treats them as a no-op)
+    assert L._dev(_dev(0, torch.complex128), torch.complex128, ctx.N, "x").numel() == 0
 
 
 @pytest.mark.parametrize("call", ["solve", "precond_apply", "precond_loss_grad", "basis_from_vectors", "gram_x",
