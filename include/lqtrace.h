@@ -327,6 +327,19 @@ int lqt_probes(lqt_ctx *ctx, uint64_t seed, long long j0, int nprobes, double *d
  * complex, row-major, written to host memory.  FP64 MFMA. */
 int lqt_gram(lqt_ctx *ctx, const double *d_x, int ka, const double *d_y, int kb, double *h_c);
 
+/* C = X^+ Y as lqt_gram, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the call allocates
+ * nothing.  Its workspace (the contraction's chunk partials and the ka x kb result) is a
+ * static device array of 32 MiB that each GPU holds from the library's first context on it
+ * until the process ends; ka * kb may be at most 1048576 (LQT_EINVAL beyond).  d_x, d_y:
+ * canonical complex128 device arrays; h_c: host, ka x kb complex row-major.  Results agree
+ * with lqt_gram up to the order of the FP64 sums.  Every call on a GPU shares that GPU's
+ * array (it keeps the last call's contents; nothing in it needs clearing), so calls that
+ * overlap on one GPU, from several contexts or threads, race and must be serialised by the
+ * caller. */
+int lqt_gram_noalloc(lqt_ctx *ctx, const double *d_x, int ka, const double *d_y, int kb,
+                     double *h_c);
+
 /* C_up = X^+ P_+ Z and C_dn = X^+ P_- Z for the Rademacher probes Z (generated on the
  * fly, j0 .. j0+s-1) where P_+/- keep spins {0,1} / {2,3}: so X^+ Z = C_up + C_dn and
  * X^+ g5 Z = C_up - C_dn.  Outputs ka x s complex row-major on the host.  FP64 MFMA. */

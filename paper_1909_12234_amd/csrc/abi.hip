@@ -67,6 +67,12 @@ int lqt_create(lqt_ctx** ctx, const int dims[4], double mass, int t_antiperiodic
         delete c;
         return LQT_EHIP;
     }
+    try {
+        lqt::static_scratch_init(c->device);  // device address of lqt_gram_noalloc's workspace
+    } catch (const lqt::Error& e) {
+        delete c;
+        return e.code;
+    }
     c->timer.init();
     *ctx = c;
     return LQT_OK;

@@ -37,14 +37,15 @@ constexpr int NB = 4;          // 16-column tiles per wave
 constexpr long long KC = 8192; // contraction chunk per block
 
 // ---------------------------------------------------------------- C = X^+ Y
+// chunk z of the contraction index covers [z kc, (z + 1) kc), kc a multiple of 4
 __global__ __launch_bounds__(256) void k_gram_part(const double2* __restrict__ X, int ka, const double2* __restrict__ Y,
-                                                   int kb, long long n, double2* __restrict__ part) {
+                                                   int kb, long long n, long long kc, double2* __restrict__ part) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
     const int a0 = blockIdx.x * 64 + 16 * w;
     const int b0 = blockIdx.y * 16 * NB;
-    const long long kbeg = (long long)blockIdx.z * KC;
-    const long long kend = min(n, kbeg + KC);
+    const long long kbeg = (long long)blockIdx.z * kc;
+    const long long kend = min(n, kbeg + kc);
     d4 ar[NB], ai[NB];
 #pragma unroll
     for (int t = 0; t < NB; t++) ar[t] = ai[t] = d4{0, 0, 0, 0};
@@ -190,13 +191,24 @@ void gemm_gram(lqt_ctx* c, const double2* X, int ka, const double2* Y, int kb, d
     c->scratch[8].ensure(sizeof(double2) * (size_t)nc * ka * kb);
     dim3 grid((ka + 63) / 64, (kb + 16 * NB - 1) / (16 * NB), nc);
     c->timer.begin(c->stream, KT_PROJ);
-    hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, c->stream, X, ka, Y, kb, n, c->scratch[8].as<double2>());
+    hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, c->stream, X, ka, Y, kb, n, KC, c->scratch[8].as<double2>());
     LQT_HIP(hipGetLastError());
     long long ne = (long long)ka * kb;
     hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, c->stream,
                        c->scratch[8].as<double2>(), nc, ne, C_dev);
     LQT_HIP(hipGetLastError());
     c->timer.end(c->stream);
+}
+
+void gemm_gram_into(hipStream_t st, const double2* X, int ka, const double2* Y, int kb, long long n, int nc,
+                    double2* part, double2* C_dev) {
+    const long long kc = (((n + nc - 1) / nc) + 3) / 4 * 4;
+    dim3 grid((ka + 63) / 64, (kb + 16 * NB - 1) / (16 * NB), nc);
+    hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, st, X, ka, Y, kb, n, kc, part);
+    LQT_HIP(hipGetLastError());
+    const long long ne = (long long)ka * kb;
+    hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, part, nc, ne, C_dev);
+    LQT_HIP(hipGetLastError());
 }
 
 void gemm_probes(lqt_ctx* c, const double2* X, int ka, uint64_t seed, long long j0, int s, double2* Cup_dev,

@@ -370,6 +370,11 @@ struct lqt_basis {
 
 namespace lqt {
 
+// ---- static workspace of lqt_gram_noalloc (noalloc.hip)
+#define LQT_STATIC_SCRATCH_BYTES (32u << 20)
+// look up the workspace's device address on `device` (current) once; called by lqt_create
+void static_scratch_init(int device);
+
 // ---- layout (layout.hip)
 void gauge_upload(lqt_ctx* c, const double* links, int on_device, double* max_unit_err, double* max_det_err);
 void to_device_layout(lqt_ctx* c, const double2* canon, double2* dev, int nrhs);

@@ -85,6 +85,7 @@ _SIGS = {
     "lqt_trace": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _P, _P, _P, _P], _I),
     "lqt_probes": ([_P, ctypes.c_uint64, ctypes.c_longlong, _I, _P], _I),
     "lqt_gram": ([_P, _P, _I, _P, _I, _P], _I),
+    "lqt_gram_noalloc": ([_P, _P, _I, _P, _I, _P], _I),
     "lqt_project_probes": ([_P, _P, _I, ctypes.c_uint64, ctypes.c_longlong, _I, _P, _P], _I),
     "lqt_combine": ([_P, _P, _I, _P, _I, _D, _D, _P], _I),
     "lqt_restrict": ([_P, _P, _P, _P, _I], _I),
@@ -277,6 +278,18 @@ class Context:
         ka, kb = X.numel() // self.N, Y.numel() // self.N
         out = torch.empty((ka, kb), dtype=torch.complex128)
         self._check(lib().lqt_gram(self._h, _ptr(X), ka, _ptr(Y), kb, _ptr(out)))
+        return out
+
+    def gram_noalloc(self, X, Y, out=None):
+        """C = X^+ Y through the allocation-free entry point (static device workspace);
+        `out` (host complex128, ka x kb) may be given to avoid allocating the result too."""
+        X = _dev(X, torch.complex128, self.N, "gram X")
+        Y = _dev(Y, torch.complex128, self.N, "gram Y")
+        ka, kb = X.numel() // self.N, Y.numel() // self.N
+        if out is None:
+            out = torch.empty((ka, kb), dtype=torch.complex128)
+        out = _host(out, torch.complex128, ka * kb, "gram output")
+        self._check(lib().lqt_gram_noalloc(self._h, _ptr(X), ka, _ptr(Y), kb, _ptr(out)))
         return out
 
     def project_probes(self, X, seed, j0, s):
