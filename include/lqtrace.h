@@ -379,7 +379,10 @@ int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const d
  * storage the vector kernel with packed half-precision arithmetic (kind 2: the half spinors
  * rounded to FP16, link products as FP16 dot products accumulated in FP32; tiles as kind 0)
  * and the same arithmetic with each 256-site block's links staged in LDS once and shared by
- * the 8 right-hand-side groups the block loops over (kind 3, 256-thread blocks only).
+ * the 8 right-hand-side groups the block loops over (kind 3, 256-thread blocks only), and the
+ * streaming kernel whose blocks walk every time slice with the spinors of three slices in
+ * registers (kind 4: FP16, one lattice whose time slices hold a multiple of 256 sites, one
+ * right-hand side per thread, 256-thread blocks).
  * Block orders: chunks of 16, 64, 256 or 1024 site blocks (1024: the whole of most
  * lattices, right-hand-side groups outermost).  *ms
  * receives the best time and tile[0..3] the chosen (rhs per thread or groups per lane, block,
@@ -389,9 +392,9 @@ int lqt_basis_prolongator_from(lqt_ctx *ctx, const int block[4], int nv, const d
 int lqt_tune(lqt_ctx *ctx, int prec, int nrhs, double *ms, int *tile);
 
 /* Set the dslash tiling used for (prec, nrhs) without timing: tile[0..3] as lqt_tune reports
- * it (kind 1 only for LQT_F16 and LQT_BF16, with 1 or 2 groups per lane; kinds 2 and 3
- * only for LQT_F16, kind 3 only with 256-thread blocks).  LQT_EINVAL for a
- * tiling the kernels do not have. */
+ * it (kind 1 only for LQT_F16 and LQT_BF16, with 1 or 2 groups per lane; kinds 2, 3 and 4
+ * only for LQT_F16, kinds 3 and 4 only with 256-thread blocks, kind 4 with one right-hand
+ * side per thread).  LQT_EINVAL for a tiling the kernels do not have. */
 int lqt_set_tile(lqt_ctx *ctx, int prec, int nrhs, const int *tile);
 
 /* Kernel timers: HIP event pairs recorded around the library's launches on the context

@@ -248,7 +248,10 @@ int lqt_set_tile(lqt_ctx* c, int prec, int nrhs, const int* tile) {
         t.kind = tile[3];
         LQT_CHECK(t.block == 64 || t.block == 128 || t.block == 256, LQT_EINVAL, "block must be 64, 128 or 256");
         LQT_CHECK(t.chunk >= 0, LQT_EINVAL, "chunk must be >= 0");
-        if (t.kind == 0 || t.kind == 2 || t.kind == 3) {
+        if (t.kind == 4) {
+            LQT_CHECK(prec == LQT_F16 && t.block == 256 && t.rhs_per_thread == 1, LQT_EINVAL,
+                      "the streaming kernel takes FP16 storage, 256-thread blocks and one rhs per thread");
+        } else if (t.kind == 0 || t.kind == 2 || t.kind == 3) {
             LQT_CHECK(t.rhs_per_thread == 1 || t.rhs_per_thread == 2 || (t.rhs_per_thread == 4 && prec != LQT_F64),
                       LQT_EINVAL, "rhs per thread must be 1, 2 or 4 (1 or 2 for FP64)");
             LQT_CHECK(t.kind == 0 || prec == LQT_F16, LQT_EINVAL, "packed half-precision arithmetic takes FP16 storage");

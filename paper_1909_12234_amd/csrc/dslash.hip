@@ -217,6 +217,24 @@ typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ hv2 ldh(const h2* base, uint32_t i) {
     return __builtin_bit_cast(hv2, *(const uint32_t*)((const char*)base + i * 4u));
 }
+
+// Buffer accesses of the packed FP16 kernels: a field (or the links) is one buffer resource;
+// the word of component c at site s sits at byte voff = 4 s (per lane, one register shared
+// by every component) + soff = 4 c V (uniform, a scalar register), so no per-component
+// address arithmetic runs on the vector ALUs.  Every offset stays below 4 GiB (checked when a
+// context is created), and the resources carry no range limit.
+using brsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ brsrc mkrsrc(const void* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xFFFFFFFFu, 0x00020000);
+}
+__device__ __forceinline__ hv2 bld(brsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(hv2, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+// stores are non-temporal (cache policy NT): outputs are not read again by the launch, so they
+// should not evict the neighbour rows that other blocks are about to read from L2
+__device__ __forceinline__ void bst(brsrc r, hv2 v, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 2);
+}
 // c q for c = CRE + i CIM in {+-1, +-i}
 template <int CRE, int CIM>
 __device__ __forceinline__ hv2 cmul_unit(hv2 q) {
@@ -283,71 +301,237 @@ extern __shared__ hv2 lqt_staged_links[];
 // staged links; backward links (at a neighbour) are read from memory, where those of the
 // block's own sites are in the lines the staging has just read.
 template <int R, bool LDSU = false, int MU = 0, bool BWD = false>
-__device__ __forceinline__ void pk_load(PkBuf<R>& b, const h2* __restrict__ Um, const h2* const inb[R], uint32_t V,
-                                        uint32_t sl, uint32_t sn, bool g5in, uint32_t s0 = 0) {
+__device__ __forceinline__ void pk_load(PkBuf<R>& b, brsrc rU, const brsrc inr[R], uint32_t V, uint32_t sl,
+                                        uint32_t sn, bool g5in, uint32_t s0 = 0) {
     if constexpr (LDSU && !BWD) {
         const uint32_t li = (9 * MU) * 256 + (sl - s0);
 #pragma unroll
         for (int i = 0; i < 9; i++) b.u[i] = lqt_staged_links[i * 256 + li];
     } else {
 #pragma unroll
-        for (int i = 0; i < 9; i++) b.u[i] = ldh(Um, i * V + sl);
+        for (int i = 0; i < 9; i++) b.u[i] = bld(rU, sl * 4u, (uint32_t)(9 * MU + i) * V * 4u);
     }
 #pragma unroll
     for (int r = 0; r < R; r++)
 #pragma unroll
         for (int c = 0; c < 12; c++) {
-            b.p[r][c] = ldh(inb[r], c * V + sn);
+            b.p[r][c] = bld(inr[r], sn * 4u, (uint32_t)c * V * 4u);
             if (g5in && c >= 6) b.p[r][c] = -b.p[r][c];
         }
 }
 template <int MU, int SG, bool BWD, int R>
-__device__ __forceinline__ void pk_comp(const PkBuf<R>& b, cpx<float> acc[R][12]) {
+__device__ __forceinline__ void pk_comp_up(const hv2 u[9], const hv2 p[R][12], cpx<float> acc[R][12]) {
     cpx<float> o0[3], o1[3];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        pk_half<MU, SG, BWD, 0>(b.u, b.p[r], o0);
-        pk_half<MU, SG, BWD, 1>(b.u, b.p[r], o1);
+        pk_half<MU, SG, BWD, 0>(u, p[r], o0);
+        pk_half<MU, SG, BWD, 1>(u, p[r], o1);
         rebuild_add<MU, SG>(acc[r], o0, o1);
     }
 }
+template <int MU, int SG, bool BWD, int R>
+__device__ __forceinline__ void pk_comp(const PkBuf<R>& b, cpx<float> acc[R][12]) {
+    pk_comp_up<MU, SG, BWD, R>(b.u, b.p, acc);
+}
 template <bool DAG, int R, bool LDSU = false>
-__device__ __forceinline__ void hop_all_pk(const h2* __restrict__ U, const h2* const inb[R], uint32_t V, uint32_t s,
-                                           const uint32_t nf[4], const uint32_t nb[4], bool g5in,
-                                           cpx<float> acc[R][12], uint32_t s0 = 0) {
+__device__ __forceinline__ void hop_all_pk(brsrc rU, const brsrc inr[R], uint32_t V, uint32_t s, const uint32_t nf[4],
+                                           const uint32_t nb[4], bool g5in, cpx<float> acc[R][12], uint32_t s0 = 0) {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
-    const h2* U1 = U + 9ll * V;
-    const h2* U2 = U + 18ll * V;
-    const h2* U3 = U + 27ll * V;
     // with staged links the scheduler would pull every LDS read to the top (one hop's reads
     // in flight is the design): a scheduling fence after each hop's products
     auto fence = [] {
         if constexpr (LDSU) __builtin_amdgcn_sched_barrier(0);
     };
     PkBuf<R> A, B;
-    pk_load<R, LDSU, 0>(A, U, inb, V, s, nf[0], g5in, s0);
-    pk_load<R, LDSU, 0, true>(B, U, inb, V, nb[0], nb[0], g5in, s0);
+    pk_load<R, LDSU, 0>(A, rU, inr, V, s, nf[0], g5in, s0);
+    pk_load<R, LDSU, 0, true>(B, rU, inr, V, nb[0], nb[0], g5in, s0);
     pk_comp<0, SF, false, R>(A, acc);
     fence();
-    pk_load<R, LDSU, 1>(A, U1, inb, V, s, nf[1], g5in, s0);
+    pk_load<R, LDSU, 1>(A, rU, inr, V, s, nf[1], g5in, s0);
     pk_comp<0, SB, true, R>(B, acc);
     fence();
-    pk_load<R, LDSU, 1, true>(B, U1, inb, V, nb[1], nb[1], g5in, s0);
+    pk_load<R, LDSU, 1, true>(B, rU, inr, V, nb[1], nb[1], g5in, s0);
     pk_comp<1, SF, false, R>(A, acc);
     fence();
-    pk_load<R, LDSU, 2>(A, U2, inb, V, s, nf[2], g5in, s0);
+    pk_load<R, LDSU, 2>(A, rU, inr, V, s, nf[2], g5in, s0);
     pk_comp<1, SB, true, R>(B, acc);
     fence();
-    pk_load<R, LDSU, 2, true>(B, U2, inb, V, nb[2], nb[2], g5in, s0);
+    pk_load<R, LDSU, 2, true>(B, rU, inr, V, nb[2], nb[2], g5in, s0);
     pk_comp<2, SF, false, R>(A, acc);
     fence();
-    pk_load<R, LDSU, 3>(A, U3, inb, V, s, nf[3], g5in, s0);
+    pk_load<R, LDSU, 3>(A, rU, inr, V, s, nf[3], g5in, s0);
     pk_comp<2, SB, true, R>(B, acc);
     fence();
-    pk_load<R, LDSU, 3, true>(B, U3, inb, V, nb[3], nb[3], g5in, s0);
+    pk_load<R, LDSU, 3, true>(B, rU, inr, V, nb[3], nb[3], g5in, s0);
     pk_comp<3, SF, false, R>(A, acc);
     pk_comp<3, SB, true, R>(B, acc);
+}
+
+// ---- Streaming operator (kind 4 of the tuner): FP16 storage, packed half arithmetic.
+// A block owns 256 consecutive sites of a time slice (one site per thread, R right-hand
+// sides) and walks every slice of its right-hand-side group in turn.  The spinors of its
+// sites at t-1, t and t+1 stay in registers, so the +-t neighbours are read from memory once
+// per sweep instead of once per neighbouring site; U_t(x - t) is the previous step's forward
+// link.  The +-x, +-y, +-z neighbours lie in the same slice: the blocks of one group run on
+// one XCD (contiguous logical blocks) and advance together, so a slice's rows are read from
+// HBM by their own block and found in L2 by the blocks next to it.  Single-lattice contexts
+// whose slice holds a multiple of 256 sites.  Measured at 16^3x32 with 128 right-hand sides it
+// fetches as many bytes as the site-block kernels: with one right-hand side per thread (two
+// spill) every group reads all links again, which takes back what the rolling slices save.
+template <int R>
+struct Sp {
+    hv2 p[R][12];
+};
+
+template <int R>
+__device__ __forceinline__ void ld_sp(Sp<R>& d, const brsrc inr[R], uint32_t V, uint32_t s, bool g5in) {
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            d.p[r][c] = bld(inr[r], s * 4u, (uint32_t)c * V * 4u);
+            if (g5in && c >= 6) d.p[r][c] = -d.p[r][c];
+        }
+}
+
+// the 9 words of U_mu at site s
+template <int MU>
+__device__ __forceinline__ void ld_link9(hv2 u[9], brsrc rU, uint32_t V, uint32_t s) {
+#pragma unroll
+    for (int i = 0; i < 9; i++) u[i] = bld(rU, s * 4u, (uint32_t)(9 * MU + i) * V * 4u);
+}
+
+// one slice t of the streaming operator: prev/cur/next hold psi at t-1, t, t+1 of the
+// thread's site; at the end psi(t + 2) is loading into prev's registers
+template <int R, bool DAG, bool G5IN, bool G5OUT>
+__device__ __forceinline__ void tstream_step(brsrc rU, const brsrc inr[R], const brsrc outr[R], Sp<R>& prev,
+                                             const Sp<R>& cur, const Sp<R>& next, hv2 utp[9], uint32_t V,
+                                             uint32_t S, int L3, int t, uint32_t s0, const uint32_t nf[3],
+                                             const uint32_t nb[3], int nr, float diag, float hs) {
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const uint32_t st = (uint32_t)t * S;
+    const uint32_t s = st + s0;
+    cpx<float> acc[R][12];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[r][c] = {0.f, 0.f};
+    // -t hop with the previous step's link, then prev's registers take psi(t + 2)
+    pk_comp_up<3, SB, true, R>(utp, prev.p, acc);
+    if (t + 2 <= L3) ld_sp<R>(prev, inr, V, (uint32_t)((t + 2) % L3) * S + s0, G5IN);
+    // +t hop: U_t(s) is this step's forward link and the next step's backward one
+    ld_link9<3>(utp, rU, V, s);
+    pk_comp_up<3, SF, false, R>(utp, next.p, acc);
+    // +-x, +-y, +-z hops, one link and its spinors at a time (the registers go to the three
+    // rolling slices; the other waves of the SIMD hide the load latency)
+    PkBuf<R> A;
+    pk_load<R, false, 0>(A, rU, inr, V, s, st + nf[0], G5IN);
+    pk_comp<0, SF, false, R>(A, acc);
+    pk_load<R, false, 0, true>(A, rU, inr, V, st + nb[0], st + nb[0], G5IN);
+    pk_comp<0, SB, true, R>(A, acc);
+    pk_load<R, false, 1>(A, rU, inr, V, s, st + nf[1], G5IN);
+    pk_comp<1, SF, false, R>(A, acc);
+    pk_load<R, false, 1, true>(A, rU, inr, V, st + nb[1], st + nb[1], G5IN);
+    pk_comp<1, SB, true, R>(A, acc);
+    pk_load<R, false, 2>(A, rU, inr, V, s, st + nf[2], G5IN);
+    pk_comp<2, SF, false, R>(A, acc);
+    pk_load<R, false, 2, true>(A, rU, inr, V, st + nb[2], st + nb[2], G5IN);
+    pk_comp<2, SB, true, R>(A, acc);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (r < nr) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                const hv2 pc = cur.p[r][c];
+                float vx = fmaf(diag, (float)pc.x, hs * acc[r][c].x);
+                float vy = fmaf(diag, (float)pc.y, hs * acc[r][c].y);
+                if (G5OUT && c >= 6) {
+                    vx = -vx;
+                    vy = -vy;
+                }
+                bst(outr[r], hv2{(_Float16)vx, (_Float16)vy}, s * 4u, (uint32_t)c * V * 4u);
+            }
+        }
+    }
+}
+
+template <int R, int OPK>
+__global__ __launch_bounds__(256, 2) void k_dslash_tstream(const h2* __restrict__ U, const h2* __restrict__ in,
+                                                           h2* __restrict__ out, LatTab tab, int nrhs,
+                                                           long long in_stride, long long out_stride, double shift,
+                                                           double scale) {
+    constexpr bool DAG = OPK == LQT_A_DAG;
+    constexpr bool G5IN = OPK == LQT_A_G5, G5OUT = OPK == LQT_G5_A;
+    const int L0 = tab.L[0][0], L1 = tab.L[0][1], L2 = tab.L[0][2], L3 = tab.L[0][3];
+    const uint32_t S = (uint32_t)(L0 * L1 * L2);
+    const uint32_t V = S * (uint32_t)L3;
+    const int nsb = (int)(S >> 8);
+    const int ngrp = (nrhs + R - 1) / R;
+    const int lb = xcd_block(ngrp * nsb);
+    if (lb < 0) return;
+    const int grp = lb / nsb, sb = lb - grp * nsb;
+    const uint32_t s0 = (uint32_t)sb * 256u + threadIdx.x;  // site within the slice
+    const int x = s0 % L0, y = (s0 / L0) % L1, z = s0 / (L0 * L1);
+    const uint32_t s1 = L0, s2 = L0 * L1;
+    const uint32_t nf[3] = {x == L0 - 1 ? s0 - (L0 - 1) : s0 + 1, y == L1 - 1 ? s0 - (L1 - 1) * s1 : s0 + s1,
+                            z == L2 - 1 ? s0 - (L2 - 1) * s2 : s0 + s2};
+    const uint32_t nb[3] = {x == 0 ? s0 + (L0 - 1) : s0 - 1, y == 0 ? s0 + (L1 - 1) * s1 : s0 - s1,
+                            z == 0 ? s0 + (L2 - 1) * s2 : s0 - s2};
+    const int r0 = grp * R;
+    const int nr = min(R, nrhs - r0);
+    brsrc inr[R], outr[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int rr = min(r0 + r, nrhs - 1);
+        inr[r] = mkrsrc(in + (long long)rr * in_stride);
+        outr[r] = mkrsrc(out + (long long)rr * out_stride);
+    }
+    const brsrc rU = mkrsrc(U);
+    const float diag = (float)((tab.diag[0] - shift) * scale);
+    const float hs = (float)(-0.5 * scale);
+    Sp<R> A, B, C;
+    hv2 utp[9];
+    ld_sp<R>(A, inr, V, (uint32_t)(L3 - 1) * S + s0, G5IN);
+    ld_sp<R>(B, inr, V, s0, G5IN);
+    ld_sp<R>(C, inr, V, S + s0, G5IN);
+    ld_link9<3>(utp, rU, V, (uint32_t)(L3 - 1) * S + s0);
+#pragma unroll 1
+    for (int t = 0; t < L3; t += 3) {
+        tstream_step<R, DAG, G5IN, G5OUT>(rU, inr, outr, A, B, C, utp, V, S, L3, t, s0, nf, nb, nr, diag, hs);
+        if (t + 1 < L3)
+            tstream_step<R, DAG, G5IN, G5OUT>(rU, inr, outr, B, C, A, utp, V, S, L3, t + 1, s0, nf, nb, nr, diag, hs);
+        if (t + 2 < L3)
+            tstream_step<R, DAG, G5IN, G5OUT>(rU, inr, outr, C, A, B, utp, V, S, L3, t + 2, s0, nf, nb, nr, diag, hs);
+    }
+}
+
+// kind 4 applies: FP16 storage, one lattice, slices of a multiple of 256 sites
+static bool tstream_fits(const Geom& g) {
+    const long long S = (long long)g.lat.L[0][0] * g.lat.L[0][1] * g.lat.L[0][2];
+    return g.lat.nlat == 1 && S % 256 == 0 && (long long)g.V == S * g.lat.L[0][3];
+}
+
+template <int R>
+static void launch_tstream(lqt_ctx* c, int op, const void* in, void* out, int nrhs, long long is, long long os,
+                           double shift, double scale) {
+    const Geom& g = c->g;
+    LQT_CHECK(tstream_fits(g), LQT_EINVAL, "streaming operator: one lattice with slices of a multiple of 256 sites");
+    const long long S = (long long)g.lat.L[0][0] * g.lat.L[0][1] * g.lat.L[0][2];
+    const int nl = (int)(S / 256) * ((nrhs + R - 1) / R);
+    const h2* U = c->U[LQT_F16].as<h2>();
+#define LQT_TSTREAM_OP(OPK)                                                                               \
+    hipLaunchKernelGGL((k_dslash_tstream<R, OPK>), dim3(xcd_grid(nl)), dim3(256), 0, c->stream, U, (const h2*)in, \
+                       (h2*)out, g.lat, nrhs, is, os, shift, scale)
+    switch (op) {
+        case LQT_A_DAG: LQT_TSTREAM_OP(LQT_A_DAG); break;
+        case LQT_A_G5: LQT_TSTREAM_OP(LQT_A_G5); break;
+        case LQT_G5_A: LQT_TSTREAM_OP(LQT_G5_A); break;
+        default: LQT_TSTREAM_OP(LQT_A); break;
+    }
+#undef LQT_TSTREAM_OP
+    LQT_HIP(hipGetLastError());
 }
 
 // EPI 0: out = op(in).  EPI 1 (FP64 only): out = b - A in, with per-block partial |out|^2.
@@ -402,7 +586,7 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
 #pragma unroll 4
         for (int k = 0; k < 36; k++)
             lqt_staged_links[k * 256 + threadIdx.x] =
-                s_blk < V ? ldh((const h2*)U, k * V + s_blk) : hv2{(_Float16)0, (_Float16)0};
+                s_blk < V ? bld(mkrsrc(U), s_blk * 4u, (uint32_t)k * V * 4u) : hv2{(_Float16)0, (_Float16)0};
         __syncthreads();
     }
     double nrm[R];
@@ -451,10 +635,10 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
                 const uint32_t tb = (t == 0) ? s + (L3 - 1) * s3 : s - s3;
                 if constexpr (PKH) {
                     const uint32_t nf[4] = {xf, yf, zf, tf}, nbk[4] = {xb, yb, zb, tb};
-                    if constexpr (G > 1)
-                        hop_all_pk<DAG, R, true>((const h2*)U, (const h2* const*)inb, V, s, nf, nbk, g5in, acc, s0);
-                    else
-                        hop_all_pk<DAG, R>(U, inb, V, s, nf, nbk, g5in, acc);
+                    brsrc inr[R];
+#pragma unroll
+                    for (int r = 0; r < R; r++) inr[r] = mkrsrc(inb[r]);
+                    hop_all_pk<DAG, R, (G > 1)>(mkrsrc(U), inr, V, s, nf, nbk, g5in, acc, s0);
                 } else {
                     hop_dir<0, DAG, R, S, C>(U, inb, V, s, xf, xb, g5in, acc);
                     hop_dir<1, DAG, R, S, C>(U, inb, V, s, yf, yb, g5in, acc);
@@ -466,11 +650,21 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
             for (int r = 0; r < R; r++) {
                 if (r < nr) {
                     cpx<C> p[12];
-                    if (!pad)
-                        load_spinor<S, C>(inb[r], V, s, g5in, p);
-                    else
+                    if (!pad) {
+                        if constexpr (PKH) {
+#pragma unroll
+                            for (int c = 0; c < 12; c++) {
+                                hv2 w = bld(mkrsrc(inb[r]), s * 4u, (uint32_t)c * V * 4u);
+                                if (g5in && c >= 6) w = -w;
+                                p[c] = {(C)(float)w.x, (C)(float)w.y};
+                            }
+                        } else {
+                            load_spinor<S, C>(inb[r], V, s, g5in, p);
+                        }
+                    } else {
 #pragma unroll
                         for (int c = 0; c < 12; c++) p[c] = {0, 0};
+                    }
                     S* o = out + (long long)(r0 + r) * out_stride;  // uniform
 #pragma unroll
                     for (int c = 0; c < 12; c++) {
@@ -485,7 +679,10 @@ __global__ __launch_bounds__(256) void k_dslash(const S* __restrict__ U, const S
                             v.y = b.y - v.y;
                             nrm[r] += (double)v.x * v.x + (double)v.y * v.y;
                         }
-                        st_c<C>(at(o, c * V + s), v);
+                        if constexpr (PKH)
+                            bst(mkrsrc(o), hv2{(_Float16)v.x, (_Float16)v.y}, s * 4u, (uint32_t)c * V * 4u);
+                        else
+                            st_c<C>(at(o, c * V + s), v);
                     }
                 }
             }
@@ -598,6 +795,11 @@ static void dslash_cfg(lqt_ctx* c, int prec, int op, const void* in, void* out, 
         dslash_mf(c, prec, op, in, out, nrhs, is, os, t, shift, scale);
         return;
     }
+    if (t.kind == 4) {
+        LQT_CHECK(prec == LQT_F16, LQT_EINVAL, "streaming dslash: FP16 storage only");
+        launch_tstream<1>(c, op, in, out, nrhs, is, os, shift, scale);
+        return;
+    }
     if (t.kind == 2 || t.kind == 3) {
         LQT_CHECK(prec == LQT_F16, LQT_EINVAL, "packed half-precision dslash: FP16 storage only");
         if (t.kind == 2)
@@ -648,6 +850,11 @@ double dslash_tune(lqt_ctx* c, int prec, int nrhs, Tuned* chosen) {
     // vector kernel with packed half-precision arithmetic (kind 2) and the same with the
     // block's links staged in LDS for 8 groups of right-hand sides (kind 3, 256-site blocks)
     std::vector<Tuned> cand;
+    if (prec == LQT_F16 && tstream_fits(c->g)) {  // streaming kernel (kind 4), one rhs per thread
+        Tuned t{1, 256, 0};
+        t.kind = 4;
+        cand.push_back(t);
+    }
     for (int kind = 0; kind < 4; kind++)
         for (int ri = 0; ri < 3; ri++) {
             if (kind == 0 && (Rs[ri] > nrhs || (prec == LQT_F64 && Rs[ri] > 2))) continue;

@@ -1,5 +1,6 @@
-"""The FP16 Wilson operator with packed half-precision arithmetic (tuner kinds 2 and 3; kind 3
-stages each 256-site block's links in LDS for 8 right-hand-side groups) against the oracle.
+"""The FP16 Wilson operator with packed half-precision arithmetic (tuner kinds 2, 3 and 4; kind 3
+stages each 256-site block's links in LDS for 8 right-hand-side groups, kind 4 streams each
+block through the time slices) against the oracle.
 
 Inputs and links as the library stores them (tests/storage16.py).  The kernel rounds each
 half spinor h = p_a + c p_b (c = +-1, +-i) to FP16 (|dh| <= u |h|, u = 2^-11 per real), then
@@ -46,6 +47,26 @@ def test_packed_half_dslash_matches_oracle(gpu, dims, eps, op, tile):
     c.close()
 
 
+# the streaming kernel (kind 4): slices of a multiple of 256 sites; odd Lt (the three-slice
+# register rotation ends mid-cycle) and Lt = 2 (the t-1 and t+1 neighbours coincide)
+@pytest.mark.parametrize("dims", [(8, 8, 4, 6), (16, 4, 8, 5), (4, 8, 8, 2)])
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
+def test_streaming_dslash_matches_oracle(gpu, dims, op):
+    lq = gpu
+    nrhs = 3
+    print(f"streaming FP16 dslash dims={dims} op={op}", flush=True)
+    links = synth.su3_links(dims, 0.5, 1)
+    c = lq.Context(dims, -0.4)
+    c.set_gauge(links)
+    c.set_tile(2, nrhs, (1, 256, 0, 4))
+    psi = synth.random_spinors(dims, nrhs, 2).reshape(nrhs, -1)
+    out = c.apply(torch.as_tensor(psi).to(torch.complex64).cuda(), op=op, prec=2).cpu().numpy().astype(np.complex128)
+    ps = stored(psi, 2)
+    ref = core.apply(stored(links, 2, links=True), dims, -0.4, op, ps)
+    _check(out, ref, ps)
+    c.close()
+
+
 def _check(out, ref, ps):
     m, mpsi = np.max(np.abs(ref)), np.max(np.abs(ps))
     for part in (np.real, np.imag):
@@ -53,7 +74,7 @@ def _check(out, ref, ps):
         assert np.all(d <= U * np.abs(part(ref)) + 8 * np.sqrt(3) * U * mpsi + 1e-5 * m), float(np.max(d / m))
 
 
-@pytest.mark.parametrize("tile", [(2, 256, 256, 2), (2, 256, 1024, 2), (2, 256, 0, 3), (2, 256, 64, 3)])
+@pytest.mark.parametrize("tile", [(2, 256, 256, 2), (2, 256, 1024, 2), (2, 256, 0, 3), (2, 256, 64, 3), (1, 256, 0, 4)])
 def test_packed_half_full_size(gpu, tile):
     """16^3x32 with 128 right-hand sides in the benchmark's launch shapes; sampled right-hand
     sides against the oracle"""
