@@ -363,6 +363,16 @@ int lqt_prolong(lqt_ctx *ctx, const lqt_basis *basis, const double *d_coarse, do
  * site_in_block with x fastest, spin2 = spin - 2*chirality) to device memory.  Returns the
  * coarse dimension in *nc. */
 int lqt_prolongator_get(const lqt_basis *basis, double *d_w, long long *nc);
+/* The coarse operator of a prolongator basis as an explicit 9-point stencil of 2nv x 2nv
+ * complex blocks (each aggregate couples to itself and to the aggregates one block away in
+ * +-mu, because A couples nearest neighbours): out = W^+ A W in (herm = 0) or
+ * g5^W W^+ A W in (herm = 1), nrhs coarse vectors [rhs][aggregate][chirality][nv], device
+ * pointers.  The stencil (FP64, nagg * 9 * (2nv)^2 complex) is built from W and the links on
+ * the first call and kept with the basis; nv <= 32.  lqt_basis_prolongator builds it before
+ * the coarse eigensolve. */
+int lqt_coarse_apply(lqt_ctx *ctx, lqt_basis *basis, const double *d_in, double *d_out, int nrhs,
+                     int herm);
+
 /* Install a prolongator from caller-supplied W in the layout above (device), and optionally
  * k coarse vectors U_bar (device, k x nc, may be NULL when k = 0): the library then forms
  * M = U_bar^+ g5^W W^+ A W U_bar, diagonalises it and keeps U_c = U_bar U_hat (Algorithm 2,

@@ -366,6 +366,8 @@ struct lqt_basis {
     lqt::DBuf W;  // [agg][chi][nv][bsites][2][3] complex double
     lqt::DBuf Wf; // FP32 copy
     lqt::DBuf Uc; // coarse eigenvectors (k x Nc) FP64
+    lqt::DBuf Dc; // explicit coarse operator W^+ A W: [agg][9 stencil slots][2nv][2nv] FP64
+    double coarse_build_s = 0;  // seconds spent building Dc
 };
 
 namespace lqt {

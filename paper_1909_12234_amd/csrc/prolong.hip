@@ -28,41 +28,6 @@ using lqt::zd;
 
 namespace lqt {
 
-struct PG {
-    int L0, L1, L2, L3;  // lattice
-    int b0, b1, b2, b3;  // block
-    int n0, n1, n2;      // blocks per direction (x, y, z)
-    int nagg, bsites, d, nv;
-    int V;
-};
-
-static PG make_pg(const lqt_ctx* c, const int* b, int nv) {
-    PG p;
-    p.L0 = c->g.L[0], p.L1 = c->g.L[1], p.L2 = c->g.L[2], p.L3 = c->g.L[3];
-    p.b0 = b[0], p.b1 = b[1], p.b2 = b[2], p.b3 = b[3];
-    p.n0 = p.L0 / p.b0, p.n1 = p.L1 / p.b1, p.n2 = p.L2 / p.b2;
-    p.bsites = p.b0 * p.b1 * p.b2 * p.b3;
-    p.nagg = c->g.V / p.bsites;
-    p.d = 6 * p.bsites;
-    p.nv = nv;
-    p.V = c->g.V;
-    return p;
-}
-
-static PG pg_of(const lqt_basis* B) {
-    PG p = make_pg(B->ctx, B->block, B->nv);
-    return p;
-}
-
-__device__ __forceinline__ int site_of(const PG& p, int agg, int bs) {
-    const int ax = agg % p.n0, ay = (agg / p.n0) % p.n1, az = (agg / (p.n0 * p.n1)) % p.n2,
-              at = agg / (p.n0 * p.n1 * p.n2);
-    const int bx = bs % p.b0, by = (bs / p.b0) % p.b1, bz = (bs / (p.b0 * p.b1)) % p.b2,
-              bt = bs / (p.b0 * p.b1 * p.b2);
-    const int x = ax * p.b0 + bx, y = ay * p.b1 + by, z = az * p.b2 + bz, t = at * p.b3 + bt;
-    return x + p.L0 * (y + p.L1 * (z + p.L2 * t));
-}
-
 __device__ __forceinline__ double pwsum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -301,8 +266,13 @@ void prolong_fields(lqt_ctx* c, const lqt_basis* B, const double2* coarse, doubl
                                     (double)nrhs * 2 * p.nagg * p.nv));
 }
 
-// out_f = g5^W W^+ A W in_f (FP64), nf coarse vectors, in chunks that bound the fine memory
+// out_f = g5^W W^+ A W in_f (FP64), nf coarse vectors: with the explicit stencil when it has
+// been built, else prolong, Wilson operator, restrict, in chunks that bound the fine memory
 static void coarse_herm(lqt_ctx* c, const lqt_basis* B, const double2* in, double2* out, int nf) {
+    if (B->Dc.p) {
+        coarse_explicit_apply(c, B, in, out, nf, true);
+        return;
+    }
     const long long n = 12LL * c->g.V;
     const long long nc = 2LL * B->nagg * B->nv;
     const int chunk = (int)std::max<long long>(1, std::min<long long>(nf, (8LL << 30) / (2 * n * 16)));
@@ -460,6 +430,16 @@ int lqt_basis_prolongator(lqt_ctx* c, const int block[4], int nv, int k, double 
             hipLaunchKernelGGL(lqt::k_block_mgs, dim3(p.nagg * 2), dim3(256), 0, c->stream, B->W.as<double2>(), p);
             LQT_HIP(hipGetLastError());
             if (k > 0) {
+                // the coarse operator as an explicit 9-point block stencil (nv <= 32), which the
+                // eigensolver applies to its whole block at once
+                if (2 * nv <= 64) {
+                    lqt::coarse_explicit_build(c, B);
+                    if (o.verbose) {
+                        fprintf(stderr, "[lqtrace] prolongator: coarse operator W^+ A W built in %.2f s\n",
+                                B->coarse_build_s);
+                        fflush(stderr);
+                    }
+                }
                 // Algorithm 2, second step: k eigenpairs of g5^W W^+ A W with smallest |lambda|
                 lqt::HermOp H = [c, B](const double2* in, double2* o2, int nf) { lqt::coarse_herm(c, B, in, o2, nf); };
                 DBuf Qb;
@@ -486,6 +466,18 @@ int lqt_basis_prolongator(lqt_ctx* c, const int block[4], int nv, int k, double 
             throw;
         }
         *out = B;
+    });
+}
+
+int lqt_coarse_apply(lqt_ctx* c, lqt_basis* B, const double* d_in, double* d_out, int nrhs, int herm) {
+    if (!c || !B) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(B->kind == 1, LQT_EINVAL, "not a prolongator basis");
+        LQT_CHECK(nrhs >= 0 && (nrhs == 0 || (d_in && d_out)), LQT_EINVAL, "bad coarse apply arguments");
+        LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
+        lqt::coarse_explicit_build(c, B);
+        lqt::coarse_explicit_apply(c, B, (const double2*)d_in, (double2*)d_out, nrhs, herm != 0);
+        LQT_HIP(hipStreamSynchronize(c->stream));
     });
 }
 

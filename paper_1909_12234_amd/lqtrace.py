@@ -91,6 +91,7 @@ _SIGS = {
     "lqt_restrict": ([_P, _P, _P, _P, _I], _I),
     "lqt_prolong": ([_P, _P, _P, _P, _I], _I),
     "lqt_prolongator_get": ([_P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
+    "lqt_coarse_apply": ([_P, _P, _P, _P, _I, _I], _I),
     "lqt_basis_prolongator_from": ([_P, _P, _I, _P, _P, _I, ctypes.POINTER(_P)], _I),
     "lqt_tune": ([_P, _I, _I, ctypes.POINTER(_D), _P], _I),
     "lqt_set_tile": ([_P, _I, _I, _P], _I),
@@ -462,6 +463,16 @@ class Basis:
         nrhs = coarse.numel() // nc.value
         out = torch.empty((nrhs, self.ctx.N), dtype=torch.complex128, device="cuda")
         self.ctx._check(lib().lqt_prolong(self.ctx._h, self._h, _ptr(coarse), _ptr(out), nrhs))
+        return out
+
+    def coarse_apply(self, coarse, herm=False):
+        """W^+ A W (g5^W W^+ A W with herm) applied to coarse vectors by the explicit stencil."""
+        nc = ctypes.c_longlong(0)
+        self.ctx._check(lib().lqt_prolongator_get(self._h, None, ctypes.byref(nc)))
+        coarse = _dev(coarse, torch.complex128, nc.value, "coarse input")
+        out = torch.empty_like(coarse)
+        self.ctx._check(lib().lqt_coarse_apply(self.ctx._h, self._h, _ptr(coarse), _ptr(out),
+                                               coarse.numel() // nc.value, int(bool(herm))))
         return out
 
     def prolongator(self):
