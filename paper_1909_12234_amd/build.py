@@ -53,7 +53,8 @@ def build(jobs=None, verbose=False):
             if verbose and err.strip():
                 sys.stderr.write(err)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib",
+           "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"link failed:\n{p.stdout}\n{p.stderr}")

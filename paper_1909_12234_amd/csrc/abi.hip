@@ -5,6 +5,7 @@
 #include <new>
 
 #include "blas.h"
+#include "devla.h"
 #include "lqt_internal.h"
 #include "solver.h"
 
@@ -118,6 +119,7 @@ void lqt_destroy(lqt_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     c->timer.destroy();
+    lqt::blas_release(c);
     delete c;
 }
 

@@ -36,7 +36,7 @@ __constant__ double2 kGamma[4][16] = {
 
 constexpr int CB_MAXNB = 64;           // largest nb = 2 nv of the explicit operator
 constexpr int CB_OUT = 16;             // nb^2 / 256 outputs per thread at nb = 64
-constexpr int CA_R = 32;               // right-hand sides per workgroup of the apply
+constexpr int CA_R = 64;               // right-hand sides per workgroup of the apply (16 x 4)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -213,12 +213,13 @@ __global__ __launch_bounds__(256) void k_coarse_self(const double2* __restrict__
 
 // out[r][a] = sum_slot Dc[a][slot] in[r][nbr(a, slot)]  (g5^W applied to the result when
 // HERM); grid (nagg, ceil(nrhs / CA_R)).  The block D^T and the inputs of the slot are staged
-// in LDS; every thread owns outputs (i, r) with i fastest.
+// in LDS; thread t owns a micro-tile of up to 4 rows i (i = ib + 16 q, ib = t % 16) and 4
+// right-hand sides (r = rb + 16 w, rb = t / 16), so every LDS value read feeds 4 products.
 template <bool HERM>
 __global__ __launch_bounds__(256) void k_coarse_apply(const double2* __restrict__ Dc, PG p,
                                                       const double2* __restrict__ in, double2* __restrict__ out,
                                                       int nrhs) {
-    extern __shared__ double2 cl[];  // Dt[nb][nb], X[CA_R][nb]
+    extern __shared__ double2 cl[];  // Dt[nb][nb], X[CA_R][nb + 1] (padded against bank conflicts)
     const int a = blockIdx.x;
     const int r0 = blockIdx.y * CA_R;
     const int nr = min(CA_R, nrhs - r0);
@@ -227,10 +228,12 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const double2* __restrict_
     const long long nb2 = (long long)nb * nb;
     double2* Dt = cl;
     double2* X = cl + nb2;
-    constexpr int MAXO = (CB_MAXNB * CA_R) / 256;
-    double2 acc[MAXO];
+    const int ib = threadIdx.x & 15, rb = threadIdx.x >> 4;
+    double2 acc[4][4];
 #pragma unroll
-    for (int q = 0; q < MAXO; q++) acc[q] = make_double2(0, 0);
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int w = 0; w < 4; w++) acc[q][w] = make_double2(0, 0);
     for (int slot = 0; slot < 9; slot++) {
         const int b = agg_nbr(p, a, slot);
         __syncthreads();
@@ -241,31 +244,36 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const double2* __restrict_
         }
         for (int t = threadIdx.x; t < CA_R * nb; t += 256) {
             const int r = t / nb, j = t % nb;
-            X[t] = r < nr ? in[(long long)(r0 + r) * nc + (long long)b * nb + j] : make_double2(0, 0);
+            X[r * (nb + 1) + j] = r < nr ? in[(long long)(r0 + r) * nc + (long long)b * nb + j] : make_double2(0, 0);
         }
         __syncthreads();
+        for (int j = 0; j < nb; j++) {
+            double2 dv[4], xv[4];
 #pragma unroll
-        for (int q = 0; q < MAXO; q++) {
-            const int o = threadIdx.x + 256 * q;
-            if (o < nb * CA_R) {
-                const int i = o % nb, r = o / nb;
-                double2 s = acc[q];
-                for (int j = 0; j < nb; j++) {
-                    const double2 dd = Dt[j * nb + i], xx = X[r * nb + j];
-                    s.x += dd.x * xx.x - dd.y * xx.y;
-                    s.y += dd.x * xx.y + dd.y * xx.x;
-                }
-                acc[q] = s;
+            for (int q = 0; q < 4; q++) {
+                const int i = ib + 16 * q;
+                dv[q] = i < nb ? Dt[j * nb + i] : make_double2(0, 0);
             }
+#pragma unroll
+            for (int w = 0; w < 4; w++) xv[w] = X[(rb + 16 * w) * (nb + 1) + j];
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    acc[q][w].x = fma(dv[q].x, xv[w].x, fma(-dv[q].y, xv[w].y, acc[q][w].x));
+                    acc[q][w].y = fma(dv[q].x, xv[w].y, fma(dv[q].y, xv[w].x, acc[q][w].y));
+                }
         }
     }
 #pragma unroll
-    for (int q = 0; q < MAXO; q++) {
-        const int o = threadIdx.x + 256 * q;
-        if (o < nb * CA_R) {
-            const int i = o % nb, r = o / nb;
+    for (int q = 0; q < 4; q++) {
+        const int i = ib + 16 * q;
+        if (i >= nb) continue;
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            const int r = rb + 16 * w;
             if (r < nr) {
-                double2 v = acc[q];
+                double2 v = acc[q][w];
                 if (HERM && i >= nv) v = make_double2(-v.x, -v.y);
                 out[(long long)(r0 + r) * nc + (long long)a * nb + i] = v;
             }
@@ -299,13 +307,13 @@ void coarse_explicit_apply(lqt_ctx* c, const lqt_basis* B, const double2* in, do
     LQT_CHECK(B->Dc.p, LQT_ESTATE, "explicit coarse operator not built");
     PG p = pg_of(B);
     const int nb = 2 * p.nv;
-    const size_t lds = sizeof(double2) * ((size_t)nb * nb + (size_t)CA_R * nb);  // <= 96 KiB
+    const size_t lds = sizeof(double2) * ((size_t)nb * nb + (size_t)CA_R * (nb + 1));  // <= 129 KiB
     static bool lds_ok = false;  // allow more than 64 KiB of dynamic LDS per workgroup
     if (!lds_ok) {
         LQT_HIP(hipFuncSetAttribute((const void*)k_coarse_apply<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(96 * 1024)));
+                                    (int)(130 * 1024)));
         LQT_HIP(hipFuncSetAttribute((const void*)k_coarse_apply<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(96 * 1024)));
+                                    (int)(130 * 1024)));
         lds_ok = true;
     }
     dim3 grid(p.nagg, (nrhs + CA_R - 1) / CA_R);

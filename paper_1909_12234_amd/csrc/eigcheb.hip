@@ -23,6 +23,7 @@
 #include <cstdio>
 
 #include "blas.h"
+#include "devla.h"
 #include "eigcheb.h"
 #include "gemm.h"
 #include "hostla.h"
@@ -137,14 +138,16 @@ static void combine_h(lqt_ctx* c, const double2* X, int ka, const std::vector<zd
     LQT_HIP(hipStreamSynchronize(c->stream));
 }
 
-// X (nf vectors) <- an orthonormal basis of its span, two passes of Gram eigen-decomposition
-// (directions below 1e-13 of the largest dropped).  tmp: nf vectors.  Returns the rank.
+// X (nf vectors) <- an orthonormal basis of its span, two passes (Cholesky of the Gram
+// matrix, or its eigen-decomposition with directions below 1e-13 of the largest dropped when
+// the Cholesky meets a pivot below 1e-14 of the largest diagonal).  tmp: nf vectors.  Returns
+// the rank.
 static int orth_block(lqt_ctx* c, double2* X, int nf, double2* tmp, long long n) {
     int r = nf;
     for (int pass = 0; pass < 2; pass++) {
         std::vector<zd> G = gram_h(c, X, r, X, r, n);
         std::vector<zd> T;
-        const int r2 = orthonormalizer(r, G, T, 1e-13);
+        const int r2 = chol_inverse(r, G, T) ? r : orthonormalizer_any(c, r, G, T, 1e-13);
         combine_h(c, X, r, T, r2, tmp, n);
         LQT_HIP(hipMemcpyAsync(X, tmp, sizeof(double2) * (size_t)r2 * n, hipMemcpyDeviceToDevice, c->stream));
         r = r2;
@@ -263,12 +266,26 @@ int eig_chebyshev(lqt_ctx* c, long long n, const HermOp& H, const HermOp32* H32,
         napp += kk;
         std::vector<zd> G2 = gram_h(c, W, kk, W, kk, n);  // V^+ H^2 V
         std::vector<zd> G1 = gram_h(c, V, kk, W, kk, n);  // V^+ H V
-        // cut of the next filter: the largest Ritz value of H^2 in the block
+        // cut of the next filter: the largest Ritz value of H^2 in the block (power iteration
+        // on the positive semi-definite G2; 60 steps settle its largest eigenvalue well enough
+        // for a filter bound)
         {
-            std::vector<double> nu;
-            std::vector<zd> E;
-            heev(kk, G2, nu, E, false);
-            a = std::min(nu[kk - 1], 0.5 * b);
+            std::vector<zd> v(kk, zd(1.0)), w(kk);
+            double nu = 0;
+            for (int pit = 0; pit < 60; pit++) {
+                double nw = 0;
+                for (int i = 0; i < kk; i++) {
+                    zd sacc = 0;
+                    for (int l = 0; l < kk; l++) sacc += G2[(size_t)i * kk + l] * v[l];
+                    w[i] = sacc;
+                    nw += std::norm(sacc);
+                }
+                double nv2 = 0;
+                for (int i = 0; i < kk; i++) nv2 += std::norm(v[i]);
+                nu = std::sqrt(nw / nv2);
+                for (int i = 0; i < kk; i++) v[i] = w[i] / std::sqrt(nw);
+            }
+            a = std::min(nu, 0.5 * b);
         }
         // harmonic Ritz pairs with target 0: G1 y = (1/mu) G2 y  ->  T^+ G1 T z = mu z with
         // T^+ G2 T = 1 (Cholesky of G2), y = T z; |mu| descending = |theta| ascending
@@ -289,7 +306,7 @@ int eig_chebyshev(lqt_ctx* c, long long n, const HermOp& H, const HermOp32* H32,
             }
         std::vector<double> mu;
         std::vector<zd> Z;
-        heev(kk, K, mu, Z, true);  // ascending |mu|
+        heev_any(c, kk, K, mu, Z, true);  // ascending |mu|
         Y.assign((size_t)kk * kk, zd(0));
         for (int j = 0; j < kk; j++) {  // column j of Y: T z_(kk-1-j), |mu| descending
             const int src = kk - 1 - j;
@@ -361,7 +378,7 @@ int eig_chebyshev(lqt_ctx* c, long long n, const HermOp& H, const HermOp32* H32,
     std::vector<zd> M = gram_h(c, Q, k, W, k, n);
     std::vector<double> th;
     std::vector<zd> E;
-    heev(k, M, th, E, true);  // ascending |theta|
+    heev_any(c, k, M, th, E, true);  // ascending |theta|
     combine_h(c, Q, k, E, k, V, n);
     LQT_HIP(hipMemcpyAsync(Q, V, sizeof(double2) * (size_t)k * n, hipMemcpyDeviceToDevice, c->stream));
     H(Q, W, k);

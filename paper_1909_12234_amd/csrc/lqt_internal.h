@@ -346,6 +346,7 @@ struct lqt_ctx {
     hipStream_t capture_stream = nullptr;  // private stream for graph capture (created on demand)
     lqt::Net net;
     double sigma_max = 0;  // power-iteration estimate, filled on demand
+    void* blas = nullptr;  // rocBLAS handle of the dense setup eigenproblems (created on demand)
 };
 
 struct lqt_basis {

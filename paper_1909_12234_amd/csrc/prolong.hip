@@ -18,6 +18,7 @@
 #include "gemm.h"
 #include "hostla.h"
 #include "lqt_internal.h"
+#include "devla.h"
 #include "eigcheb.h"
 #include "prolong.h"
 #include "solver.h"
@@ -322,7 +323,7 @@ static void coarse_oblique_setup(lqt_ctx* c, lqt_basis* B, const double2* Ubar, 
     LQT_HIP(hipStreamSynchronize(c->stream));
     std::vector<double> lam;
     std::vector<zd> Uh;
-    heev(k, M, lam, Uh, true);
+    heev_any(c, k, M, lam, Uh, true);
     LQT_HIP(hipMemcpyAsync(Md.p, Uh.data(), sizeof(double2) * Uh.size(), hipMemcpyHostToDevice, c->stream));
     B->Uc.ensure(sizeof(double2) * (size_t)k * nc);
     gemm_combine(c, Ubar, k, Md.as<double2>(), k, 0.0, 1.0, B->Uc.as<double2>(), nc);

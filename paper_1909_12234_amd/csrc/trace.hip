@@ -25,6 +25,7 @@
 #include "gemm.h"
 #include "hostla.h"
 #include "lqt_internal.h"
+#include "devla.h"
 #include "eigcheb.h"
 #include "prolong.h"
 #include "solver.h"
@@ -69,7 +70,7 @@ static int orthonormalize(lqt_ctx* c, double2* X, int k, double2* tmp, long long
     for (int pass = 0; pass < 2; pass++) {
         std::vector<zd> G = gram_host(c, X, r, X, r, n);
         std::vector<zd> T;
-        int r2 = orthonormalizer(r, G, T, 1e-13);
+        int r2 = orthonormalizer_any(c, r, G, T, 1e-13);
         combine_host(c, X, r, T, r2, 0.0, 1.0, tmp, n);
         LQT_HIP(hipMemcpyAsync(X, tmp, sizeof(double2) * (size_t)r2 * n, hipMemcpyDeviceToDevice, c->stream));
         r = r2;
@@ -87,7 +88,7 @@ void fine_oblique_setup(lqt_ctx* c, lqt_basis* B, const double2* X, int k) {
     std::vector<zd> M = gram_host(c, X, k, AX.as<double2>(), k);
     std::vector<double> lam;
     std::vector<zd> Uh;
-    heev(k, M, lam, Uh, true);
+    heev_any(c, k, M, lam, Uh, true);
     B->U.ensure(sizeof(double2) * (size_t)k * n);
     combine_host(c, X, k, Uh, k, 0.0, 1.0, B->U.as<double2>());
     LQT_HIP(hipMemcpyAsync(AX.p, B->U.p, sizeof(double2) * (size_t)k * n, hipMemcpyDeviceToDevice, c->stream));

@@ -34,23 +34,33 @@ def test_roofline_takes_the_dominant_family_against_hbm():
 
 
 def test_recorded_traffic_is_used_only_for_its_source_and_tile(tmp_path, monkeypatch):
-    with open(os.path.join(ROOT, "paper_1909_12234_amd", "traffic.json")) as f:
-        recs = json.load(f)["kernels"]["dslash"]
-    rec = recs[0]
-    tile = tuple(rec["tile"])
-    assert bench._measured_traffic("dslash", tile) == rec["fetch_bytes"] + rec["write_bytes"]
+    import hashlib
+
+    pkg = tmp_path / "paper_1909_12234_amd"
+    (pkg / "csrc").mkdir(parents=True)
+    src = b"// kernel source\n"
+    (pkg / "csrc" / "k.hip").write_bytes(src)
+    rec = {"source": "csrc/k.hip", "sha256_16": hashlib.sha256(src).hexdigest()[:16],
+           "tile": [2, 256, 64, 3], "fetch_bytes": 1000, "write_bytes": 24}
+    other = dict(rec, tile=[2, 256, 64, 2], fetch_bytes=5)
+    (pkg / "traffic.json").write_text(json.dumps({"kernels": {"dslash": [rec, other]}}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench._measured_traffic("dslash", (2, 256, 64, 3)) == 1024
+    assert bench._measured_traffic("dslash", (2, 256, 64, 2)) == 29
     assert bench._measured_traffic("dslash", (7, 7, 7, 7)) is None
     assert bench._measured_traffic("no_such_kernel") is None
     # a kernel source that differs from the recorded hash voids the record
-    pkg = tmp_path / "paper_1909_12234_amd"
-    (pkg / "csrc").mkdir(parents=True)
-    shutil.copy(os.path.join(ROOT, "paper_1909_12234_amd", "traffic.json"), pkg / "traffic.json")
-    src = open(os.path.join(ROOT, "paper_1909_12234_amd", rec["source"]), "rb").read()
-    (pkg / rec["source"]).write_bytes(src)
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench._measured_traffic("dslash", tile) == rec["fetch_bytes"] + rec["write_bytes"]
-    (pkg / rec["source"]).write_bytes(src + b"\n// edited\n")
-    assert bench._measured_traffic("dslash", tile) is None
+    (pkg / "csrc" / "k.hip").write_bytes(src + b"// edited\n")
+    assert bench._measured_traffic("dslash", (2, 256, 64, 3)) is None
+
+
+def test_committed_traffic_records_are_well_formed():
+    with open(os.path.join(ROOT, "paper_1909_12234_amd", "traffic.json")) as f:
+        recs = json.load(f)["kernels"]["dslash"]
+    for rec in recs:
+        assert os.path.exists(os.path.join(ROOT, "paper_1909_12234_amd", rec["source"]))
+        assert len(rec["tile"]) == 4 and rec["fetch_bytes"] > 0 and rec["write_bytes"] > 0
+        assert len(rec["sha256_16"]) == 16
 
 
 def test_more_than_one_gpu_exits_before_touching_a_device():

@@ -46,7 +46,7 @@ def test_explicit_coarse_operator_matches_oracle(gpu, dims, block, nv, m):
     c.set_gauge(U)
     B = c.basis_prolongator_from(block, nv, torch.as_tensor(W.reshape(-1)).cuda())
     rng = np.random.default_rng(9)
-    x = rng.standard_normal((37, nc)) + 1j * rng.standard_normal((37, nc))
+    x = rng.standard_normal((70, nc)) + 1j * rng.standard_normal((70, nc))
     y = B.coarse_apply(torch.as_tensor(x).cuda()).cpu().numpy()
     ref = (Dc @ x.T).T
     assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
