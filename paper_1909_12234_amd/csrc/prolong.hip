@@ -115,13 +115,9 @@ __global__ __launch_bounds__(256) void k_block_mgs(double2* __restrict__ W, PG p
 // ---------------------------------------------------------------- restrict / prolong
 constexpr int RB = 8;  // right-hand sides per workgroup: each W entry is read once per RB
 
-// coarse[r][(a*2 + c)*nv + v] = sum_e conj(W[a][c][v][e]) y_r(e); grid (nagg*2, ceil(nrhs/RB)).
-// PROBES: y_r is the Rademacher probe j0 + r, and the result goes to out_up (c = 0) or
-// out_dn (c = 1) with zeros in the other.
-template <bool PROBES>
+// coarse[r][(a*2 + c)*nv + v] = sum_e conj(W[a][c][v][e]) y_r(e); grid (nagg*2, ceil(nrhs/RB))
 __global__ __launch_bounds__(256) void k_restrict(const double2* __restrict__ W, PG p, const double2* __restrict__ y,
-                                                  int nrhs, uint64_t seed, long long j0, double2* __restrict__ out,
-                                                  double2* __restrict__ out_dn) {
+                                                  int nrhs, double2* __restrict__ out) {
     extern __shared__ double lds[];  // [nv][RB][4 waves][2]
     const int blk = blockIdx.x, agg = blk >> 1, ch = blk & 1;
     const int r0 = blockIdx.y * RB;
@@ -138,18 +134,10 @@ __global__ __launch_bounds__(256) void k_restrict(const double2* __restrict__ W,
             const int bs = e / 6, s2 = (e % 6) / 3, col = e % 3;
             const int comp = (2 * ch + s2) * 3 + col;
             const int site = site_of(p, agg, bs);
-            uint64_t hi = 0;
-            if (PROBES) hi = psm64((uint64_t)(12LL * site + comp));
 #pragma unroll
             for (int r = 0; r < RB; r++) {
                 if (r < nr) {
-                    double2 yv;
-                    if (PROBES) {
-                        double z = (psm64(seed ^ psm64((uint64_t)(j0 + r0 + r) ^ hi)) >> 63) ? -1.0 : 1.0;
-                        yv = make_double2(z, 0.0);
-                    } else {
-                        yv = y[(long long)(r0 + r) * n + (long long)comp * p.V + site];
-                    }
+                    const double2 yv = y[(long long)(r0 + r) * n + (long long)comp * p.V + site];
                     ar[r] += w.x * yv.x + w.y * yv.y;
                     ai[r] += w.x * yv.y - w.y * yv.x;
                 }
@@ -174,12 +162,66 @@ __global__ __launch_bounds__(256) void k_restrict(const double2* __restrict__ W,
             a += lds[((v * RB + r) * 4 + w) * 2];
             b += lds[((v * RB + r) * 4 + w) * 2 + 1];
         }
-        const long long o = (long long)(r0 + r) * nc + (long long)blk * p.nv + v;
-        if (PROBES) {
-            out[o] = ch == 0 ? make_double2(a, b) : make_double2(0, 0);
+        out[(long long)(r0 + r) * nc + (long long)blk * p.nv + v] = make_double2(a, b);
+    }
+}
+
+// Restriction of Rademacher probes for the deflation projections (Algorithm 2, last step):
+// out_up / out_dn [r][(a*2 + c)*nv + v] = sum_e conj(W[a][c][v][e]) z_r(e) for the block of
+// chirality c (zero in the other array), z_r the probe j0 + r.  One workgroup per (block, RBP
+// probes); thread (r = t mod RBP, q = t / RBP) sums the entries e = q (mod 256 / RBP) of a tile
+// for probe r.  A tile's signs are hashed once into LDS as bit masks (bit r set: z_r(e) = -1)
+// and each row of W is staged in LDS, so W streams from HBM once per RBP probes and the real
+// +-1 probe turns the products into signed additions.
+constexpr int RBP = 32;
+constexpr int RP_TILE = 1536;  // W row entries per tile (one chirality half of a 4^4 block)
+
+__global__ __launch_bounds__(256) void k_restrict_probes(const double2* __restrict__ W, PG p, int nrhs, uint64_t seed,
+                                                         long long j0, double2* __restrict__ out_up,
+                                                         double2* __restrict__ out_dn) {
+    __shared__ uint32_t sg[RP_TILE];
+    __shared__ double2 row[RP_TILE];
+    __shared__ double2 red[256 / RBP][RBP];
+    const int blk = blockIdx.x, agg = blk >> 1, ch = blk & 1;
+    const int r0 = blockIdx.y * RBP;
+    const int nr = min(RBP, nrhs - r0);
+    const int r = threadIdx.x % RBP, q = threadIdx.x / RBP;
+    const double2* Wb = W + (long long)blk * p.nv * p.d;
+    const long long nc = 2LL * p.nagg * p.nv;
+    const int ntiles = (p.d + RP_TILE - 1) / RP_TILE;
+    for (int v = 0; v < p.nv; v++) {
+        double ar = 0, ai = 0;
+        for (int tl = 0; tl < ntiles; tl++) {
+            const int e0 = tl * RP_TILE, ne = min(RP_TILE, p.d - e0);
+            __syncthreads();  // readers of the previous tile and of red are done
+            if (v == 0 || ntiles > 1) {
+                for (int e = threadIdx.x; e < ne; e += 256) {
+                    const int ee = e0 + e;
+                    const int bs = ee / 6, s2 = (ee % 6) / 3, col = ee % 3;
+                    const uint64_t hi = psm64((uint64_t)(12LL * site_of(p, agg, bs) + (2 * ch + s2) * 3 + col));
+                    uint32_t bits = 0;
+                    for (int rr = 0; rr < nr; rr++)
+                        bits |= (uint32_t)(psm64(seed ^ psm64((uint64_t)(j0 + r0 + rr) ^ hi)) >> 63) << rr;
+                    sg[e] = bits;
+                }
+            }
+            for (int e = threadIdx.x; e < ne; e += 256) row[e] = Wb[(long long)v * p.d + e0 + e];
+            __syncthreads();
+            for (int e = q; e < ne; e += 256 / RBP) {
+                const double2 w = row[e];
+                const bool neg = (sg[e] >> r) & 1u;
+                ar += neg ? -w.x : w.x;  // Re conj(w) z
+                ai += neg ? w.y : -w.y;  // Im conj(w) z
+            }
+        }
+        red[q][r] = make_double2(ar, ai);
+        __syncthreads();
+        if (threadIdx.x < nr) {
+            double a = 0, b = 0;
+            for (int qq = 0; qq < 256 / RBP; qq++) a += red[qq][threadIdx.x].x, b += red[qq][threadIdx.x].y;
+            const long long o = (long long)(r0 + threadIdx.x) * nc + (long long)blk * p.nv + v;
+            out_up[o] = ch == 0 ? make_double2(a, b) : make_double2(0, 0);
             out_dn[o] = ch == 1 ? make_double2(a, b) : make_double2(0, 0);
-        } else {
-            out[o] = make_double2(a, b);
         }
     }
 }
@@ -248,11 +290,10 @@ void restrict_fields(lqt_ctx* c, const lqt_basis* B, const double2* fine, double
     dim3 grid(p.nagg * 2, (nrhs + RB - 1) / RB);
     size_t lds = sizeof(double) * p.nv * RB * 4 * 2;
     c->timer.begin(c->stream, KT_PR);
-    hipLaunchKernelGGL((k_restrict<false>), grid, dim3(256), lds, c->stream, B->W.as<double2>(), p, fine, nrhs, 0ull,
-                       0ll, coarse, (double2*)nullptr);
+    hipLaunchKernelGGL(k_restrict, grid, dim3(256), lds, c->stream, B->W.as<double2>(), p, fine, nrhs, coarse);
     LQT_HIP(hipGetLastError());
-    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V * grid.y + (double)nrhs * 12 * p.V +
-                                    (double)nrhs * 2 * p.nagg * p.nv));
+    // algorithmic bytes: W once, the fine and the coarse fields once each
+    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V + (double)nrhs * 12 * p.V + (double)nrhs * 2 * p.nagg * p.nv));
 }
 
 void prolong_fields(lqt_ctx* c, const lqt_basis* B, const double2* coarse, double2* fine, int nrhs) {
@@ -263,8 +304,8 @@ void prolong_fields(lqt_ctx* c, const lqt_basis* B, const double2* coarse, doubl
     c->timer.begin(c->stream, KT_PR);
     hipLaunchKernelGGL(k_prolong, grid, dim3(256), lds, c->stream, B->W.as<double2>(), p, coarse, nrhs, fine);
     LQT_HIP(hipGetLastError());
-    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V * grid.y + (double)nrhs * 12 * p.V +
-                                    (double)nrhs * 2 * p.nagg * p.nv));
+    // algorithmic bytes: W once, the fine and the coarse fields once each
+    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V + (double)nrhs * 12 * p.V + (double)nrhs * 2 * p.nagg * p.nv));
 }
 
 // out_f = g5^W W^+ A W in_f (FP64), nf coarse vectors: with the explicit stencil when it has
@@ -298,13 +339,12 @@ void prolong_project_probes(lqt_ctx* c, const lqt_basis* B, uint64_t seed, long 
     rz.ensure(sizeof(double2) * (size_t)s * nc * 2);
     double2* up = rz.as<double2>();
     double2* dn = up + (size_t)s * nc;
-    dim3 grid(p.nagg * 2, (s + RB - 1) / RB);
-    size_t lds = sizeof(double) * p.nv * RB * 4 * 2;
+    dim3 grid(p.nagg * 2, (s + RBP - 1) / RBP);
     c->timer.begin(c->stream, KT_PR);
-    hipLaunchKernelGGL((k_restrict<true>), grid, dim3(256), lds, c->stream, B->W.as<double2>(), p,
-                       (const double2*)nullptr, s, seed, j0, up, dn);
+    hipLaunchKernelGGL(k_restrict_probes, grid, dim3(256), 0, c->stream, B->W.as<double2>(), p, s, seed, j0, up, dn);
     LQT_HIP(hipGetLastError());
-    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V * grid.y + 2.0 * s * nc));
+    // algorithmic bytes: W once, both coarse outputs
+    c->timer.end(c->stream, 16.0 * ((double)p.nv * 12 * p.V + 2.0 * s * nc));
     gemm_gram(c, B->Uc.as<double2>(), B->k, up, s, cup, nc);
     gemm_gram(c, B->Uc.as<double2>(), B->k, dn, s, cdn, nc);
 }

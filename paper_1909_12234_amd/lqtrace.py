@@ -329,13 +329,22 @@ class Context:
         b.converged = rc == 0
         return b
 
-    def basis_prolongator(self, block, nv, k, null_xi=1e-2, null_maxit=200, **opts):
+    def basis_prolongator(self, block, nv, k, null_xi=1e-2, null_maxit=200, require_converged=False, **opts):
+        """Algorithm 2's basis: W from nv near-null vectors per chirality on the aggregates of
+        `block`, then the k smallest-|lambda| coarse eigenvectors.  A basis whose coarse pairs
+        did not all meet the residual criterion is still returned (basis.converged = False)
+        unless required."""
         h = ctypes.c_void_p()
         o = _opts(**opts)
         b = (ctypes.c_int * 4)(*block)
-        self._check(lib().lqt_basis_prolongator(self._h, b, int(nv), int(k), float(null_xi), int(null_maxit),
-                                                ctypes.byref(o), ctypes.byref(h)))
-        return Basis(self, h, nv=nv)
+        rc = lib().lqt_basis_prolongator(self._h, b, int(nv), int(k), float(null_xi), int(null_maxit),
+                                         ctypes.byref(o), ctypes.byref(h))
+        self._check(rc, allow=() if require_converged else (LQT_ENOTCONV,))
+        if not h:
+            raise LqtError(rc, lib().lqt_last_error(self._h).decode())
+        bas = Basis(self, h, nv=nv)
+        bas.converged = rc == 0
+        return bas
 
     def basis_prolongator_from(self, block, nv, W, coarse=None):
         h = ctypes.c_void_p()

@@ -28,9 +28,12 @@ WORKLOADS = {
     # Gaussian field at 1e-2, r = A e) in 4 epochs
     "wilson16x32_net": dict(dims=(16, 16, 16, 32), eps=0.5, seed=1, mass=-1.90, nprobes=256, probe_seed=1003,
                             xi=1e-8, inner_prec="bf16", train_pairs=1024, train_epochs=4, pair_xi=1e-2),
-    # 32^3x64 prolongator deflation, 4^4 aggregates, 24 null vectors per chirality, k = 256
+    # 32^3x64 prolongator deflation (Algorithm 2): 4^4 aggregates, 24 near-null vectors per
+    # chirality (FP16 s-step solves to 1e-2 or 200 steps), explicit coarse operator, k = 256
+    # coarse eigenvectors; 256 probes solved 32 at a time with the 16^3x32 workload's solver
     "wilson32x64_mg": dict(dims=(32, 32, 32, 64), eps=0.5, seed=1, mass=-1.90, nprobes=256, probe_seed=1004,
-                           xi=1e-8, block=(4, 4, 4, 4), nv=24, k=256, inner_prec="bf16"),
+                           xi=1e-8, block=(4, 4, 4, 4), nv=24, k=256, inner_prec="f16", restart=15, sstep=1,
+                           batch=32),
 }
 
 PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}

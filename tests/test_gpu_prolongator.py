@@ -88,7 +88,7 @@ def test_prolongator_basis_from_near_null_vectors(gpu):
     Ai = np.linalg.inv(A)
     c = lq.Context(dims, m)
     c.set_gauge(U)
-    B = c.basis_prolongator(block, nv, k, null_xi=1e-2, null_maxit=200)
+    B = c.basis_prolongator(block, nv, k, null_xi=1e-2, null_maxit=200, require_converged=True)
     W = B.prolongator().cpu().numpy().reshape(-1, 2, nv, 6 * 16)
     for a in range(W.shape[0]):  # orthonormal blocks
         for ch in range(2):
@@ -123,7 +123,7 @@ def test_coarse_eigensolver_returns_smallest_pairs(gpu):
     A = dense.dense_operator(U, dims, m)
     c = lq.Context(dims, m)
     c.set_gauge(U)
-    B = c.basis_prolongator(block, nv, k, null_xi=1e-2, null_maxit=200, eig_xi=1e-9, outer_maxit=200)
+    B = c.basis_prolongator(block, nv, k, null_xi=1e-2, null_maxit=200, require_converged=True, eig_xi=1e-9, outer_maxit=200)
     W = B.prolongator().cpu().numpy().reshape(-1, 2, nv, 6 * 16)
     P = pr.dense_prolongator(W, dims, block)
     g5c = pr.coarse_g5(W.shape[0], nv)
@@ -134,3 +134,34 @@ def test_coarse_eigensolver_returns_smallest_pairs(gpu):
     print(f"coarse ||R|| {r2:.2e} sin angle {sin:.2e} gap {delta:.2e}", flush=True)
     B.close()
     c.close()
+
+
+@pytest.mark.parametrize("dims,block,nv,s", [((8, 8, 8, 8), (8, 4, 4, 4), 3, 37), ((4, 4, 4, 8), (4, 4, 2, 2), 4, 70)])
+def test_deflation_corrections_match_oracle(gpu, dims, block, nv, s):
+    """The deflation corrections of Algorithm 2's estimator (undeflated minus deflated samples
+    of the same probes, whose solves are bitwise identical) against the oracle on X = W U_bar,
+    for blocks with more entries than one tile of the probe restriction (8 x 4 x 4 x 4 sites:
+    3072 entries per chirality) and more probes than one workgroup restricts (32)."""
+    lq = gpu
+    m, seed = 0.2, 1011
+    print(f"Algorithm 2 corrections dims={dims} block={block} nv={nv} probes={s}", flush=True)
+    U = synth.su3_links(dims, 0.3, 2)
+    W = _W(dims, block, nv)
+    nc = W.shape[0] * 2 * nv
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.standard_normal((nc, 5)) + 1j * rng.standard_normal((nc, 5)))
+    Ubar = Q.T.copy()
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    B = c.basis_prolongator_from(block, nv, torch.as_tensor(W.reshape(-1)).cuda(), torch.as_tensor(Ubar).cuda())
+    r0 = c.trace(s, seed, 1e-10, samples=True)
+    rB = c.trace(s, seed, 1e-10, basis=B, samples=True)
+    B.close()
+    c.close()
+    X = pr.prolong(W, Ubar, dims, block)
+    Uo, lam, ug5u, t0 = estimator.oblique_setup(X, core.apply(U, dims, m, core.OP_A, X))
+    assert abs(complex(rB["t0_re"], rB["t0_im"]) - t0) <= 1e-9 * abs(t0)
+    Z = core.probes(seed, s, X.shape[1])
+    corr = estimator.oblique_corrections(Z, Uo, lam)
+    corr_gpu = r0["samples"].numpy() - rB["samples"].numpy()
+    assert np.max(np.abs(corr_gpu - corr)) <= 1e-9 * np.max(np.abs(corr)) + 1e-9 * np.max(np.abs(r0["samples"].numpy()))
