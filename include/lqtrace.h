@@ -310,6 +310,29 @@ int lqt_trace(lqt_ctx *ctx, const lqt_basis *basis, int projector, int nprobes, 
               double xi, const lqt_solver_opts *opts, lqt_trace_result *out,
               double *h_rank_curve, double *h_samples);
 
+/* lqt_trace with the partition basis H of Algorithms 1 and 2 (Section 1: spin-colour
+ * dilution and hierarchical probing; lqt_trace is hp_vectors = 1, dilute = 0).  Draw j
+ * solves the q = hp_vectors * (dilute ? 12 : 1) real vectors
+ *   v_{j,m,c} = z_j (.) h_m (.) e_c,   m < hp_vectors, c < 12 (dilute) or e_c = 1,
+ * z_j the Rademacher probe of lqt_trace, e_c the indicator of spin-colour component
+ * c = 3 spin + colour at every site, and h_m(x) = (-1)^{sum over the set bits beta of m of
+ * f_beta(x)} with the nested bit functions of level l = beta / 4 on the coordinate bits
+ * x_l = (x >> l) & 1:  f_{4l} = x_l + y_l + z_l + t_l (mod 2), f_{4l+1} = x_l,
+ * f_{4l+2} = y_l, f_{4l+3} = z_l.  At the closing colours hp_vectors = 2^{4i} the probing
+ * separates every pair of sites that differ modulo 2^i in some direction (hp_vectors = 2:
+ * the red-black partition).  The sample of draw j is
+ *   t_j = (1/hp_vectors) sum_{m,c} [v^T y_v - (v^T U) Lambda^{-1} (U^+ g5 v)]   (oblique)
+ * with y_v = A^{-1}_xi v (the orthogonal projector solves on (1 - U U^+) v instead), an
+ * unbiased estimate of the trace of the deflated inverse; t0, the statistics over the
+ * nprobes draws and the rank curve are as in lqt_trace.  nsolves and nfailed count the
+ * nprobes * q solves.  hp_vectors must be a power of two (at most 2^20), and every
+ * extent a multiple of 2^{l+1} for the highest level l in use (LQT_EINVAL otherwise);
+ * single-lattice contexts only. */
+int lqt_trace_probing(lqt_ctx *ctx, const lqt_basis *basis, int projector, int nprobes,
+                      uint64_t seed, double xi, int hp_vectors, int dilute,
+                      const lqt_solver_opts *opts, lqt_trace_result *out, double *h_rank_curve,
+                      double *h_samples);
+
 /* Undeflated Hutchinson estimates of trace(A_k^{-1}), one per lattice of the context (Eq. 1;
  * the same probes and solves as lqt_trace, the samples split by lattice): res receives nlat
  * results, samples (may be NULL) 2*nlat*nprobes doubles [lattice][probe] (re, im).  nsolves,

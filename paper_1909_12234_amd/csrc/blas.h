@@ -7,6 +7,9 @@ namespace lqt {
 void norm2_fields(lqt_ctx* c, const double2* x, int nf, double* out_dev);
 void dot_fields(lqt_ctx* c, const double2* x, const double2* y, int nf, double2* out_dev);
 void probes_gen(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double2* out);
+// partition probe vectors p0 .. p0+nvec-1 (hp probing signs, dilution into the 12
+// spin-colour components when dilute) of a single-lattice context
+void partition_probes_gen(lqt_ctx* c, uint64_t seed, long long p0, int nvec, int hp, int dilute, double2* out);
 // z_j^T y_j for nprobes fields; per_lattice: out_dev[j * nlat + k] over the sites of lattice k
 void probe_dots(lqt_ctx* c, uint64_t seed, long long j0, const double2* y, int nprobes, double2* out_dev,
                 bool per_lattice = false);

@@ -86,6 +86,53 @@ void probes_gen(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double2* o
     LQT_HIP(hipGetLastError());
 }
 
+// Partition probes (the partition basis H of Algorithms 1 and 2: spin-colour dilution and
+// hierarchical probing, Section 1).  Vector p = j q + m nd + cc (q = hp nd vectors per draw,
+// nd = 12 with dilution, else 1) is the Rademacher probe j times the probing sign h_m of
+// each site, restricted to spin-colour component cc when diluting.  h_m(x) is -1 to the sum
+// over the set bits beta of m of f_beta(x), with the nested bit functions of level
+// l = beta / 4 on the coordinate bits x_l = (x >> l) & 1:
+//   f_{4l} = x_l + y_l + z_l + t_l (red-black at level l), f_{4l+1} = x_l, f_{4l+2} = y_l,
+//   f_{4l+3} = z_l,
+// so the first 2^{4i} signs span the indicators of the sites congruent modulo 2^i in every
+// direction (the closing colours).
+__device__ __forceinline__ int hp_parity(uint32_t m, int x, int y, int z, int t) {
+    int par = 0;
+    for (int beta = 0; (m >> beta) != 0u; beta++) {
+        if (!((m >> beta) & 1u)) continue;
+        const int l = beta >> 2;
+        const int xl = (x >> l) & 1, yl = (y >> l) & 1, zl = (z >> l) & 1, tl = (t >> l) & 1;
+        const int w = beta & 3;
+        par += w == 0 ? xl + yl + zl + tl : (w == 1 ? xl : (w == 2 ? yl : zl));
+    }
+    return par & 1;
+}
+
+__global__ __launch_bounds__(256) void k_partition_probe_gen(uint64_t seed, long long p0, int hp, int nd, int L0,
+                                                             int L1, int L2, int V, double2* __restrict__ out) {
+    const int f = blockIdx.y, s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= V) return;
+    const long long p = p0 + f;
+    const int q = hp * nd;
+    const long long j = p / q;
+    const int r = (int)(p % q), m = r / nd, cc = r % nd;
+    const int x = s % L0, y = (s / L0) % L1, z = (s / (L0 * L1)) % L2, t = s / (L0 * L1 * L2);
+    const double sg = hp_parity((uint32_t)m, x, y, z, t) ? -1.0 : 1.0;
+    const long long n = 12LL * V;
+#pragma unroll
+    for (int c = 0; c < 12; c++)
+        out[f * n + (long long)c * V + s] =
+            make_double2((nd == 1 || c == cc) ? sg * probe_entry(seed, (uint64_t)j, (uint64_t)(12LL * s + c)) : 0.0, 0.0);
+}
+
+void partition_probes_gen(lqt_ctx* c, uint64_t seed, long long p0, int nvec, int hp, int dilute, double2* out) {
+    if (nvec <= 0) return;
+    LQT_CHECK(nvec <= 65535, LQT_EINVAL, "partition probes: at most 65535 vectors per launch");
+    hipLaunchKernelGGL(k_partition_probe_gen, dim3((c->g.V + 255) / 256, nvec), dim3(256), 0, c->stream, seed, p0, hp,
+                       dilute ? 12 : 1, c->g.L[0], c->g.L[1], c->g.L[2], c->g.V, out);
+    LQT_HIP(hipGetLastError());
+}
+
 // partial sums of z_j^T y_j (complex) per (block, probe): y device layout FP64
 __global__ __launch_bounds__(256) void k_probe_dot_part(uint64_t seed, long long j0, const double2* __restrict__ y,
                                                         LatTab t, double2* __restrict__ part) {

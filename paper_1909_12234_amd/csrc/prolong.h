@@ -51,6 +51,8 @@ void prolong_project_probes(lqt_ctx* c, const lqt_basis* B, uint64_t seed, long 
                             double2* cdn);
 // coarse = W^+ fine and fine = W coarse for nrhs fields (fine: device layout FP64)
 void restrict_fields(lqt_ctx* c, const lqt_basis* B, const double2* fine, double2* coarse, int nrhs);
+// cm = U_c^+ W^+ Z, cg = U_c^+ g5^W W^+ Z for s fine fields (k x s, device)
+void prolong_project_fields(lqt_ctx* c, const lqt_basis* B, const double2* Z, int s, double2* cm, double2* cg);
 void prolong_fields(lqt_ctx* c, const lqt_basis* B, const double2* coarse, double2* fine, int nrhs);
 
 }  // namespace lqt

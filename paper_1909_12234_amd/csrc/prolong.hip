@@ -349,6 +349,21 @@ void prolong_project_probes(lqt_ctx* c, const lqt_basis* B, uint64_t seed, long 
     gemm_gram(c, B->Uc.as<double2>(), B->k, dn, s, cdn, nc);
 }
 
+// cm = U_c^+ W^+ Z and cg = U_c^+ g5^W W^+ Z (= u_i^+ g5 z for the chirality-split W) for s
+// fine fields Z, k x s each (device)
+void prolong_project_fields(lqt_ctx* c, const lqt_basis* B, const double2* Z, int s, double2* cm, double2* cg) {
+    PG p = pg_of(B);
+    const long long nc = 2LL * p.nagg * p.nv;
+    DBuf rz;
+    rz.ensure(sizeof(double2) * (size_t)s * nc);
+    restrict_fields(c, B, Z, rz.as<double2>(), s);
+    gemm_gram(c, B->Uc.as<double2>(), B->k, rz.as<double2>(), s, cm, nc);
+    const long long tot = nc * s;
+    hipLaunchKernelGGL(k_g5c, g1(tot), dim3(256), 0, c->stream, rz.as<double2>(), nc, p.nv, tot);
+    LQT_HIP(hipGetLastError());
+    gemm_gram(c, B->Uc.as<double2>(), B->k, rz.as<double2>(), s, cg, nc);
+}
+
 // Coarse oblique data from coarse vectors Ubar (k, device): M = Ubar^+ g5^W W^+ A W Ubar,
 // eigh, Uc = Ubar U_hat, u_i^+ g5 u_i = Uc_i^+ g5^W Uc_i.
 static void coarse_oblique_setup(lqt_ctx* c, lqt_basis* B, const double2* Ubar, int k) {

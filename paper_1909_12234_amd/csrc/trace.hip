@@ -392,6 +392,12 @@ int lqt_trace_lattices(lqt_ctx* c, int nprobes, uint64_t seed, double xi, const 
 
 int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64_t seed, double xi,
               const lqt_solver_opts* opts, lqt_trace_result* res, double* rank_curve, double* samples) {
+    return lqt_trace_probing(c, B, projector, nprobes, seed, xi, 1, 0, opts, res, rank_curve, samples);
+}
+
+int lqt_trace_probing(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64_t seed, double xi,
+                      int hp_vectors, int dilute, const lqt_solver_opts* opts, lqt_trace_result* res,
+                      double* rank_curve, double* samples) {
     if (!c) return LQT_EINVAL;
     int nfail_total = 0;
     int rc = guard(c, [&] {
@@ -400,6 +406,21 @@ int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64
         LQT_CHECK(nprobes >= 1, LQT_EINVAL, "nprobes must be >= 1");
         LQT_CHECK(xi > 0 && xi < 1, LQT_EINVAL, "xi must be in (0, 1)");
         LQT_CHECK(projector == LQT_OBLIQUE_G5 || projector == LQT_ORTH, LQT_EINVAL, "bad projector");
+        LQT_CHECK(dilute == 0 || dilute == 1, LQT_EINVAL, "dilute must be 0 or 1");
+        LQT_CHECK(hp_vectors >= 1 && hp_vectors <= (1 << 20) && !(hp_vectors & (hp_vectors - 1)), LQT_EINVAL,
+                  "hp_vectors must be a power of two (1 = no probing)");
+        {
+            // the highest level l of the nested colourings needs extents divisible by 2^(l+1)
+            int b = 0;
+            while ((1 << b) < hp_vectors) b++;
+            if (b > 0) {
+                const int m = 2 << ((b - 1) / 4);
+                for (int d = 0; d < 4; d++)
+                    LQT_CHECK(c->g.L[d] % m == 0, LQT_EINVAL,
+                              std::to_string(hp_vectors) + " probing vectors need extents divisible by " +
+                                  std::to_string(m));
+            }
+        }
         LQT_CHECK(!B || B->ctx == c, LQT_EINVAL, "basis belongs to another context");
         LQT_CHECK(!(B && projector == LQT_ORTH && (!B->orthonormal || B->kind != 0)), LQT_EINVAL,
                   "the orthogonal projector needs an orthonormal fine basis (lqt_basis_eig)");
@@ -409,63 +430,103 @@ int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64
         const long long n = 12LL * c->g.V;
         const int k = B ? B->k : 0;
         const int s = nprobes;
-        // probe chunk: the caller's batch, else what fits (Z and Y FP64 + the Krylov basis)
+        // solves per draw: the probing vectors, each split into the 12 components with dilution
+        const int nd = dilute ? 12 : 1;
+        const int q = hp_vectors * nd;
+        const bool part = q > 1;
+        LQT_CHECK((long long)s * q <= (1LL << 31) - 1, LQT_EINVAL, "too many probe vectors");
+        const int nvec = s * q;
+        // vector chunk: the caller's batch, else what fits (Z and Y FP64 + the Krylov basis)
         size_t fr = 0, tot = 0;
         LQT_HIP(hipMemGetInfo(&fr, &tot));
         size_t per = (size_t)n * 16 * 2 + (size_t)(o.restart + 1) * n * lqt::storage_bytes(o.prec) + (size_t)n * 32;
         if (o.use_net) per += (size_t)o.restart * n * lqt::storage_bytes(o.prec);
         int fit = (int)std::max<size_t>(1, (size_t)(0.6 * (double)(fr + c->scratch[0].n + c->scratch[10].n +
                                                                      c->scratch[11].n)) / per);
-        int chunk = std::min(s, o.max_batch > 0 ? o.max_batch : s);
-        chunk = std::max(1, std::min(chunk, fit));
+        int chunk = std::min(nvec, o.max_batch > 0 ? o.max_batch : nvec);
+        chunk = std::max(1, std::min({chunk, fit, 65535}));
         c->scratch[10].ensure(sizeof(double2) * (size_t)chunk * n);
         c->scratch[11].ensure(sizeof(double2) * (size_t)chunk * n);
         double2* Z = c->scratch[10].as<double2>();
         double2* Y = c->scratch[11].as<double2>();
-        std::vector<zd> t(s), Cm((size_t)k * s), Cg((size_t)k * s);
-        std::vector<lqt_solve_stats> st(s);
+        // per draw: the undeflated sample t_j and the per-mode oblique terms
+        // term[i][j] = (1/hp) sum over the vectors v of draw j of (v^T u_i)(u_i^+ g5 v)
+        std::vector<zd> t(s, zd(0)), term((size_t)k * s, zd(0));
+        std::vector<lqt_solve_stats> st(nvec);
         hipEvent_t e0, e1, e2;
         LQT_HIP(hipEventCreate(&e0));
         LQT_HIP(hipEventCreate(&e1));
         LQT_HIP(hipEventCreate(&e2));
         double t_setup = 0, t_solve = 0;
+        const double wgt = 1.0 / hp_vectors;
         DBuf small;
-        for (int j0 = 0; j0 < s; j0 += chunk) {
-            const int cs = std::min(chunk, s - j0);
+        std::vector<zd> tv(chunk);
+        for (int p0 = 0; p0 < nvec; p0 += chunk) {
+            const int cs = std::min(chunk, nvec - p0);
             LQT_HIP(hipEventRecord(e0, c->stream));
+            if (part)
+                lqt::partition_probes_gen(c, seed, p0, cs, hp_vectors, dilute, Z);
+            else
+                lqt::probes_gen(c, seed, p0, cs, Z);
+            std::vector<zd> hm, hg;  // u_i^+ v and u_i^+ g5 v of the chunk, k x cs
             if (B) {
                 small.ensure(sizeof(double2) * (size_t)k * cs * 2);
-                double2* cup = small.as<double2>();
-                double2* cdn = cup + (size_t)k * cs;
-                if (B->kind == 0) {
-                    const double2* U = (projector == LQT_ORTH) ? B->Q.as<double2>() : B->U.as<double2>();
-                    lqt::gemm_probes(c, U, k, seed, j0, cs, cup, cdn);
+                double2* cm = small.as<double2>();
+                double2* cg = cm + (size_t)k * cs;
+                hm.resize((size_t)k * cs);
+                hg.resize((size_t)k * cs);
+                const double2* Ub = (projector == LQT_ORTH) ? B->Q.as<double2>() : B->U.as<double2>();
+                if (!part) {
+                    // the probes are regenerated inside the projection kernels
+                    double2* cup = cm;
+                    double2* cdn = cg;
+                    if (B->kind == 0)
+                        lqt::gemm_probes(c, Ub, k, seed, p0, cs, cup, cdn);
+                    else
+                        lqt::prolong_project_probes(c, B, seed, p0, cs, cup, cdn);
+                    std::vector<zd> hu((size_t)k * cs), hd((size_t)k * cs);
+                    lqt::d2h(c, hu.data(), cup, sizeof(double2) * hu.size());
+                    lqt::d2h(c, hd.data(), cdn, sizeof(double2) * hd.size());
+                    for (size_t e = 0; e < hu.size(); e++) hm[e] = hu[e] + hd[e], hg[e] = hu[e] - hd[e];
                 } else {
-                    lqt::prolong_project_probes(c, B, seed, j0, cs, cup, cdn);
-                }
-                std::vector<zd> hu((size_t)k * cs), hd((size_t)k * cs);
-                lqt::d2h(c, hu.data(), cup, sizeof(double2) * hu.size());
-                lqt::d2h(c, hd.data(), cdn, sizeof(double2) * hd.size());
-                for (int i = 0; i < k; i++)
-                    for (int j = 0; j < cs; j++) {
-                        zd a = hu[(size_t)i * cs + j], b = hd[(size_t)i * cs + j];
-                        Cm[(size_t)i * s + j0 + j] = a + b;  // u_i^+ z_j
-                        Cg[(size_t)i * s + j0 + j] = a - b;  // u_i^+ g5 z_j
+                    if (B->kind == 0) {
+                        lqt::gemm_gram(c, Ub, k, Z, cs, cm);
+                        if (projector == LQT_OBLIQUE_G5) {
+                            LQT_HIP(hipMemcpyAsync(Y, Z, sizeof(double2) * (size_t)cs * n, hipMemcpyDeviceToDevice,
+                                                   c->stream));
+                            lqt::gamma5_fields(c, Y, cs);
+                            lqt::gemm_gram(c, Ub, k, Y, cs, cg);
+                        }
+                    } else {
+                        lqt::prolong_project_fields(c, B, Z, cs, cm, cg);
                     }
-            }
-            lqt::probes_gen(c, seed, j0, cs, Z);
-            if (B && projector == LQT_ORTH) {  // z <- z - Q (Q^+ z)
-                std::vector<zd> C((size_t)k * cs);
-                for (int i = 0; i < k; i++)
-                    for (int j = 0; j < cs; j++) C[(size_t)i * cs + j] = Cm[(size_t)i * s + j0 + j];
-                lqt::combine_host(c, B->Q.as<double2>(), k, C, cs, 1.0, -1.0, Z);
+                    lqt::d2h(c, hm.data(), cm, sizeof(double2) * hm.size());
+                    if (projector == LQT_OBLIQUE_G5) lqt::d2h(c, hg.data(), cg, sizeof(double2) * hg.size());
+                }
+                if (projector == LQT_OBLIQUE_G5) {
+                    for (int i = 0; i < k; i++)
+                        for (int pl = 0; pl < cs; pl++) {
+                            const int j = (p0 + pl) / q;
+                            // v real: v^T u_i = conj(u_i^+ v)
+                            term[(size_t)i * s + j] += wgt * std::conj(hm[(size_t)i * cs + pl]) * hg[(size_t)i * cs + pl];
+                        }
+                } else {  // v <- v - Q (Q^+ v)
+                    lqt::combine_host(c, B->Q.as<double2>(), k, hm, cs, 1.0, -1.0, Z);
+                }
             }
             LQT_HIP(hipEventRecord(e1, c->stream));
-            nfail_total += lqt::solve_fields(c, Z, Y, cs, xi, o, st.data() + j0);
+            nfail_total += lqt::solve_fields(c, Z, Y, cs, xi, o, st.data() + p0);
             LQT_HIP(hipEventRecord(e2, c->stream));
             c->scratch[9].ensure(sizeof(double2) * (size_t)cs);
-            lqt::probe_dots(c, seed, j0, Y, cs, c->scratch[9].as<double2>());
-            lqt::d2h(c, t.data() + j0, c->scratch[9].p, sizeof(double2) * cs);
+            if (part) {
+                // v^T y with the unprojected v (regenerated: the orthogonal projector changed Z)
+                if (B && projector == LQT_ORTH) lqt::partition_probes_gen(c, seed, p0, cs, hp_vectors, dilute, Z);
+                lqt::dot_fields(c, Z, Y, cs, c->scratch[9].as<double2>());
+            } else {
+                lqt::probe_dots(c, seed, p0, Y, cs, c->scratch[9].as<double2>());
+            }
+            lqt::d2h(c, tv.data(), c->scratch[9].p, sizeof(double2) * cs);
+            for (int pl = 0; pl < cs; pl++) t[(p0 + pl) / q] += wgt * tv[pl];
             float a = 0, b = 0;
             LQT_HIP(hipEventElapsedTime(&a, e0, e1));
             LQT_HIP(hipEventElapsedTime(&b, e1, e2));
@@ -495,8 +556,7 @@ int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64
         if (B && projector == LQT_OBLIQUE_G5)
             for (int j = 0; j < s; j++) {
                 zd corr = 0;
-                for (int i = 0; i < k; i++)
-                    corr += std::conj(Cm[(size_t)i * s + j]) * Cg[(size_t)i * s + j] / B->lambda[2 * i];
+                for (int i = 0; i < k; i++) corr += term[(size_t)i * s + j] / B->lambda[2 * i];
                 ts[j] = t[j] - corr;
             }
         Stats S = summarize(ts);
@@ -508,7 +568,7 @@ int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64
         res->var_mean = S.var / s;
         res->jackknife_err = S.jk;
         res->var_re_only = S.var_re;
-        res->nsolves = s;
+        res->nsolves = nvec;
         res->nfailed = 0;
         res->nfallback = 0;
         res->iters_total = 0;
@@ -536,8 +596,7 @@ int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64
                 for (int i = 0; i < kp; i++) t0k += zd(B->ug5u[2 * i], B->ug5u[2 * i + 1]) / B->lambda[2 * i];
                 for (int j = 0; j < s; j++) {
                     zd corr = 0;
-                    for (int i = 0; i < kp; i++)
-                        corr += std::conj(Cm[(size_t)i * s + j]) * Cg[(size_t)i * s + j] / B->lambda[2 * i];
+                    for (int i = 0; i < kp; i++) corr += term[(size_t)i * s + j] / B->lambda[2 * i];
                     tk[j] = base[j] - corr;
                 }
                 Stats Sk = summarize(tk);

@@ -83,6 +83,7 @@ _SIGS = {
     "lqt_precond_train": ([_P, _I, ctypes.c_uint64, _P, _P], _I),
     "lqt_precond_loss_grad": ([_P, _P, _I, _P, _P], _I),
     "lqt_trace": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _P, _P, _P, _P], _I),
+    "lqt_trace_probing": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _I, _I, _P, _P, _P, _P], _I),
     "lqt_probes": ([_P, ctypes.c_uint64, ctypes.c_longlong, _I, _P], _I),
     "lqt_gram": ([_P, _P, _I, _P, _I, _P], _I),
     "lqt_gram_noalloc": ([_P, _P, _I, _P, _I, _P], _I),
@@ -417,15 +418,23 @@ class Context:
         return out
 
     def trace(self, nprobes, seed, xi, basis=None, projector=OBLIQUE_G5, rank_curve=False, samples=False,
-              raise_on_fail=True, **opts):
+              raise_on_fail=True, hp_vectors=1, dilute=False, **opts):
+        """Deflated Hutchinson estimate over nprobes draws; hp_vectors > 1 or dilute use the
+        partition basis (lqt_trace_probing: each draw solves hp_vectors * (12 if dilute else
+        1) vectors)."""
         res = TraceResult()
         o = _opts(**opts)
         k = basis.k if basis is not None else 0
         curve = torch.zeros((k + 1, 3), dtype=torch.float64) if rank_curve else None
         samp = torch.zeros(nprobes, dtype=torch.complex128) if samples else None
-        rc = lib().lqt_trace(self._h, basis._h if basis is not None else None, int(projector), int(nprobes),
-                             ctypes.c_uint64(seed), float(xi), ctypes.byref(o), ctypes.byref(res), _ptr(curve),
-                             _ptr(samp))
+        bh = basis._h if basis is not None else None
+        if hp_vectors == 1 and not dilute:
+            rc = lib().lqt_trace(self._h, bh, int(projector), int(nprobes), ctypes.c_uint64(seed), float(xi),
+                                 ctypes.byref(o), ctypes.byref(res), _ptr(curve), _ptr(samp))
+        else:
+            rc = lib().lqt_trace_probing(self._h, bh, int(projector), int(nprobes), ctypes.c_uint64(seed), float(xi),
+                                         int(hp_vectors), int(bool(dilute)), ctypes.byref(o), ctypes.byref(res),
+                                         _ptr(curve), _ptr(samp))
         self._check(rc, allow=() if raise_on_fail else (LQT_ENOTCONV,))
         out = {f: getattr(res, f) for f, _ in TraceResult._fields_}
         out["rc"] = rc
