@@ -17,6 +17,9 @@ Paper: Romero, Stathopoulos, Orginos, "Multigrid deflation for Lattice QCD".
                    t0 = sum_i lambda_i^{-1} u_i^+ g5 u_i.
   Algorithm 1      orthogonal projector U U^+: t0 = sum_i u_i^+ A^{-1} u_i and the
                    stochastic part on A^{-1}(I - U U^+).
+  Section 1        Truncated Solver Method: the samples of A_xi^{-1} (solves stopped at a loose
+                   xi) are biased; an independent set of probes solved both loosely and tightly
+                   estimates the trace of the difference, which is added.
 Vectors are rows: X has shape (k, N), probes Z (s, N) real, solutions Y (s, N).
 """
 import numpy as np
@@ -114,3 +117,16 @@ def oblique_projector_dense(A, U, lam):
     N = A.shape[0]
     g5 = g5_vec(N)
     return (A @ U.T) @ np.diag(1.0 / lam) @ (np.conj(U) * g5[None, :])
+
+
+def tsm_combine(t_main, t0, corr_loose, corr_tight):
+    """Truncated Solver Method (Section 1): estimate t0 + mean(t_main) + mean(d) with the
+    corrections d_j = corr_tight_j - corr_loose_j of an independent probe set solved at both
+    tolerances; the two means are independent, so the variance of the estimate is
+    var(t_main)/s + var(d)/n_c (one-draw variances with the (n-1) denominator)."""
+    main = summarize(t_main, t0)
+    d = np.asarray(corr_tight, dtype=np.complex128) - np.asarray(corr_loose, dtype=np.complex128)
+    corr = summarize(d)
+    return {"estimate": main["estimate"] + corr["estimate"], "err": np.sqrt(main["var_mean"] + corr["var_mean"]),
+            "corr_mean": corr["estimate"], "corr_var_sample": corr["var_sample"]}
+
