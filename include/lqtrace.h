@@ -301,6 +301,10 @@ int lqt_precond_train(lqt_ctx *ctx, int npairs, uint64_t seed, const lqt_train_o
  *                   t0 = sum_i lambda_i^{-1} u_i^+ g5 u_i                  (Section 2.1)
  *   LQT_ORTH:       y_j = A^{-1}_xi (1 - U U^+) z_j, t_j = z_j^T y_j,
  *                   t0 = sum_i u_i^+ A^{-1}_xi u_i                         (Algorithm 1)
+ * The orthogonal projector takes an lqt_basis_eig basis (U its orthonormal eigenvectors) or
+ * a prolongator basis with orthonormal coarse vectors (U = W U_c, applied as restriction,
+ * coarse products and prolongation; LQT_EINVAL if max |U_c^+ U_c - I| > 1e-10): its
+ * variance is the rough lower bound of Section 2.1 for any projector onto the same span.
  * basis = NULL gives the undeflated estimator.  rank_curve (may be NULL) receives
  * (k+1) x 3 doubles: for each rank k' = 0..k the estimate (re), its one-probe variance
  * and the jackknife error, recomputed from the stored k x s products (Section 2.2;
@@ -332,6 +336,31 @@ int lqt_trace_probing(lqt_ctx *ctx, const lqt_basis *basis, int projector, int n
                       uint64_t seed, double xi, int hp_vectors, int dilute,
                       const lqt_solver_opts *opts, lqt_trace_result *out, double *h_rank_curve,
                       double *h_samples);
+
+/* Result of lqt_trace_tsm. */
+typedef struct {
+    double trace_re, trace_im;   /* main estimate + mean correction                          */
+    double err;                  /* sqrt(var_mean of the main draws + var(d) / ncorr)        */
+    double corr_re, corr_im;     /* mean correction: (1/ncorr) sum_j d_j                     */
+    double corr_var_sample;      /* one-draw variance of the d_j ((n-1) denominator)         */
+    double corr_jackknife_err;   /* jackknife error of the mean correction                   */
+    long long nsolves_loose, nsolves_tight, iters_loose, iters_tight;
+    int nfailed;                 /* solves of any of the three runs that missed their xi     */
+} lqt_tsm_result;
+
+/* Truncated Solver Method (Section 1): the samples of solves stopped at xi_loose are biased
+ * by the trace of A^{-1} - A^{-1}_xi_loose, which an independent probe set estimates.  The
+ * main run is lqt_trace_probing over nprobes draws of seed at xi_loose (into *main, t0
+ * included); the correction draws j < ncorr of seed_corr are solved at xi_loose and at
+ * xi_tight, and d_j = t_j(xi_tight) - t_j(xi_loose) (the deflation terms of a draw do not
+ * depend on the solves and cancel).  out->trace = main + mean(d); out->err combines the two
+ * independent standard errors.  corr_samples (may be NULL): 2*ncorr doubles, the d_j.
+ * LQT_EINVAL unless ncorr >= 2, seed_corr != seed and 0 < xi_tight < xi_loose; LQT_ENOTCONV
+ * (results filled) when a solve missed its tolerance. */
+int lqt_trace_tsm(lqt_ctx *ctx, const lqt_basis *basis, int projector, int nprobes, uint64_t seed,
+                  double xi_loose, int ncorr, uint64_t seed_corr, double xi_tight, int hp_vectors,
+                  int dilute, const lqt_solver_opts *opts, lqt_trace_result *main,
+                  lqt_tsm_result *out, double *h_corr_samples);
 
 /* Undeflated Hutchinson estimates of trace(A_k^{-1}), one per lattice of the context (Eq. 1;
  * the same probes and solves as lqt_trace, the samples split by lattice): res receives nlat

@@ -53,6 +53,10 @@ void prolong_project_probes(lqt_ctx* c, const lqt_basis* B, uint64_t seed, long 
 void restrict_fields(lqt_ctx* c, const lqt_basis* B, const double2* fine, double2* coarse, int nrhs);
 // cm = U_c^+ W^+ Z, cg = U_c^+ g5^W W^+ Z for s fine fields (k x s, device)
 void prolong_project_fields(lqt_ctx* c, const lqt_basis* B, const double2* Z, int s, double2* cm, double2* cg);
+// Z <- Z - W U_c C (C: k x s device coefficients; tmp: s fine fields of work space)
+void prolong_subtract(lqt_ctx* c, const lqt_basis* B, const double2* C, int s, double2* Z, double2* tmp);
+// LQT_EINVAL unless the coarse vectors U_c are orthonormal (orthogonal projector W U_c U_c^+ W^+)
+void prolong_check_orthonormal(lqt_ctx* c, const lqt_basis* B);
 void prolong_fields(lqt_ctx* c, const lqt_basis* B, const double2* coarse, double2* fine, int nrhs);
 
 }  // namespace lqt

@@ -364,6 +364,46 @@ void prolong_project_fields(lqt_ctx* c, const lqt_basis* B, const double2* Z, in
     gemm_gram(c, B->Uc.as<double2>(), B->k, rz.as<double2>(), s, cg, nc);
 }
 
+__global__ void k_sub_from(double2* __restrict__ z, const double2* __restrict__ y, long long total) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    double2 a = z[i], b = y[i];
+    z[i] = make_double2(a.x - b.x, a.y - b.y);
+}
+
+// Z <- Z - W U_c C for s fine fields Z and the k x s coefficients C (device); tmp: s fine fields
+void prolong_subtract(lqt_ctx* c, const lqt_basis* B, const double2* C, int s, double2* Z, double2* tmp) {
+    PG p = pg_of(B);
+    const long long nc = 2LL * p.nagg * p.nv;
+    DBuf cc;
+    cc.ensure(sizeof(double2) * (size_t)s * nc);
+    gemm_combine(c, B->Uc.as<double2>(), B->k, C, s, 0.0, 1.0, cc.as<double2>(), nc);
+    prolong_fields(c, B, cc.as<double2>(), tmp, s);
+    const long long tot = 12LL * p.V * s;
+    hipLaunchKernelGGL(k_sub_from, g1(tot), dim3(256), 0, c->stream, Z, tmp, tot);
+    LQT_HIP(hipGetLastError());
+}
+
+// The orthogonal projector W U_c U_c^+ W^+ needs orthonormal coarse vectors (W is orthonormal
+// by construction): LQT_EINVAL unless max |U_c^+ U_c - I| <= 1e-10.
+void prolong_check_orthonormal(lqt_ctx* c, const lqt_basis* B) {
+    const int k = B->k;
+    if (k == 0) return;
+    const long long nc = 2LL * B->nagg * B->nv;
+    DBuf G;
+    G.ensure(sizeof(double2) * (size_t)k * k);
+    gemm_gram(c, B->Uc.as<double2>(), k, B->Uc.as<double2>(), k, G.as<double2>(), nc);
+    std::vector<zd> h((size_t)k * k);
+    LQT_HIP(hipMemcpyAsync(h.data(), G.p, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    LQT_HIP(hipStreamSynchronize(c->stream));
+    double dev = 0;
+    for (int i = 0; i < k; i++)
+        for (int j = 0; j < k; j++) dev = std::max(dev, std::abs(h[(size_t)i * k + j] - zd(i == j ? 1.0 : 0.0)));
+    LQT_CHECK(dev <= 1e-10, LQT_EINVAL,
+              "the orthogonal projector needs orthonormal coarse vectors (max |U_c^+ U_c - I| = " + std::to_string(dev) +
+                  ")");
+}
+
 // Coarse oblique data from coarse vectors Ubar (k, device): M = Ubar^+ g5^W W^+ A W Ubar,
 // eigh, Uc = Ubar U_hat, u_i^+ g5 u_i = Uc_i^+ g5^W Uc_i.
 static void coarse_oblique_setup(lqt_ctx* c, lqt_basis* B, const double2* Ubar, int k) {

@@ -395,9 +395,11 @@ int lqt_trace(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64
     return lqt_trace_probing(c, B, projector, nprobes, seed, xi, 1, 0, opts, res, rank_curve, samples);
 }
 
-int lqt_trace_probing(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64_t seed, double xi,
+// The trace of lqt_trace_probing; with_t0 = false skips the deterministic part (the k extra
+// solves of the orthogonal projector), for the correction runs of lqt_trace_tsm.
+static int trace_impl(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64_t seed, double xi,
                       int hp_vectors, int dilute, const lqt_solver_opts* opts, lqt_trace_result* res,
-                      double* rank_curve, double* samples) {
+                      double* rank_curve, double* samples, bool with_t0) {
     if (!c) return LQT_EINVAL;
     int nfail_total = 0;
     int rc = guard(c, [&] {
@@ -422,9 +424,10 @@ int lqt_trace_probing(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes
             }
         }
         LQT_CHECK(!B || B->ctx == c, LQT_EINVAL, "basis belongs to another context");
-        LQT_CHECK(!(B && projector == LQT_ORTH && (!B->orthonormal || B->kind != 0)), LQT_EINVAL,
+        LQT_CHECK(!(B && projector == LQT_ORTH && B->kind == 0 && !B->orthonormal), LQT_EINVAL,
                   "the orthogonal projector needs an orthonormal fine basis (lqt_basis_eig)");
         need_gauge(c);
+        if (B && projector == LQT_ORTH && B->kind == 1) lqt::prolong_check_orthonormal(c, B);
         lqt::SolveOpts o = lqt::make_opts(opts);
         LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net without preconditioner weights");
         const long long n = 12LL * c->g.V;
@@ -510,8 +513,11 @@ int lqt_trace_probing(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes
                             // v real: v^T u_i = conj(u_i^+ v)
                             term[(size_t)i * s + j] += wgt * std::conj(hm[(size_t)i * cs + pl]) * hg[(size_t)i * cs + pl];
                         }
-                } else {  // v <- v - Q (Q^+ v)
+                } else if (B->kind == 0) {  // v <- v - Q (Q^+ v)
                     lqt::combine_host(c, B->Q.as<double2>(), k, hm, cs, 1.0, -1.0, Z);
+                } else {  // v <- v - W U_c (U_c^+ W^+ v), Y as the fine work space
+                    lqt::h2d(c, cm, hm.data(), sizeof(double2) * hm.size());
+                    lqt::prolong_subtract(c, B, cm, cs, Z, Y);
                 }
             }
             LQT_HIP(hipEventRecord(e1, c->stream));
@@ -540,7 +546,7 @@ int lqt_trace_probing(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes
         zd t0 = 0;
         if (B && projector == LQT_OBLIQUE_G5) {
             for (int i = 0; i < k; i++) t0 += zd(B->ug5u[2 * i], B->ug5u[2 * i + 1]) / B->lambda[2 * i];
-        } else if (B) {  // Algorithm 1: t0 = sum_i u_i^+ A^{-1}_xi u_i (k extra solves)
+        } else if (B && with_t0 && B->kind == 0) {  // Algorithm 1: t0 = sum_i u_i^+ A^{-1}_xi u_i (k extra solves)
             DBuf Yu;
             Yu.ensure(sizeof(double2) * (size_t)k * n);
             std::vector<lqt_solve_stats> su(k);
@@ -550,6 +556,20 @@ int lqt_trace_probing(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes
             std::vector<zd> d(k);
             lqt::d2h(c, d.data(), c->scratch[9].p, sizeof(double2) * k);
             for (auto& x : d) t0 += x;
+        } else if (B && with_t0) {  // the same with u_i = W U_c e_i, prolongated a chunk at a time
+            const long long nc = 2LL * B->nagg * B->nv;
+            const int ck = std::min(k, chunk);
+            std::vector<lqt_solve_stats> su(ck);
+            std::vector<zd> d(ck);
+            for (int i0 = 0; i0 < k; i0 += ck) {
+                const int cnt = std::min(ck, k - i0);
+                lqt::prolong_fields(c, B, B->Uc.as<double2>() + (size_t)i0 * nc, Z, cnt);
+                nfail_total += lqt::solve_fields(c, Z, Y, cnt, xi, o, su.data());
+                c->scratch[9].ensure(sizeof(double2) * (size_t)cnt);
+                lqt::dot_fields(c, Z, Y, cnt, c->scratch[9].as<double2>());
+                lqt::d2h(c, d.data(), c->scratch[9].p, sizeof(double2) * cnt);
+                for (int i = 0; i < cnt; i++) t0 += d[i];
+            }
         }
         // samples
         std::vector<zd> base = t, ts = t;
@@ -608,6 +628,59 @@ int lqt_trace_probing(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes
     });
     if (rc == LQT_OK && nfail_total) return LQT_ENOTCONV;
     return rc;
+}
+
+int lqt_trace_probing(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64_t seed, double xi,
+                      int hp_vectors, int dilute, const lqt_solver_opts* opts, lqt_trace_result* res,
+                      double* rank_curve, double* samples) {
+    return trace_impl(c, B, projector, nprobes, seed, xi, hp_vectors, dilute, opts, res, rank_curve, samples, true);
+}
+
+int lqt_trace_tsm(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes, uint64_t seed, double xi_loose,
+                  int ncorr, uint64_t seed_corr, double xi_tight, int hp_vectors, int dilute,
+                  const lqt_solver_opts* opts, lqt_trace_result* main, lqt_tsm_result* out, double* corr_samples) {
+    if (!c) return LQT_EINVAL;
+    if (!main || !out || ncorr < 2 || seed_corr == seed || !(xi_tight > 0 && xi_tight < xi_loose)) {
+        c->err = "tsm: needs results, ncorr >= 2, seed_corr != seed and 0 < xi_tight < xi_loose";
+        return LQT_EINVAL;
+    }
+    int rc = trace_impl(c, B, projector, nprobes, seed, xi_loose, hp_vectors, dilute, opts, main, nullptr, nullptr,
+                        true);
+    if (rc != LQT_OK && rc != LQT_ENOTCONV) return rc;
+    int worst = rc;
+    // the correction probes at both tolerances: the deflation terms of a draw do not depend on
+    // the solves, so the difference of its two samples is (1/hp) sum_v v^T (y_tight - y_loose)
+    std::vector<double> sl(2 * (size_t)ncorr), st(2 * (size_t)ncorr);
+    lqt_trace_result rl{}, rt{};
+    rc = trace_impl(c, B, projector, ncorr, seed_corr, xi_loose, hp_vectors, dilute, opts, &rl, nullptr, sl.data(),
+                    false);
+    if (rc != LQT_OK && rc != LQT_ENOTCONV) return rc;
+    if (rc != LQT_OK) worst = rc;
+    rc = trace_impl(c, B, projector, ncorr, seed_corr, xi_tight, hp_vectors, dilute, opts, &rt, nullptr, st.data(),
+                    false);
+    if (rc != LQT_OK && rc != LQT_ENOTCONV) return rc;
+    if (rc != LQT_OK) worst = rc;
+    std::vector<zd> d(ncorr);
+    for (int j = 0; j < ncorr; j++) d[j] = zd(st[2 * j] - sl[2 * j], st[2 * j + 1] - sl[2 * j + 1]);
+    Stats S = summarize(d);
+    out->trace_re = main->trace_re + S.mean.real();
+    out->trace_im = main->trace_im + S.mean.imag();
+    out->err = std::sqrt(main->var_mean + S.var / ncorr);
+    out->corr_re = S.mean.real();
+    out->corr_im = S.mean.imag();
+    out->corr_var_sample = S.var;
+    out->corr_jackknife_err = S.jk;
+    out->nsolves_loose = main->nsolves + rl.nsolves;
+    out->nsolves_tight = rt.nsolves;
+    out->iters_loose = main->iters_total + rl.iters_total;
+    out->iters_tight = rt.iters_total;
+    out->nfailed = main->nfailed + rl.nfailed + rt.nfailed;
+    if (corr_samples)
+        for (int j = 0; j < ncorr; j++) {
+            corr_samples[2 * j] = d[j].real();
+            corr_samples[2 * j + 1] = d[j].imag();
+        }
+    return worst;
 }
 
 int lqt_gram(lqt_ctx* c, const double* x, int ka, const double* y, int kb, double* h_c) {

@@ -46,6 +46,14 @@ class TraceResult(ctypes.Structure):
                 ("seconds_setup", ctypes.c_double), ("nfallback", ctypes.c_int)]
 
 
+class TsmResult(ctypes.Structure):
+    _fields_ = [("trace_re", ctypes.c_double), ("trace_im", ctypes.c_double), ("err", ctypes.c_double),
+                ("corr_re", ctypes.c_double), ("corr_im", ctypes.c_double), ("corr_var_sample", ctypes.c_double),
+                ("corr_jackknife_err", ctypes.c_double), ("nsolves_loose", ctypes.c_longlong),
+                ("nsolves_tight", ctypes.c_longlong), ("iters_loose", ctypes.c_longlong),
+                ("iters_tight", ctypes.c_longlong), ("nfailed", ctypes.c_int)]
+
+
 class TrainOpts(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int), ("lr", ctypes.c_double), ("batch", ctypes.c_int),
                 ("pair_xi", ctypes.c_double), ("verbose", ctypes.c_int)]
@@ -84,6 +92,7 @@ _SIGS = {
     "lqt_precond_loss_grad": ([_P, _P, _I, _P, _P], _I),
     "lqt_trace": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _P, _P, _P, _P], _I),
     "lqt_trace_probing": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _I, _I, _P, _P, _P, _P], _I),
+    "lqt_trace_tsm": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _I, ctypes.c_uint64, _D, _I, _I, _P, _P, _P, _P], _I),
     "lqt_probes": ([_P, ctypes.c_uint64, ctypes.c_longlong, _I, _P], _I),
     "lqt_gram": ([_P, _P, _I, _P, _I, _P], _I),
     "lqt_gram_noalloc": ([_P, _P, _I, _P, _I, _P], _I),
@@ -443,6 +452,25 @@ class Context:
         if samples:
             out["samples"] = samp
         return out
+
+
+    def trace_tsm(self, nprobes, seed, xi_loose, ncorr, seed_corr, xi_tight, basis=None, projector=OBLIQUE_G5,
+                  hp_vectors=1, dilute=False, raise_on_fail=True, **opts):
+        """Truncated Solver Method (lqt_trace_tsm): returns (main trace result, TSM result
+        with the correction samples)."""
+        main, out = TraceResult(), TsmResult()
+        o = _opts(**opts)
+        corr = torch.zeros(ncorr, dtype=torch.complex128)
+        rc = lib().lqt_trace_tsm(self._h, basis._h if basis is not None else None, int(projector), int(nprobes),
+                                 ctypes.c_uint64(seed), float(xi_loose), int(ncorr), ctypes.c_uint64(seed_corr),
+                                 float(xi_tight), int(hp_vectors), int(bool(dilute)), ctypes.byref(o),
+                                 ctypes.byref(main), ctypes.byref(out), _ptr(corr))
+        self._check(rc, allow=() if raise_on_fail else (LQT_ENOTCONV,))
+        m = {f: getattr(main, f) for f, _ in TraceResult._fields_}
+        t = {f: getattr(out, f) for f, _ in TsmResult._fields_}
+        t["corr_samples"] = corr
+        t["rc"] = rc
+        return m, t
 
 
 class Basis:
