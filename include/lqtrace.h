@@ -112,6 +112,11 @@ typedef struct {
                         (lqt_basis_eig, the coarse eigensolve of lqt_basis_prolongator) [128] */
     double eig_xi;   /* acceptance tolerance of the coarse eigensolve of
                         lqt_basis_prolongator [0: null_xi]                                */
+    int twogrid;     /* 1: the two-grid preconditioner of lqt_precond_twogrid as the right
+                        preconditioner of FGMRES (not with use_net, sstep or graph) [0]   */
+    int tg_smooth;   /* its minimal-residual smoothing steps on A [4; negative: none]    */
+    double tg_coarse_tol; /* relative residual of its coarse GMRES solve [0.1]          */
+    int tg_coarse_maxit;  /* cap on the coarse GMRES steps per application [32]         */
 } lqt_solver_opts;
 
 /* Per right-hand side solve statistics. */
@@ -291,6 +296,23 @@ int lqt_precond_loss_grad(lqt_ctx *ctx, const double *d_e, int npairs, double *h
  * the mean loss of the last epoch (accumulated over its steps). */
 int lqt_precond_train(lqt_ctx *ctx, int npairs, uint64_t seed, const lqt_train_opts *opts,
                       double *h_final_loss);
+
+/* Two-grid preconditioner (Section 2, the two-grid method) from a prolongator basis of this
+ * context (lqt_basis_prolongator / _from; its coarse vectors are not used): one application
+ * to a residual v, from x = 0, is the coarse grid correction x_c = W D_c^{-1} W^+ v with the
+ * explicit coarse operator D_c = W^+ A W (built here if missing), solved by batched FP64
+ * GMRES(16) to opts->tg_coarse_tol (at most tg_coarse_maxit steps), followed by
+ * opts->tg_smooth minimal-residual steps on A (s = v - A x_c; p = A s, a = p^+ s / p^+ p,
+ * x += a s, s -= a p).  solver option twogrid = 1 puts it inside FGMRES as the right
+ * preconditioner (the coarse solve and the smoothing depend on v, which flexible GMRES
+ * allows).  The basis stays owned by the caller and must outlive its use; basis = NULL
+ * clears it (lqt_basis_free of the set basis clears it too).  Single-lattice contexts. */
+int lqt_precond_twogrid(lqt_ctx *ctx, lqt_basis *basis);
+
+/* One application of the two-grid preconditioner to nrhs canonical complex128 device
+ * fields (the options' tg_* fields), for verification and measurement. */
+int lqt_precond_twogrid_apply(lqt_ctx *ctx, const double *d_in, double *d_out, int nrhs,
+                              const lqt_solver_opts *opts);
 
 /* ---- trace estimation -------------------------------------------------------------- */
 

@@ -24,6 +24,11 @@ struct KryState {
     int* frozen;      // [slot]           1 once the cycle of the slot has ended
 };
 
+// storage S <-> FP64 over total complex entries of the same layout
+template <typename S>
+void fields_to_f64(lqt_ctx* c, const S* in, double2* out, long long total);
+template <typename S>
+void fields_from_f64(lqt_ctx* c, const double2* in, S* out, long long total);
 template <typename S>
 void kry_dots(lqt_ctx* c, const void* Vb, long long vstride, int j, int ns, double2* part);
 template <typename S>

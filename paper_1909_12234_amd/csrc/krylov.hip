@@ -1129,7 +1129,39 @@ void sstep_finish(lqt_ctx* c, const void* Vb, long long vstride, int s, int ns, 
     c->timer.end(c->stream);
 }
 
+// storage S <-> FP64 over total complex entries (same layout)
+template <typename S>
+__global__ void k_to_f64(const S* __restrict__ in, double2* __restrict__ out, long long total) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const cx<double> v = ldk<S, double>(in + i);
+    out[i] = make_double2(v.x, v.y);
+}
+
+template <typename S>
+__global__ void k_from_f64(const double2* __restrict__ in, S* __restrict__ out, long long total) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    stk<S, double>(out + i, cx<double>{in[i].x, in[i].y});
+}
+
+template <typename S>
+void fields_to_f64(lqt_ctx* c, const S* in, double2* out, long long total) {
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_to_f64<S>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream, in, out, total);
+    LQT_HIP(hipGetLastError());
+}
+
+template <typename S>
+void fields_from_f64(lqt_ctx* c, const double2* in, S* out, long long total) {
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_from_f64<S>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream, in, out, total);
+    LQT_HIP(hipGetLastError());
+}
+
 #define INST(S)                                                                                          \
+    template void fields_to_f64<S>(lqt_ctx*, const S*, double2*, long long);                             \
+    template void fields_from_f64<S>(lqt_ctx*, const double2*, S*, long long);                           \
     template int kry_blocks<S>(const lqt_ctx*);                                                          \
     template void kry_dots<S>(lqt_ctx*, const void*, long long, int, int, double2*);                     \
     template void kry_update<S>(lqt_ctx*, void*, long long, int, int, const KryState&, int, double*);    \

@@ -347,6 +347,8 @@ struct lqt_ctx {
     lqt::Net net;
     double sigma_max = 0;  // power-iteration estimate, filled on demand
     void* blas = nullptr;  // rocBLAS handle of the dense setup eigenproblems (created on demand)
+    lqt_basis* tg = nullptr;  // prolongator of the two-grid preconditioner (caller-owned)
+    lqt::DBuf tg_work[2];     // its FP64 fine and coarse work fields
 };
 
 struct lqt_basis {

@@ -21,6 +21,10 @@ struct SolveOpts {
     int stall_window = 2;   // FP64 residuals without a decrease that count as a stall
     int eig_degree = 128;   // Chebyshev filter degree of the eigensolvers
     double eig_xi = 0.0;    // acceptance tolerance of the coarse eigensolve (0: null_xi)
+    int twogrid = 0;        // 1: two-grid right preconditioner (lqt_precond_twogrid) in FGMRES
+    int tg_smooth = 4;      // its minimal-residual smoothing steps
+    double tg_coarse_tol = 0.1;  // relative residual of its coarse solve
+    int tg_coarse_maxit = 32;    // cap on the coarse GMRES steps
 };
 
 SolveOpts make_opts(const lqt_solver_opts* u);

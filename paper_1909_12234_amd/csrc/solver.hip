@@ -16,6 +16,7 @@
 #include "krylov.h"
 #include "lqt_internal.h"
 #include "ptc.h"
+#include "twogrid.h"
 #include "solver.h"
 #include "stall.h"
 
@@ -103,7 +104,8 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     basisb.ensure((size_t)(m + 1) * nb * n * eb);
     // flexible GMRES: z_j = M v_j is kept for the solution update (right preconditioning)
     DBuf& zb = c->scratch[12];
-    if (o.use_net) zb.ensure((size_t)m * nb * n * eb);
+    const bool flex = o.use_net || o.twogrid;
+    if (flex) zb.ensure((size_t)m * nb * n * eb);
     rb.ensure((size_t)nb * n * sizeof(double2) + 4 * 256 * (size_t)nb);
     StateBuf sb;
     sb.carve(stb, nb, m);
@@ -293,9 +295,12 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
                 return;
             }
             const void* aj = vj;
-            if (o.use_net) {
+            if (flex) {
                 void* zj = (char*)zb.p + (size_t)j * vstride * eb;
-                ptc_apply<S>(c, (const S*)vj, (S*)zj, nn);
+                if (o.use_net)
+                    ptc_apply<S>(c, (const S*)vj, (S*)zj, nn);
+                else
+                    twogrid_apply<S>(c, (const S*)vj, (S*)zj, nn, o);
                 aj = zj;
             }
             dslash(c, prec, LQT_A, aj, vj1, nn, n, n);
@@ -309,7 +314,7 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
             if (carry)
                 kry_sstep_carry<S>(c, x, act_d, basis, vstride, nn, sb.st, theta, sigma, (double*)part, rn2c);
             else
-                kry_xupdate<S>(c, x, act_d, o.use_net ? zb.p : basis, vstride, nn, sb.st);
+                kry_xupdate<S>(c, x, act_d, flex ? zb.p : basis, vstride, nn, sb.st);
             c->timer.end(c->stream);
         };
         if (o.graph) {
@@ -414,7 +419,7 @@ static int run_fallback(lqt_ctx* c, const double2* b, double2* x, int nb, double
             idx.push_back(i);
             how.push_back(stalled[i]);
         }
-    ChainCfg cur{o0.prec, o0.use_net, o0.sstep};
+    ChainCfg cur{o0.prec, o0.use_net || o0.twogrid, o0.sstep};
     int level = 0, nfail = 0;
     while (!idx.empty()) {
         ChainCfg nx;
@@ -426,12 +431,13 @@ static int run_fallback(lqt_ctx* c, const double2* b, double2* x, int nb, double
         level++;
         SolveOpts o = o0;
         o.prec = cur.prec;
-        o.use_net = cur.net;
+        o.use_net = cur.net ? o0.use_net : 0;
+        o.twogrid = cur.net ? o0.twogrid : 0;
         o.sstep = cur.sstep;
         const int ns = (int)idx.size();
         if (o0.verbose) {
             fprintf(stderr, "[lqtrace] solve: %d stalled system(s) continue at fallback level %d (storage %d%s%s)\n",
-                    ns, level, o.prec, o.use_net ? ", net" : "", o.sstep ? ", s-step" : "");
+                    ns, level, o.prec, o.use_net ? ", net" : (o.twogrid ? ", two-grid" : ""), o.sstep ? ", s-step" : "");
             fflush(stderr);
         }
         DBuf bs, xs;
@@ -494,6 +500,10 @@ SolveOpts make_opts(const lqt_solver_opts* u) {
         o.stall_window = u->stall_window > 0 ? u->stall_window : 2;
         o.eig_degree = u->eig_degree > 0 ? u->eig_degree : 128;
         o.eig_xi = u->eig_xi > 0 ? u->eig_xi : 0.0;
+        o.twogrid = u->twogrid;
+        o.tg_smooth = u->tg_smooth > 0 ? u->tg_smooth : (u->tg_smooth < 0 ? 0 : 4);
+        o.tg_coarse_tol = u->tg_coarse_tol > 0 ? u->tg_coarse_tol : 0.1;
+        o.tg_coarse_maxit = u->tg_coarse_maxit > 0 ? u->tg_coarse_maxit : 32;
     }
     return o;
 }
@@ -505,7 +515,10 @@ int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, 
     LQT_CHECK(xi > 0, LQT_EINVAL, "tolerance must be positive");
     LQT_CHECK(!o.use_net || c->net.set, LQT_ESTATE, "use_net requires preconditioner weights (lqt_precond_set/train)");
     LQT_CHECK(!o.use_net || c->g.lat.nlat == 1, LQT_EINVAL, "the network preconditioner serves single-lattice contexts");
-    LQT_CHECK(!o.sstep || (!o.use_net && o.restart <= (storage_bytes(o.prec) == 4 ? 15 : 8)), LQT_EINVAL,
+    LQT_CHECK(!(o.use_net && o.twogrid), LQT_EINVAL, "use_net and twogrid are exclusive");
+    LQT_CHECK(!o.twogrid || c->tg, LQT_ESTATE, "twogrid requires a prolongator (lqt_precond_twogrid)");
+    LQT_CHECK(!o.twogrid || !o.graph, LQT_EINVAL, "the two-grid preconditioner cannot run inside a captured graph");
+    LQT_CHECK(!o.sstep || (!o.use_net && !o.twogrid && o.restart <= (storage_bytes(o.prec) == 4 ? 15 : 8)), LQT_EINVAL,
               "s-step cycles need restart <= 15 (16-bit storage) or <= 8, and no network preconditioner");
     LQT_CHECK(o.reliable >= 0 && o.reliable < 1, LQT_EINVAL, "reliable must be below 1");
     const long long n = 12LL * c->g.V;
@@ -515,6 +528,7 @@ int solve_fields(lqt_ctx* c, const double2* b, double2* x, int nrhs, double xi, 
     size_t per = (size_t)(o.restart + 1) * n * storage_bytes(o.prec) + (size_t)n * 16 * 2 +
                  (size_t)((c->g.V + 255) / 256) * (o.restart + 2) * 16;
     if (o.use_net) per += (size_t)o.restart * n * storage_bytes(o.prec) + (size_t)c->g.V * 24 * 8 * 2;
+    if (o.twogrid) per += (size_t)o.restart * n * storage_bytes(o.prec) + (size_t)n * 16 * 4;
     size_t have = (size_t)(0.7 * (double)(fr + c->scratch[0].n + c->scratch[1].n + c->scratch[3].n +
                                           c->scratch[12].n + c->net.act.n));
     int fit = (int)std::max<size_t>(1, have / per);

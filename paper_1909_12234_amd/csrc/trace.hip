@@ -302,6 +302,7 @@ int lqt_basis_vectors(const lqt_basis* B, double* out) {
 void lqt_basis_free(lqt_basis* B) {
     if (!B) return;
     if (B->ctx) (void)hipStreamSynchronize(B->ctx->stream);
+    if (B->ctx && B->ctx->tg == B) B->ctx->tg = nullptr;
     delete B;
 }
 
@@ -444,6 +445,7 @@ static int trace_impl(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes
         LQT_HIP(hipMemGetInfo(&fr, &tot));
         size_t per = (size_t)n * 16 * 2 + (size_t)(o.restart + 1) * n * lqt::storage_bytes(o.prec) + (size_t)n * 32;
         if (o.use_net) per += (size_t)o.restart * n * lqt::storage_bytes(o.prec);
+        if (o.twogrid) per += (size_t)o.restart * n * lqt::storage_bytes(o.prec) + (size_t)n * 16 * 4;
         int fit = (int)std::max<size_t>(1, (size_t)(0.6 * (double)(fr + c->scratch[0].n + c->scratch[10].n +
                                                                      c->scratch[11].n)) / per);
         int chunk = std::min(nvec, o.max_batch > 0 ? o.max_batch : nvec);

@@ -30,7 +30,8 @@ class SolverOpts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("verbose", ctypes.c_int), ("outer_maxit", ctypes.c_int),
                 ("graph", ctypes.c_int), ("sstep", ctypes.c_int), ("reliable", ctypes.c_double),
                 ("fallback", ctypes.c_int), ("stall_window", ctypes.c_int), ("eig_degree", ctypes.c_int),
-                ("eig_xi", ctypes.c_double)]
+                ("eig_xi", ctypes.c_double), ("twogrid", ctypes.c_int), ("tg_smooth", ctypes.c_int),
+                ("tg_coarse_tol", ctypes.c_double), ("tg_coarse_maxit", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -91,6 +92,8 @@ _SIGS = {
     "lqt_precond_train": ([_P, _I, ctypes.c_uint64, _P, _P], _I),
     "lqt_precond_loss_grad": ([_P, _P, _I, _P, _P], _I),
     "lqt_trace": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _P, _P, _P, _P], _I),
+    "lqt_precond_twogrid": ([_P, _P], _I),
+    "lqt_precond_twogrid_apply": ([_P, _P, _P, _I, _P], _I),
     "lqt_trace_probing": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _I, _I, _P, _P, _P, _P], _I),
     "lqt_trace_tsm": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _I, ctypes.c_uint64, _D, _I, _I, _P, _P, _P, _P], _I),
     "lqt_probes": ([_P, ctypes.c_uint64, ctypes.c_longlong, _I, _P], _I),
@@ -162,9 +165,11 @@ _APPLY_DTYPE = {0: torch.complex128, 1: torch.complex64, 2: torch.complex64, 3: 
 
 
 def _opts(prec=F64, restart=32, maxit=100000, use_net=0, max_batch=0, cgs2=0, inner_tol=0.0, verbose=0,
-          outer_maxit=0, graph=0, sstep=0, reliable=0.0, fallback=0, stall_window=0, eig_degree=0, eig_xi=0.0):
+          outer_maxit=0, graph=0, sstep=0, reliable=0.0, fallback=0, stall_window=0, eig_degree=0, eig_xi=0.0,
+          twogrid=0, tg_smooth=0, tg_coarse_tol=0.0, tg_coarse_maxit=0):
     return SolverOpts(prec, restart, maxit, use_net, max_batch, cgs2, inner_tol, verbose, outer_maxit, graph, sstep,
-                      reliable, fallback, stall_window, eig_degree, eig_xi)
+                      reliable, fallback, stall_window, eig_degree, eig_xi, twogrid, tg_smooth, tg_coarse_tol,
+                      tg_coarse_maxit)
 
 
 class Context:
@@ -375,6 +380,19 @@ class Context:
         return Basis(self, h)
 
     # -- learned preconditioner
+    def precond_twogrid(self, basis):
+        """Use the prolongator of `basis` (None clears) for the two-grid preconditioner."""
+        self._check(lib().lqt_precond_twogrid(self._h, basis._h if basis is not None else None))
+        self._tg_basis = basis
+
+    def precond_twogrid_apply(self, x, **opts):
+        """One two-grid application to canonical complex128 device fields."""
+        x = _dev(x, torch.complex128, self.N, "two-grid input")
+        out = torch.empty_like(x)
+        o = _opts(**opts)
+        self._check(lib().lqt_precond_twogrid_apply(self._h, _ptr(x), _ptr(out), x.numel() // self.N, ctypes.byref(o)))
+        return out
+
     def precond_set(self, weights):
         w = torch.as_tensor(weights, dtype=torch.complex64).contiguous().cpu()
         return self._check(lib().lqt_precond_set(self._h, _ptr(w), w.numel() * 8))
