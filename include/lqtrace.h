@@ -215,7 +215,12 @@ int lqt_solve(lqt_ctx *ctx, const double *d_b, double *d_x, int nrhs, double xi,
  * (theta, q) is accepted when ||H q - theta q|| <= xi |theta|, which implies the convergence
  * test of the paper's Table 1, ||H^{-1} q - q/theta|| <= xi ||H^{-1}||.  Returns
  * LQT_ENOTCONV (with the basis in *out) if not all k pairs pass.
- * tau must be 0 (the i*tau*g5 shift of Section 3.2 is not implemented; LQT_EINVAL).
+ * tau: the shift of Algorithm 1, whose eigensolve targets g5 (A + i tau g5)^{-1} =
+ * (A g5 + i tau)^{-1}: its eigenvectors are those of A g5 and its largest magnitudes
+ * 1/|lambda + i tau| = 1/sqrt(lambda^2 + tau^2) order them as the smallest |lambda|, so the
+ * basis and the returned lambda (eigenvalues of A g5) do not depend on tau.  The shift only
+ * conditions the inexact inversions of an inverse-based eigensolver; the Chebyshev filter
+ * applies H itself and takes no inverse, so tau (any finite value) changes nothing here.
  * *out receives a basis owned by the caller (free with lqt_basis_free); the context
  * must outlive it. */
 int lqt_basis_eig(lqt_ctx *ctx, int k, double xi, double tau, const lqt_solver_opts *opts,

@@ -221,7 +221,9 @@ int lqt_basis_eig(lqt_ctx* c, int k, double xi, double tau, const lqt_solver_opt
         LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
         LQT_CHECK(k >= 1, LQT_EINVAL, "k must be >= 1");
         LQT_CHECK(xi > 0 && xi < 1, LQT_EINVAL, "xi must be in (0, 1)");
-        LQT_CHECK(tau == 0.0, LQT_EINVAL, "the shifted (tau != 0) eigensolver is not implemented");
+        // the shift i tau g5 leaves the eigenvectors of A g5 and their order unchanged (the
+        // filter takes no inverse, where the shift would condition the solves)
+        LQT_CHECK(std::isfinite(tau), LQT_EINVAL, "tau must be finite");
         need_gauge(c);
         const long long n = 12LL * c->g.V;
         LQT_CHECK(k <= n / 8, LQT_EINVAL, "k too large for the lattice");

@@ -209,3 +209,22 @@ def test_trace_error_paths(gpu, cfg0):
     assert r["rc"] == -4 and r["nfailed"] == 4
     B.close()
     c.close()
+
+
+def test_tau_shift_leaves_the_basis_unchanged(gpu, cfg0):
+    """Algorithm 1's target g5 (A + i tau g5)^{-1} = (A g5 + i tau)^{-1} has the eigenvectors
+    of A g5, ordered by |lambda + i tau|, i.e. by |lambda|: the basis for tau = 0.3 is the
+    basis for tau = 0 (the filter applies A g5 itself), and a non-finite tau is refused."""
+    lq = gpu
+    dims, m, U, A, Ai = cfg0
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    B0 = c.basis_eig(16, xi=1e-2, tau=0.0)
+    B1 = c.basis_eig(16, xi=1e-2, tau=0.3)
+    assert np.array_equal(B0.eigenvalues().numpy(), B1.eigenvalues().numpy())
+    assert torch.equal(B0.vectors(), B1.vectors())
+    with pytest.raises(lq.LqtError):
+        c.basis_eig(16, xi=1e-2, tau=float("inf"))
+    B0.close()
+    B1.close()
+    c.close()
