@@ -53,9 +53,10 @@ def parse():
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration) and exit")
     ap.add_argument("--inner-prec", choices=["f32", "f16", "bf16"], default=None,
                     help="override the workload's inner storage precision")
-    ap.add_argument("--basis-iters", type=int, default=200,
+    ap.add_argument("--mass", type=float, default=None, help="override the workload's bare mass (conditioning scans)")
+    ap.add_argument("--basis-iters", type=int, default=400,
                     help="cap on the filtered iterations of the A g5 eigensolver before the timed region (it stops "
-                         "once all k pairs meet the Table 1 test; about 65 on 16^3x32)")
+                         "once all k pairs meet the Table 1 test; about 65 at m = -1.90 and 270 at m = -1.95 on 16^3x32)")
     return ap.parse_args()
 
 
@@ -344,6 +345,8 @@ def run_mg(a, w):
     import synth
     from paper_1909_12234_amd.workloads import PREC
 
+    if a.mass is not None:
+        w = dict(w, mass=a.mass)
     dims, mass, eps = w["dims"], w["mass"], w["eps"]
     nprobes = a.nprobes or w["nprobes"]
     prec = PREC[a.inner_prec or w["inner_prec"]]
@@ -515,6 +518,8 @@ def main():
         return run_batched(a, w)
     if a.workload == "wilson16x32_net":
         return run_net(a, w)
+    if a.mass is not None:
+        w = dict(w, mass=a.mass)
     dims, mass, eps = w["dims"], w["mass"], w["eps"]
     nprobes = a.nprobes or w["nprobes"]
     if a.inner_prec:

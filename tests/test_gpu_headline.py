@@ -1,4 +1,4 @@
-"""The benchmark's configuration against the oracle: 16^3x32, m = -1.90, 128 probes, FP16
+"""The benchmark's configuration against the oracle: 16^3x32, m = -1.95, 128 probes, FP16
 s-step GMRES(15) with FP64 defect correction to 1e-8, oblique g5 deflation with a k = 64
 basis from the library's A g5 eigensolver.
 

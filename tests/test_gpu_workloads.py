@@ -17,7 +17,7 @@ def _relres(U, dims, m, b, x):
 
 
 def test_mixed_16x32_probe_solves(gpu):
-    """16^3x32, m = -1.90, the workload's 16-bit inner s-step cycles with FP64 defect correction
+    """16^3x32, m = -1.95, the workload's 16-bit inner s-step cycles with FP64 defect correction
     to 1e-8, in the launch configuration of the benchmark (128 probes, autotuned operator
     tiles); 4 sampled solutions are checked with the oracle operator and their samples z^T y
     against the oracle's dot."""
