@@ -15,6 +15,8 @@
 //
 // One thread owns one site and R right-hand sides: each link is loaded once and applied
 // to R spinors.  Algorithmic traffic per site: 72 link reals + R*(24 in + 24 out) reals.
+#include <iterator>
+
 #include "blas.h"
 #include "dslash_mfma.h"
 #include "lqt_internal.h"
@@ -816,12 +818,32 @@ static void dslash_cfg(lqt_ctx* c, int prec, int op, const void* in, void* out, 
     }
 }
 
+// The tile for (prec, nrhs): the tuned one, else (a solve's active set shrinks as its systems
+// converge) the tile tuned for the nearest larger batch of the same precision, else the nearest
+// smaller one, narrowed to at most nrhs fields per thread; the default tile when none is tuned.
+static Tuned tile_for(const lqt_ctx* c, int prec, int nrhs) {
+    auto it = c->tuned.find(tune_key(prec, nrhs));
+    if (it != c->tuned.end()) return it->second;
+    const long long lo_key = tune_key(prec, 0), hi_key = tune_key(prec + 1, 0);
+    const Tuned* pick = nullptr;
+    auto up = c->tuned.lower_bound(tune_key(prec, nrhs));
+    if (up != c->tuned.end() && up->first < hi_key) {
+        pick = &up->second;
+    } else if (up != c->tuned.begin()) {
+        auto dn = std::prev(up);
+        if (dn->first > lo_key && dn->first < hi_key) pick = &dn->second;
+    }
+    if (!pick) return default_tile(prec, nrhs);
+    Tuned t = *pick;
+    if (t.kind != 1 && t.kind != 4)
+        while (t.rhs_per_thread > 1 && t.rhs_per_thread > nrhs) t.rhs_per_thread >>= 1;
+    return t;
+}
+
 void dslash(lqt_ctx* c, int prec, int op, const void* in, void* out, int nrhs, long long in_stride,
             long long out_stride, double shift, double scale) {
     if (nrhs <= 0) return;
-    Tuned t;
-    auto it = c->tuned.find(tune_key(prec, nrhs));
-    t = (it != c->tuned.end()) ? it->second : default_tile(prec, nrhs);
+    const Tuned t = tile_for(c, prec, nrhs);
     c->timer.begin(c->stream, KT_DSLASH);
     dslash_cfg(c, prec, op, in, out, nrhs, in_stride, out_stride, t, shift, scale);
     const double b = (double)storage_bytes(prec) / 2;  // bytes per real
