@@ -402,6 +402,12 @@ int lqt_trace_lattices(lqt_ctx *ctx, int nprobes, uint64_t seed, double xi,
 /* Write the real Rademacher probes j0 .. j0+nprobes-1 as canonical complex128 fields. */
 int lqt_probes(lqt_ctx *ctx, uint64_t seed, long long j0, int nprobes, double *d_out);
 
+/* Write the partition probe vectors p0 .. p0+nvec-1 of lqt_trace_probing (vector
+ * p = j q + m nd + c of draw j, q = hp_vectors nd, nd = 12 with dilution, else 1) as
+ * canonical complex128 fields (device).  Single-lattice contexts. */
+int lqt_partition_probes(lqt_ctx *ctx, uint64_t seed, long long p0, int nvec, int hp_vectors,
+                         int dilute, double *d_out);
+
 /* C = X^+ Y for ka fields X and kb fields Y (canonical complex128, device); C is ka x kb
  * complex, row-major, written to host memory.  FP64 MFMA. */
 int lqt_gram(lqt_ctx *ctx, const double *d_x, int ka, const double *d_y, int kb, double *h_c);

@@ -209,6 +209,28 @@ int lqt_solve(lqt_ctx* c, const double* b, double* x, int nrhs, double xi, const
     return rc;
 }
 
+int lqt_partition_probes(lqt_ctx* c, uint64_t seed, long long p0, int nvec, int hp_vectors, int dilute, double* out) {
+    if (!c) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(nvec >= 0 && p0 >= 0, LQT_EINVAL, "bad vector range");
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "partition probes serve single-lattice contexts");
+        LQT_CHECK(dilute == 0 || dilute == 1, LQT_EINVAL, "dilute must be 0 or 1");
+        LQT_CHECK(hp_vectors >= 1 && hp_vectors <= (1 << 20) && !(hp_vectors & (hp_vectors - 1)), LQT_EINVAL,
+                  "hp_vectors must be a power of two");
+        if (nvec == 0) return;
+        LQT_CHECK(out, LQT_EINVAL, "null output");
+        const long long n = 12LL * c->g.V;
+        DBuf t;
+        t.ensure(sizeof(double2) * (size_t)n * nvec);
+        for (int f0 = 0; f0 < nvec; f0 += 65535) {
+            const int cnt = std::min(65535, nvec - f0);
+            lqt::partition_probes_gen(c, seed, p0 + f0, cnt, hp_vectors, dilute, t.as<double2>() + (size_t)f0 * n);
+        }
+        lqt::from_device_layout(c, t.as<double2>(), (double2*)out, nvec);
+        LQT_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
 int lqt_probes(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double* out) {
     if (!c) return LQT_EINVAL;
     return guard(c, [&] {

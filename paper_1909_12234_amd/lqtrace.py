@@ -97,6 +97,7 @@ _SIGS = {
     "lqt_trace_probing": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _I, _I, _P, _P, _P, _P], _I),
     "lqt_trace_tsm": ([_P, _P, _I, _I, ctypes.c_uint64, _D, _I, ctypes.c_uint64, _D, _I, _I, _P, _P, _P, _P], _I),
     "lqt_probes": ([_P, ctypes.c_uint64, ctypes.c_longlong, _I, _P], _I),
+    "lqt_partition_probes": ([_P, ctypes.c_uint64, ctypes.c_longlong, _I, _I, _I, _P], _I),
     "lqt_gram": ([_P, _P, _I, _P, _I, _P], _I),
     "lqt_gram_noalloc": ([_P, _P, _I, _P, _I, _P], _I),
     "lqt_project_probes": ([_P, _P, _I, ctypes.c_uint64, ctypes.c_longlong, _I, _P, _P], _I),
@@ -254,6 +255,13 @@ class Context:
     def probes(self, seed, nprobes, j0=0):
         out = torch.empty((nprobes, self.N), dtype=torch.complex128, device="cuda")
         self._check(lib().lqt_probes(self._h, ctypes.c_uint64(seed), int(j0), int(nprobes), _ptr(out)))
+        return out
+
+    def partition_probes(self, seed, nvec, hp_vectors, dilute, p0=0):
+        """Partition probe vectors p0 .. p0+nvec-1 of trace(..., hp_vectors, dilute)."""
+        out = torch.empty((nvec, self.N), dtype=torch.complex128, device="cuda")
+        self._check(lib().lqt_partition_probes(self._h, ctypes.c_uint64(seed), int(p0), int(nvec), int(hp_vectors),
+                                               int(bool(dilute)), _ptr(out)))
         return out
 
     def tune(self, prec, nrhs, return_tile=False):

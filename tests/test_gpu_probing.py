@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import synth
-from oracle import dense, estimator, probing, prolongator as pr
+from oracle import core, dense, estimator, probing, prolongator as pr
 
 pytestmark = pytest.mark.gpu
 
@@ -158,3 +158,28 @@ def test_probing_argument_checks(gpu, op):
     r = c.trace(1, 1, 1e-8, hp_vectors=16, dilute=True)
     assert r["nsolves"] == 192
     c.close()
+
+
+@pytest.mark.parametrize("dims,hp,dilute,p0,nvec", [((16, 16, 16, 32), 16, True, 190, 5),
+                                                     ((16, 16, 16, 32), 256, False, 1000, 3),
+                                                     ((32, 32, 32, 64), 32, True, 7, 3)])
+def test_partition_probes_bit_exact_at_full_size(gpu, dims, hp, dilute, p0, nvec):
+    """The device generator of the partition vectors against the oracle's vectors of the same
+    draws, bit for bit, at the benchmark lattices (levels 1 and 2 of the nested colourings, a
+    range that straddles two draws)."""
+    lq = gpu
+    print(f"partition probes dims={dims} hp={hp} dilute={dilute}", flush=True)
+    c = lq.Context(dims, 0.1)
+    seed = 1050
+    got = c.partition_probes(seed, nvec, hp, dilute, p0=p0).cpu().numpy()
+    c.close()
+    nd = 12 if dilute else 1
+    q = hp * nd
+    for f in range(nvec):
+        j, r = divmod(p0 + f, q)
+        m, cc = divmod(r, nd)
+        # row r of probing.partition_vectors(seed, j, dims, hp, dilute), built alone
+        ref = np.repeat(probing.hp_sign(dims, m), 12) * core.probes(seed, 1, got.shape[1], j0=j)[0]
+        if dilute:
+            ref = np.where(np.arange(got.shape[1]) % 12 == cc, ref, 0.0)
+        assert np.array_equal(got[f].real, ref) and not np.any(got[f].imag)
