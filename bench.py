@@ -53,6 +53,8 @@ def parse():
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration) and exit")
     ap.add_argument("--inner-prec", choices=["f32", "f16", "bf16"], default=None,
                     help="override the workload's inner storage precision")
+    ap.add_argument("--no-orth-bound", action="store_true",
+                    help="multigrid workload: skip the orthogonal-projector variance (the lower bound of Section 2.1)")
     ap.add_argument("--mass", type=float, default=None, help="override the workload's bare mass (conditioning scans)")
     ap.add_argument("--basis-iters", type=int, default=400,
                     help="cap on the filtered iterations of the A g5 eigensolver before the timed region (it stops "
@@ -385,6 +387,16 @@ def run_mg(a, w):
     elapsed = time.perf_counter() - t0
     kt = ctx.kernel_times(mode=3)
     ok = sum(r["nsolves"] - r["nfailed"] for r in results)
+    # the orthogonal projector onto the same span W U_c on the same probes: the rough lower
+    # bound of Section 2.1 for the variance of any projector of this rank (untimed; its t0
+    # takes k more solves)
+    r_orth = None
+    if not a.no_orth_bound:
+        t_orth = time.perf_counter()
+        r_orth = ctx.trace(nprobes, w["probe_seed"], w["xi"], basis=basis, projector=lq.ORTH, max_batch=w["batch"],
+                           **solver)
+        torch.cuda.synchronize()
+        t_orth = time.perf_counter() - t_orth
     bpr = {0: 8, 1: 4, 2: 2, 3: 2}[prec]
     pr_ms, pr_calls, pr_b = kt["prolongator"]
     pr_gbs = pr_b / (pr_ms * 1e-3) / 1e9 if pr_ms > 0 else None
@@ -412,6 +424,9 @@ def run_mg(a, w):
                                 "jackknife_err": float(curve[0, 2])},
         "variance_ratio_undeflated_over_deflated": round(float(curve[0, 1]) / last["var_sample"], 4),
         "rank_min_var": {"rank": int(np.argmin(curve[:, 1])), "var_sample": float(np.min(curve[:, 1]))},
+        "estimate_orthogonal_projector": ({"trace": r_orth["trace_re"], "var_sample": r_orth["var_sample"],
+                                           "jackknife_err": r_orth["jackknife_err"], "nfailed": r_orth["nfailed"],
+                                           "seconds": round(t_orth, 1)} if r_orth else None),
         "setup_s": round(t_setup, 2),
         "basis_s": round(t_basis, 2),
         "basis_min_abs_lambda": float(np.min(np.abs(lam))),
