@@ -9,6 +9,11 @@ an array of shape (nagg, 2, nv, d), d = 6 * sites per block, with local index
 e = bs * 6 + s2 * 3 + colour (bs = site inside the block with x fastest, spin = 2 c + s2),
 and the coarse index (a, c, v) flattened in that order.  Fine vectors use the canonical
 index 12 * site + 3 * spin + colour.
+
+Second level (Table 2: blocks of the coarse lattice): the level-1 coarse lattice (one site per
+aggregate, x fastest) is blocked again; a level-2 block (A, c) gathers the chirality-c entries
+(a1, c, v1) of its level-1 sites, local index e = ls * nv1 + v1 (ls = site inside the block,
+x fastest), so W2 has shape (nagg2, 2, nv2, bsites2 * nv1) and g5^{W1} W2 = W2 g5^{W2}.
 """
 import numpy as np
 
@@ -42,10 +47,25 @@ def fine_index(dims, block):
     return idx
 
 
-def block_orthonormalize(Y, dims, block):
+def coarse_fine_index(cdims, block2, nv1):
+    """idx[A, c, e]: level-1 coarse index (a1 * 2 + c) * nv1 + v1 of entry e = ls * nv1 + v1
+    of level-2 block (A, c)."""
+    site = aggregates(cdims, block2)
+    nagg2, bs2 = site.shape
+    idx = np.empty((nagg2, 2, bs2 * nv1), dtype=np.int64)
+    for c in range(2):
+        for ls in range(bs2):
+            for v1 in range(nv1):
+                idx[:, c, ls * nv1 + v1] = (site[:, ls] * 2 + c) * nv1 + v1
+    return idx
+
+
+def block_orthonormalize(Y, dims, block, idx=None):
     """W from fine vectors Y (nv, N): restrict each vector to every (aggregate, chirality)
-    block and run modified Gram-Schmidt twice inside the block."""
-    idx = fine_index(dims, block)
+    block and run modified Gram-Schmidt twice inside the block (idx: the blocks' index map,
+    default the fine lattice's; coarse_fine_index for the second level)."""
+    if idx is None:
+        idx = fine_index(dims, block)
     nagg, _, d = idx.shape
     nv = Y.shape[0]
     W = np.empty((nagg, 2, nv, d), dtype=np.complex128)
@@ -62,11 +82,14 @@ def block_orthonormalize(Y, dims, block):
     return W
 
 
-def dense_prolongator(W, dims, block):
-    """P as an N x nc matrix (columns = prolongated unit coarse vectors)."""
-    idx = fine_index(dims, block)
+def dense_prolongator(W, dims, block, idx=None, N=None):
+    """P as an N x nc matrix (columns = prolongated unit coarse vectors); idx and N for the
+    second level (coarse_fine_index, N = nc1)."""
+    if idx is None:
+        idx = fine_index(dims, block)
     nagg, _, nv, d = W.shape
-    N = 12 * int(np.prod(dims))
+    if N is None:
+        N = 12 * int(np.prod(dims))
     P = np.zeros((N, nagg * 2 * nv), dtype=np.complex128)
     for a in range(nagg):
         for c in range(2):

@@ -160,3 +160,60 @@ def test_aggregate_geometry_free_field_coarse_stencil():
                 Ps[idx[a, c], (a * 2 + c) * 6 + v] = W[a, c, v]
     Acs = Ps.conj().T @ core.apply(U, dims, m, core.OP_A, Ps.T.copy()).T
     assert np.max(np.abs(Acs - ref)) > 1e-2
+
+
+def _two_level(dims, block1, nv1, block2, nv2, m=0.1, seed=4):
+    from oracle import core as _core
+    U = synth.su3_links(dims, 0.4, seed)
+    rng = np.random.default_rng(seed)
+    N = 12 * int(np.prod(dims))
+    W1 = pr.block_orthonormalize(rng.standard_normal((nv1, N)) + 1j * rng.standard_normal((nv1, N)), dims, block1)
+    P1 = pr.dense_prolongator(W1, dims, block1)
+    Dc = P1.conj().T @ _core.apply(U, dims, m, _core.OP_A, P1.T.copy()).T
+    cdims = tuple(L // b for L, b in zip(dims, block1))
+    idx2 = pr.coarse_fine_index(cdims, block2, nv1)
+    nc1 = P1.shape[1]
+    W2 = pr.block_orthonormalize(rng.standard_normal((nv2, nc1)) + 1j * rng.standard_normal((nv2, nc1)), cdims, block2,
+                                 idx=idx2)
+    P2 = pr.dense_prolongator(W2, cdims, block2, idx=idx2, N=nc1)
+    return U, W1, P1, Dc, cdims, W2, P2
+
+
+def test_second_level_blocks_orthonormal_and_chirality_split():
+    """Level-2 blocks of the coarse lattice: W2^+ W2 = I per block, P2^+ P2 = I, and
+    g5^{W1} P2 = P2 g5^{W2} (a block holds one chirality of the level-1 coarse entries)."""
+    U, W1, P1, Dc, cdims, W2, P2 = _two_level((8, 4, 4, 4), (2, 2, 2, 2), 4, (2, 2, 2, 2), 3)
+    for a in range(W2.shape[0]):
+        for c in range(2):
+            assert np.allclose(W2[a, c].conj() @ W2[a, c].T, np.eye(3), atol=1e-12)
+    assert np.allclose(P2.conj().T @ P2, np.eye(P2.shape[1]), atol=1e-12)
+    g1 = pr.coarse_g5(W1.shape[0], 4)
+    g2 = pr.coarse_g5(W2.shape[0], 3)
+    assert np.allclose(g1[:, None] * P2, P2 * g2[None, :], atol=0)
+    # every level-1 coarse entry is covered exactly once by the level-2 index map
+    idx2 = pr.coarse_fine_index(cdims, (2, 2, 2, 2), 4)
+    assert np.array_equal(np.sort(idx2.ravel()), np.arange(P1.shape[1]))
+
+
+def test_second_level_operator_is_a_nine_point_g5_hermitian_stencil():
+    """D_cc = P2^+ D_c P2: g5^{W2} D_cc is Hermitian, and with 4 level-2 blocks along x the
+    blocks two apart do not couple (D_c couples only neighbouring level-1 sites, and level-2
+    blocks two apart share no level-1 neighbours); the product P1 P2 is an orthonormal
+    chirality-split prolongator of the fine lattice."""
+    dims, block1, nv1, block2, nv2 = (16, 4, 4, 4), (2, 2, 2, 2), 4, (2, 2, 2, 2), 3
+    U, W1, P1, Dc, cdims, W2, P2 = _two_level(dims, block1, nv1, block2, nv2)
+    Dcc = P2.conj().T @ Dc @ P2
+    g2 = pr.coarse_g5(W2.shape[0], nv2)
+    H = g2[:, None] * Dcc
+    assert np.max(np.abs(H - H.conj().T)) <= 1e-12 * np.max(np.abs(H))
+    nb = 2 * nv2
+    assert W2.shape[0] == 4  # level-2 lattice 4 x 1 x 1 x 1
+    blk = lambda a, b: Dcc[a * nb:(a + 1) * nb, b * nb:(b + 1) * nb]
+    scale = np.max(np.abs(Dcc))
+    for a in range(4):
+        assert np.max(np.abs(blk(a, (a + 2) % 4))) <= 1e-13 * scale
+        assert np.max(np.abs(blk(a, (a + 1) % 4))) > 1e-3 * scale
+    P = P1 @ P2
+    assert np.allclose(P.conj().T @ P, np.eye(P.shape[1]), atol=1e-12)
+    g5 = np.tile(np.array([1.0] * 6 + [-1.0] * 6), P.shape[0] // 12)
+    assert np.allclose(g5[:, None] * P, P * g2[None, :], atol=1e-14)
