@@ -240,6 +240,37 @@ int lqt_basis_eig(lqt_ctx *ctx, int k, double xi, double tau, const lqt_solver_o
 int lqt_basis_prolongator(lqt_ctx *ctx, const int block[4], int nv, int k, double null_xi,
                           int null_maxit, const lqt_solver_opts *opts, lqt_basis **out);
 
+/* Algorithm 2 with two multigrid levels (Table 2: the coarse lattice of lqt_basis_prolongator
+ * blocked again, Table 3's two-level deflation space).  Level 1 is built as in
+ * lqt_basis_prolongator (nv <= 32, so its coarse operator D_c = W^+ A W is the explicit
+ * stencil).  Level 2: nv2 near-null vectors of D_c (coarse GMRES on Ae = Ay0 to null_xi or
+ * null_maxit steps), blocked on block2 blocks of the coarse lattice and split by chirality
+ * (g5^W W2 = W2 g5^{W2}), orthonormalised: W2[A][c][v2][ls * nv + v1] with ls the coarse site
+ * inside the level-2 block (x fastest).  The level-2 operator D_cc = W2^+ D_c W2 is a 9-point
+ * block stencil (2 nv2 <= 64).  Its k smallest-|lambda| eigenvectors U2 of g5^{W2} D_cc
+ * (the coarse eigensolve of lqt_basis_eig, accepted at opts->eig_xi, default null_xi) give
+ * the coarse vectors W2 U2 of the level-1 space, which are rotated as in
+ * lqt_basis_prolongator: the deflation space is X = W W2 U2.  block2 must divide the coarse
+ * lattice; 1 <= nv2 <= 32; 0 <= k <= nc2 / 8 with nc2 = 2 nv2 (coarse sites / level-2 block
+ * sites).  Returns LQT_ENOTCONV (with the basis in *out) if the level-2 pairs did not all
+ * pass. */
+int lqt_basis_prolongator2(lqt_ctx *ctx, const int block[4], int nv, const int block2[4], int nv2,
+                           int k, double null_xi, int null_maxit, const lqt_solver_opts *opts,
+                           lqt_basis **out);
+
+/* The same from caller-supplied W (as lqt_basis_prolongator_from), W2 (device, the layout
+ * above) and k level-2 coarse vectors (device, k x nc2, may be NULL with k = 0). */
+int lqt_basis_prolongator2_from(lqt_ctx *ctx, const int block[4], int nv, const double *d_w,
+                                const int block2[4], int nv2, const double *d_w2,
+                                const double *d_coarse2, int k, lqt_basis **out);
+
+/* D_cc (herm: g5^{W2} D_cc) applied to nrhs level-2 coarse vectors (device, nc2 each). */
+int lqt_coarse2_apply(lqt_ctx *ctx, lqt_basis *basis, const double *d_in, double *d_out, int nrhs,
+                      int herm);
+
+/* Copy W2 of a two-level basis to d_w2 (may be NULL) and report nc2. */
+int lqt_prolongator2_get(const lqt_basis *basis, double *d_w2, long long *nc2);
+
 /* Build a basis from k caller-supplied fine vectors (canonical complex128, device).  The
  * vectors X are used as given for the K = g5 oblique projector (Section 2.1): the library
  * forms M = X^+ g5 A X, diagonalises it and rotates U = X U_hat.  For LQT_ORTH the columns

@@ -305,8 +305,14 @@ void coarse_explicit_build(lqt_ctx* c, lqt_basis* B) {
 void coarse_explicit_apply(lqt_ctx* c, const lqt_basis* B, const double2* in, double2* out, int nrhs, bool herm) {
     if (nrhs <= 0) return;
     LQT_CHECK(B->Dc.p, LQT_ESTATE, "explicit coarse operator not built");
-    PG p = pg_of(B);
+    coarse_stencil_apply(c, pg_of(B), B->Dc.as<double2>(), in, out, nrhs, herm);
+}
+
+void coarse_stencil_apply(lqt_ctx* c, const PG& p, const double2* Dc, const double2* in, double2* out, int nrhs,
+                          bool herm) {
+    if (nrhs <= 0) return;
     const int nb = 2 * p.nv;
+    LQT_CHECK(nb <= CB_MAXNB, LQT_EINVAL, "stencil blocks larger than 64");
     const size_t lds = sizeof(double2) * ((size_t)nb * nb + (size_t)CA_R * (nb + 1));  // <= 129 KiB
     static bool lds_ok = false;  // allow more than 64 KiB of dynamic LDS per workgroup
     if (!lds_ok) {
@@ -319,11 +325,9 @@ void coarse_explicit_apply(lqt_ctx* c, const lqt_basis* B, const double2* in, do
     dim3 grid(p.nagg, (nrhs + CA_R - 1) / CA_R);
     c->timer.begin(c->stream, KT_PR);
     if (herm)
-        hipLaunchKernelGGL(k_coarse_apply<true>, grid, dim3(256), lds, c->stream, B->Dc.as<double2>(), p, in, out,
-                           nrhs);
+        hipLaunchKernelGGL(k_coarse_apply<true>, grid, dim3(256), lds, c->stream, Dc, p, in, out, nrhs);
     else
-        hipLaunchKernelGGL(k_coarse_apply<false>, grid, dim3(256), lds, c->stream, B->Dc.as<double2>(), p, in, out,
-                           nrhs);
+        hipLaunchKernelGGL(k_coarse_apply<false>, grid, dim3(256), lds, c->stream, Dc, p, in, out, nrhs);
     LQT_HIP(hipGetLastError());
     // stencil blocks once per group of right-hand sides, inputs (9 slots) and outputs once
     c->timer.end(c->stream, 16.0 * ((double)p.nagg * 9 * nb * nb * grid.y + (double)nrhs * p.nagg * nb * 10));

@@ -371,6 +371,12 @@ struct lqt_basis {
     lqt::DBuf Uc; // coarse eigenvectors (k x Nc) FP64
     lqt::DBuf Dc; // explicit coarse operator W^+ A W: [agg][9 stencil slots][2nv][2nv] FP64
     double coarse_build_s = 0;  // seconds spent building Dc
+    // second level (blocks of the coarse lattice): nv2 = 0 when absent
+    int block2[4] = {0, 0, 0, 0};
+    int nv2 = 0;
+    lqt::DBuf W2;   // [A][chi][nv2][bsites2 * nv][..] complex double
+    lqt::DBuf Dc2;  // level-2 operator W2^+ Dc W2 as a 9-point block stencil [A][slot][2nv2][2nv2]
+    double level2_build_s = 0;
 };
 
 namespace lqt {

@@ -57,6 +57,19 @@ void prolong_project_fields(lqt_ctx* c, const lqt_basis* B, const double2* Z, in
 void prolong_subtract(lqt_ctx* c, const lqt_basis* B, const double2* C, int s, double2* Z, double2* tmp);
 // LQT_EINVAL unless the coarse vectors U_c are orthonormal (orthogonal projector W U_c U_c^+ W^+)
 void prolong_check_orthonormal(lqt_ctx* c, const lqt_basis* B);
+// block modified Gram-Schmidt of nblocks blocks of p.nv vectors of p.d entries
+void block_mgs(lqt_ctx* c, double2* W, const PG& p, int nblocks);
+// a 9-point block stencil [agg][slot][nb][nb] (nb = 2 p.nv) on the lattice of aggregates of p
+void coarse_stencil_apply(lqt_ctx* c, const PG& p, const double2* Dc, const double2* in, double2* out, int nrhs,
+                          bool herm);
+// second level (level2.hip): geometry, W2 from nv2 level-1 coarse vectors Y, the level-2
+// operator, restriction / prolongation between level-1 and level-2 coarse fields
+PG pg2_of(const lqt_basis* B);
+void level2_blocks(lqt_ctx* c, lqt_basis* B, const double2* Y);
+void level2_build(lqt_ctx* c, lqt_basis* B);
+void level2_apply(lqt_ctx* c, const lqt_basis* B, const double2* in, double2* out, int nrhs, bool herm);
+void restrict2_fields(lqt_ctx* c, const lqt_basis* B, const double2* y1, double2* x2, int nrhs);
+void prolong2_fields(lqt_ctx* c, const lqt_basis* B, const double2* x2, double2* y1, int nrhs);
 void prolong_fields(lqt_ctx* c, const lqt_basis* B, const double2* coarse, double2* fine, int nrhs);
 
 }  // namespace lqt

@@ -21,6 +21,7 @@
 #include "devla.h"
 #include "eigcheb.h"
 #include "prolong.h"
+#include "twogrid.h"
 #include "solver.h"
 
 using lqt::DBuf;
@@ -110,6 +111,11 @@ __global__ __launch_bounds__(256) void k_block_mgs(double2* __restrict__ W, PG p
             }
             __syncthreads();
         }
+}
+
+void block_mgs(lqt_ctx* c, double2* W, const PG& p, int nblocks) {
+    hipLaunchKernelGGL(k_block_mgs, dim3(nblocks), dim3(256), 0, c->stream, W, p);
+    LQT_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------- restrict / prolong
@@ -629,6 +635,192 @@ int lqt_prolong(lqt_ctx* c, const lqt_basis* B, const double* coarse, double* fi
         lqt::from_device_layout(c, f.as<double2>(), (double2*)fine, nrhs);
         LQT_HIP(hipStreamSynchronize(c->stream));
     });
+}
+
+// ---- second multigrid level
+static void check_level2(const lqt_basis* B, const int* block2, int nv2) {
+    LQT_CHECK(block2, LQT_EINVAL, "null level-2 block");
+    const lqt::PG p = lqt::pg_of(B);
+    const int n[4] = {p.n0, p.n1, p.n2, p.n3};
+    for (int i = 0; i < 4; i++)
+        LQT_CHECK(block2[i] >= 1 && n[i] % block2[i] == 0, LQT_EINVAL,
+                  "level-2 block extents must divide the coarse lattice");
+    const int bs2 = block2[0] * block2[1] * block2[2] * block2[3];
+    LQT_CHECK(2 * B->nv <= 64, LQT_EINVAL, "the second level needs the explicit coarse operator (nv <= 32)");
+    LQT_CHECK(nv2 >= 1 && nv2 <= 32 && nv2 <= bs2 * B->nv, LQT_EINVAL, "nv2 must be in 1..min(32, level-2 block entries)");
+}
+
+static void level2_setup(lqt_ctx* c, lqt_basis* B, const int* block2, int nv2) {
+    for (int i = 0; i < 4; i++) B->block2[i] = block2[i];
+    B->nv2 = nv2;
+}
+
+// Algorithm 2's second and third steps on the level-2 operator: the k eigenpairs of
+// g5^{W2} D_cc with smallest |lambda|, prolongated to the level-1 coarse space, then the
+// rotation of the coarse vectors.  Returns the number of pairs that passed.
+static int level2_eig(lqt_ctx* c, lqt_basis* B, int k, double xi, const lqt::SolveOpts& o) {
+    const lqt::PG q = lqt::pg2_of(B);
+    const long long nc1 = 2LL * B->nagg * B->nv, nc2 = 2LL * q.nagg * q.nv;
+    lqt::HermOp H = [c, B](const double2* in, double2* o2, int nf) { lqt::level2_apply(c, B, in, o2, nf, true); };
+    DBuf Qb;
+    std::vector<double> theta, resT;
+    const int conv = lqt::eig_chebyshev(c, nc2, H, nullptr, lqt::wilson_norm_bound(c), k, xi, o.outer_maxit,
+                                        o.eig_degree, o.verbose, Qb, theta, resT);
+    DBuf Ub;
+    Ub.ensure(sizeof(double2) * (size_t)k * nc1);
+    lqt::prolong2_fields(c, B, Qb.as<double2>(), Ub.as<double2>(), k);
+    lqt::coarse_oblique_setup(c, B, Ub.as<double2>(), k);
+    B->theta.assign(theta.begin(), theta.begin() + k);
+    B->resid.assign(resT.begin(), resT.begin() + k);
+    return conv;
+}
+
+int lqt_basis_prolongator2(lqt_ctx* c, const int block[4], int nv, const int block2[4], int nv2, int k,
+                           double null_xi, int null_maxit, const lqt_solver_opts* opts, lqt_basis** out) {
+    if (!c || !out) return LQT_EINVAL;
+    *out = nullptr;
+    return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
+        LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
+        lqt::check_block(c, block, nv);
+        LQT_CHECK(null_xi > 0 && null_xi < 1 && null_maxit >= 1, LQT_EINVAL, "bad null-vector tolerance");
+        lqt_basis* B = new_prolongator(c, block, nv);
+        try {
+            check_level2(B, block2, nv2);
+            level2_setup(c, B, block2, nv2);
+            const lqt::PG q = lqt::pg2_of(B);
+            const long long nc2 = 2LL * q.nagg * nv2;
+            LQT_CHECK(k >= 0 && k <= nc2 / 8, LQT_EINVAL, "k must be in 0..nc2/8");
+            lqt::SolveOpts o = lqt::make_opts(opts);
+            const long long n = 12LL * c->g.V;
+            const long long nc1 = 2LL * B->nagg * nv;
+            // level 1: near-null vectors of A, W, the explicit coarse operator
+            {
+                lqt::SolveOpts on = o;
+                on.maxit = null_maxit;
+                DBuf Y0, AY, E;
+                Y0.ensure(sizeof(double2) * (size_t)nv * n);
+                AY.ensure(sizeof(double2) * (size_t)nv * n);
+                E.ensure(sizeof(double2) * (size_t)nv * n);
+                lqt::gaussian_fields(c, 0x4E554C4Cull, n, nv, Y0.as<double2>());
+                lqt::dslash(c, LQT_F64, LQT_A, Y0.p, AY.p, nv, n, n);
+                std::vector<lqt_solve_stats> st(nv);
+                lqt::solve_fields(c, AY.as<double2>(), E.as<double2>(), nv, null_xi, on, st.data());
+                hipLaunchKernelGGL(lqt::k_sub, lqt::g1((long long)nv * n), dim3(256), 0, c->stream, Y0.as<double2>(),
+                                   E.as<double2>(), (long long)nv * n);
+                LQT_HIP(hipGetLastError());
+                lqt::PG p = lqt::make_pg(c, block, nv);
+                long long tot = (long long)p.nagg * 2 * nv * p.d;
+                hipLaunchKernelGGL(lqt::k_gather_null, lqt::g1(tot), dim3(256), 0, c->stream, E.as<double2>(), p,
+                                   B->W.as<double2>());
+                lqt::block_mgs(c, B->W.as<double2>(), p, p.nagg * 2);
+                lqt::coarse_explicit_build(c, B);
+            }
+            // level 2: near-null vectors of D_c (coarse GMRES to null_xi or null_maxit steps), W2,
+            // the level-2 operator
+            {
+                DBuf Y0, AY, E;
+                Y0.ensure(sizeof(double2) * (size_t)nv2 * nc1);
+                AY.ensure(sizeof(double2) * (size_t)nv2 * nc1);
+                E.ensure(sizeof(double2) * (size_t)nv2 * nc1);
+                lqt::gaussian_fields(c, 0x4E554C32ull, nc1, nv2, Y0.as<double2>());
+                lqt::coarse_explicit_apply(c, B, Y0.as<double2>(), AY.as<double2>(), nv2, false);
+                const double rel = lqt::coarse_gmres(c, B, AY.as<double2>(), E.as<double2>(), nv2, null_xi, null_maxit);
+                hipLaunchKernelGGL(lqt::k_sub, lqt::g1((long long)nv2 * nc1), dim3(256), 0, c->stream, Y0.as<double2>(),
+                                   E.as<double2>(), (long long)nv2 * nc1);
+                LQT_HIP(hipGetLastError());
+                lqt::level2_blocks(c, B, E.as<double2>());
+                lqt::level2_build(c, B);
+                if (o.verbose) {
+                    fprintf(stderr,
+                            "[lqtrace] prolongator: level 1 operator built in %.2f s; %d level-2 near-null vectors "
+                            "(coarse relative residual %.2e); level-2 operator built in %.2f s\n",
+                            B->coarse_build_s, nv2, rel, B->level2_build_s);
+                    fflush(stderr);
+                }
+            }
+            if (k > 0) {
+                const double exi = o.eig_xi > 0 ? o.eig_xi : null_xi;
+                const int conv = level2_eig(c, B, k, exi, o);
+                LQT_HIP(hipStreamSynchronize(c->stream));
+                *out = B;
+                if (conv < k) {
+                    c->err = "level-2 eigensolver: " + std::to_string(conv) + " of " + std::to_string(k) +
+                             " pairs converged";
+                    throw Error{LQT_ENOTCONV, c->err};
+                }
+                return;
+            }
+            LQT_HIP(hipStreamSynchronize(c->stream));
+        } catch (const Error& e) {
+            if (*out == nullptr) delete B;
+            throw;
+        }
+        *out = B;
+    });
+}
+
+int lqt_basis_prolongator2_from(lqt_ctx* c, const int block[4], int nv, const double* d_w, const int block2[4],
+                                int nv2, const double* d_w2, const double* d_coarse2, int k, lqt_basis** out) {
+    if (!c || !out) return LQT_EINVAL;
+    *out = nullptr;
+    return guard(c, [&] {
+        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "not available for a context of several lattices");
+        LQT_CHECK(c->have_gauge, LQT_ESTATE, "no gauge field set (call lqt_set_gauge)");
+        lqt::check_block(c, block, nv);
+        LQT_CHECK(d_w && d_w2, LQT_EINVAL, "null prolongator");
+        LQT_CHECK(k >= 0 && (k == 0 || d_coarse2), LQT_EINVAL, "level-2 coarse vectors missing");
+        lqt_basis* B = new_prolongator(c, block, nv);
+        try {
+            check_level2(B, block2, nv2);
+            level2_setup(c, B, block2, nv2);
+            const lqt::PG q = lqt::pg2_of(B);
+            const long long nc1 = 2LL * B->nagg * nv, nc2 = 2LL * q.nagg * nv2;
+            LQT_CHECK(k <= nc2, LQT_EINVAL, "k must be at most nc2");
+            LQT_HIP(hipMemcpyAsync(B->W.p, d_w, sizeof(double2) * (size_t)nv * 12 * c->g.V, hipMemcpyDeviceToDevice,
+                                   c->stream));
+            lqt::coarse_explicit_build(c, B);
+            const size_t w2 = (size_t)q.nagg * 2 * nv2 * q.d;
+            B->W2.ensure(sizeof(double2) * w2);
+            LQT_HIP(hipMemcpyAsync(B->W2.p, d_w2, sizeof(double2) * w2, hipMemcpyDeviceToDevice, c->stream));
+            lqt::level2_build(c, B);
+            if (k > 0) {
+                DBuf Ub;
+                Ub.ensure(sizeof(double2) * (size_t)k * nc1);
+                lqt::prolong2_fields(c, B, (const double2*)d_coarse2, Ub.as<double2>(), k);
+                lqt::coarse_oblique_setup(c, B, Ub.as<double2>(), k);
+            }
+            (void)nc2;
+            LQT_HIP(hipStreamSynchronize(c->stream));
+        } catch (...) {
+            delete B;
+            throw;
+        }
+        *out = B;
+    });
+}
+
+int lqt_coarse2_apply(lqt_ctx* c, lqt_basis* B, const double* d_in, double* d_out, int nrhs, int herm) {
+    if (!c || !B) return LQT_EINVAL;
+    return guard(c, [&] {
+        LQT_CHECK(B->kind == 1 && B->nv2 > 0 && B->Dc2.p, LQT_EINVAL, "not a two-level prolongator basis");
+        LQT_CHECK(nrhs >= 0 && (nrhs == 0 || (d_in && d_out)), LQT_EINVAL, "bad level-2 apply arguments");
+        lqt::level2_apply(c, B, (const double2*)d_in, (double2*)d_out, nrhs, herm != 0);
+        LQT_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+int lqt_prolongator2_get(const lqt_basis* B, double* d_w2, long long* nc2) {
+    if (!B || B->kind != 1 || B->nv2 == 0) return LQT_EINVAL;
+    const lqt::PG q = lqt::pg2_of(B);
+    if (nc2) *nc2 = 2LL * q.nagg * q.nv;
+    if (d_w2) {
+        if (hipMemcpyAsync(d_w2, B->W2.p, sizeof(double2) * (size_t)q.nagg * 2 * q.nv * q.d, hipMemcpyDeviceToDevice,
+                           B->ctx->stream) != hipSuccess)
+            return LQT_EHIP;
+        if (hipStreamSynchronize(B->ctx->stream) != hipSuccess) return LQT_EHIP;
+    }
+    return LQT_OK;
 }
 
 int lqt_prolongator_get(const lqt_basis* B, double* d_w, long long* nc) {

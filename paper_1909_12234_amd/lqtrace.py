@@ -106,6 +106,10 @@ _SIGS = {
     "lqt_prolong": ([_P, _P, _P, _P, _I], _I),
     "lqt_prolongator_get": ([_P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
     "lqt_coarse_apply": ([_P, _P, _P, _P, _I, _I], _I),
+    "lqt_basis_prolongator2": ([_P, _P, _I, _P, _I, _I, _D, _I, _P, ctypes.POINTER(_P)], _I),
+    "lqt_basis_prolongator2_from": ([_P, _P, _I, _P, _P, _I, _P, _P, _I, ctypes.POINTER(_P)], _I),
+    "lqt_coarse2_apply": ([_P, _P, _P, _P, _I, _I], _I),
+    "lqt_prolongator2_get": ([_P, _P, ctypes.POINTER(ctypes.c_longlong)], _I),
     "lqt_basis_prolongator_from": ([_P, _P, _I, _P, _P, _I, ctypes.POINTER(_P)], _I),
     "lqt_tune": ([_P, _I, _I, ctypes.POINTER(_D), _P], _I),
     "lqt_set_tile": ([_P, _I, _I, _P], _I),
@@ -381,6 +385,36 @@ class Context:
                                                      ctypes.byref(h)))
         return Basis(self, h, nv=nv)
 
+    def basis_prolongator2(self, block, nv, block2, nv2, k, null_xi=1e-2, null_maxit=200, require_converged=False,
+                           **opts):
+        """Algorithm 2 with two multigrid levels (lqt_basis_prolongator2)."""
+        h = ctypes.c_void_p()
+        o = _opts(**opts)
+        b1 = (ctypes.c_int * 4)(*block)
+        b2 = (ctypes.c_int * 4)(*block2)
+        rc = lib().lqt_basis_prolongator2(self._h, b1, int(nv), b2, int(nv2), int(k), float(null_xi), int(null_maxit),
+                                          ctypes.byref(o), ctypes.byref(h))
+        self._check(rc, allow=() if require_converged else (LQT_ENOTCONV,))
+        if not h:
+            raise LqtError(rc, lib().lqt_last_error(self._h).decode())
+        bas = Basis(self, h, nv=nv, nv2=nv2)
+        bas.converged = rc == 0
+        return bas
+
+    def basis_prolongator2_from(self, block, nv, W, block2, nv2, W2, coarse2=None):
+        h = ctypes.c_void_p()
+        b1 = (ctypes.c_int * 4)(*block)
+        b2 = (ctypes.c_int * 4)(*block2)
+        W = _dev(W, torch.complex128, self.N * int(nv), "prolongator W")
+        if W.numel() != self.N * int(nv):
+            raise ValueError("prolongator W must hold nv * N entries")
+        W2 = _dev(W2, torch.complex128, 0, "level-2 prolongator W2")
+        k = 0 if coarse2 is None else coarse2.shape[0]
+        cv = None if coarse2 is None else _dev(coarse2, torch.complex128, 0, "level-2 coarse vectors")
+        self._check(lib().lqt_basis_prolongator2_from(self._h, b1, int(nv), _ptr(W), b2, int(nv2), _ptr(W2), _ptr(cv),
+                                                      int(k), ctypes.byref(h)))
+        return Basis(self, h, nv=nv, nv2=nv2)
+
     def basis_from_vectors(self, X):
         h = ctypes.c_void_p()
         X = _dev(X, torch.complex128, self.N, "basis vectors")
@@ -500,10 +534,11 @@ class Context:
 
 
 class Basis:
-    def __init__(self, ctx, handle, nv=0):
+    def __init__(self, ctx, handle, nv=0, nv2=0):
         self.ctx = ctx
         self._h = handle
         self.nv = nv
+        self.nv2 = nv2
         k = ctypes.c_int(0)
         ctx._check(lib().lqt_basis_eigenvalues(self._h, None, ctypes.byref(k)))
         self.k = k.value
@@ -546,6 +581,27 @@ class Basis:
         self.ctx._check(lib().lqt_coarse_apply(self.ctx._h, self._h, _ptr(coarse), _ptr(out),
                                                coarse.numel() // nc.value, int(bool(herm))))
         return out
+
+    def coarse2_apply(self, x, herm=False):
+        """The level-2 operator W2^+ W^+ A W W2 (g5^{W2} times it with herm) on level-2 vectors."""
+        nc2 = ctypes.c_longlong(0)
+        self.ctx._check(lib().lqt_prolongator2_get(self._h, None, ctypes.byref(nc2)))
+        x = _dev(x, torch.complex128, nc2.value, "level-2 input")
+        out = torch.empty_like(x)
+        self.ctx._check(lib().lqt_coarse2_apply(self.ctx._h, self._h, _ptr(x), _ptr(out), x.numel() // nc2.value,
+                                                int(bool(herm))))
+        return out
+
+    def prolongator2(self):
+        """W2 as a flat complex128 device tensor (layout in the header)."""
+        nc2 = ctypes.c_longlong(0)
+        self.ctx._check(lib().lqt_prolongator2_get(self._h, None, ctypes.byref(nc2)))
+        nc = ctypes.c_longlong(0)
+        self.ctx._check(lib().lqt_prolongator_get(self._h, None, ctypes.byref(nc)))
+        # every level-1 coarse entry belongs to one level-2 block and chirality: nv2 * nc1 entries
+        W2 = torch.empty(self.nv2 * nc.value, dtype=torch.complex128, device="cuda")
+        self.ctx._check(lib().lqt_prolongator2_get(self._h, _ptr(W2), ctypes.byref(nc2)))
+        return W2
 
     def prolongator(self):
         """W as a flat complex128 device tensor of nv*N entries (layout in the header)."""
