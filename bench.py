@@ -365,8 +365,12 @@ def run_mg(a, w):
     solver = dict(prec=prec, restart=w["restart"], sstep=w["sstep"])
     ctx.kernel_times(mode=2)
     t_basis = time.perf_counter()
-    basis = ctx.basis_prolongator(w["block"], w["nv"], w["k"], null_xi=1e-2, null_maxit=200, verbose=1,
-                                  outer_maxit=a.basis_iters, **solver)
+    if "block2" in w:
+        basis = ctx.basis_prolongator2(w["block"], w["nv"], w["block2"], w["nv2"], w["k"], null_xi=1e-2,
+                                       null_maxit=200, verbose=1, outer_maxit=a.basis_iters, **solver)
+    else:
+        basis = ctx.basis_prolongator(w["block"], w["nv"], w["k"], null_xi=1e-2, null_maxit=200, verbose=1,
+                                      outer_maxit=a.basis_iters, **solver)
     torch.cuda.synchronize()
     t_basis = time.perf_counter() - t_basis
     kt_setup = ctx.kernel_times(mode=3)
@@ -438,12 +442,14 @@ def run_mg(a, w):
         "cpu_baseline": None,
         "cpu_baseline_note": "the oracle is timed on the 16^3x32 workload's line only",
     }
+    lvl2 = (f", second level {w['block2'][0]}^4 blocks of the coarse lattice with nv2={w['nv2']}"
+            if "block2" in w else "")
     config = {"workload": f"{a.workload}: Wilson-Dirac {dims[0]}^3x{dims[3]}, eps={eps}, m={mass}, {nprobes} "
                           f"Rademacher probes, xi={w['xi']}, oblique g5 deflation on X = W U_c: {w['block'][0]}^4 "
-                          f"aggregates, nv={w['nv']} per chirality, k={w['k']} coarse eigenvectors, s-step "
+                          f"aggregates, nv={w['nv']} per chirality{lvl2}, k={w['k']} coarse eigenvectors, s-step "
                           f"GMRES({w['restart']}) in batches of {w['batch']}",
               "lattice": list(dims), "probes": nprobes, "block": list(w["block"]), "nv": w["nv"],
-              "deflation_rank": w["k"], "batch": w["batch"]}
+              "deflation_rank": w["k"], "batch": w["batch"], "levels": 2 if "block2" in w else 1}
     _line(a, ok / elapsed, elapsed, w["inner_prec"], config, extra, metric=MG_METRIC)
 
 

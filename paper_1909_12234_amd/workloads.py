@@ -34,6 +34,12 @@ WORKLOADS = {
     "wilson32x64_mg": dict(dims=(32, 32, 32, 64), eps=0.5, seed=1, mass=-1.90, nprobes=256, probe_seed=1004,
                            xi=1e-8, block=(4, 4, 4, 4), nv=24, k=256, inner_prec="f16", restart=15, sstep=1,
                            batch=32),
+    # the same with a second multigrid level (Table 2: 2^4 blocks of the 8^3x16 coarse lattice,
+    # 32 near-null vectors of the coarse operator per chirality, nc2 = 32768); the k = 256
+    # coarse eigenvectors come from the level-2 operator (Table 3's two-level deflation space)
+    "wilson32x64_mg2": dict(dims=(32, 32, 32, 64), eps=0.5, seed=1, mass=-1.90, nprobes=256, probe_seed=1004,
+                            xi=1e-8, block=(4, 4, 4, 4), nv=24, block2=(2, 2, 2, 2), nv2=32, k=256, inner_prec="f16",
+                            restart=15, sstep=1, batch=32),
 }
 
 PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
