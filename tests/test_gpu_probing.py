@@ -183,3 +183,33 @@ def test_partition_probes_bit_exact_at_full_size(gpu, dims, hp, dilute, p0, nvec
         if dilute:
             ref = np.where(np.arange(got.shape[1]) % 12 == cc, ref, 0.0)
         assert np.array_equal(got[f].real, ref) and not np.any(got[f].imag)
+
+
+def test_partitioned_trace_at_the_benchmark_size(gpu):
+    """16^3x32 at the headline operator, FP16 s-step GMRES(15): one draw of red-black probing
+    with dilution (24 solves).  The draw's sample equals (1/2) sum_v v^T y_v over the library's
+    own solutions of the same vectors (same batch, bitwise-identical solves), the oracle
+    recomputes every solution's FP64 residual (<= xi) and forms the dot products itself."""
+    from paper_1909_12234_amd.workloads import PREC, WORKLOADS
+
+    lq = gpu
+    w = WORKLOADS["wilson16x32_mixed"]
+    dims, m, xi = w["dims"], w["mass"], w["xi"]
+    prec = PREC[w["inner_prec"]]
+    print("partition trace at 16^3x32", flush=True)
+    U = synth.su3_links(dims, w["eps"], w["seed"])
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    c.tune(prec, 24)
+    seed, hp = 1070, 2
+    r = c.trace(1, seed, xi, samples=True, hp_vectors=hp, dilute=True, prec=prec, restart=w["restart"],
+                sstep=w["sstep"])
+    V = c.partition_probes(seed, 24, hp, True)
+    y, st, _ = c.solve(V, xi, prec=prec, restart=w["restart"], sstep=w["sstep"])
+    c.close()
+    assert r["nfailed"] == 0 and all(s[0] for s in st)
+    Vh, yh = V.cpu().numpy(), y.cpu().numpy()
+    res = Vh - core.apply(U, dims, m, core.OP_A, yh)
+    assert np.max(np.linalg.norm(res, axis=1) / np.linalg.norm(Vh, axis=1)) <= xi * 1.05
+    t = np.sum(Vh.real * yh, axis=1).sum() / hp
+    assert abs(r["samples"].numpy()[0] - t) <= 1e-9 * abs(t)
