@@ -435,7 +435,8 @@ int lqt_probes(lqt_ctx *ctx, uint64_t seed, long long j0, int nprobes, double *d
 
 /* Write the partition probe vectors p0 .. p0+nvec-1 of lqt_trace_probing (vector
  * p = j q + m nd + c of draw j, q = hp_vectors nd, nd = 12 with dilution, else 1) as
- * canonical complex128 fields (device).  Single-lattice contexts. */
+ * canonical complex128 fields (device).  hp_vectors, dilute and the lattice must be valid as
+ * for lqt_trace_probing (LQT_EINVAL otherwise); single-lattice contexts. */
 int lqt_partition_probes(lqt_ctx *ctx, uint64_t seed, long long p0, int nvec, int hp_vectors,
                          int dilute, double *d_out);
 

@@ -213,10 +213,7 @@ int lqt_partition_probes(lqt_ctx* c, uint64_t seed, long long p0, int nvec, int 
     if (!c) return LQT_EINVAL;
     return guard(c, [&] {
         LQT_CHECK(nvec >= 0 && p0 >= 0, LQT_EINVAL, "bad vector range");
-        LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "partition probes serve single-lattice contexts");
-        LQT_CHECK(dilute == 0 || dilute == 1, LQT_EINVAL, "dilute must be 0 or 1");
-        LQT_CHECK(hp_vectors >= 1 && hp_vectors <= (1 << 20) && !(hp_vectors & (hp_vectors - 1)), LQT_EINVAL,
-                  "hp_vectors must be a power of two");
+        lqt::check_partition(c, hp_vectors, dilute);
         if (nvec == 0) return;
         LQT_CHECK(out, LQT_EINVAL, "null output");
         const long long n = 12LL * c->g.V;

@@ -10,6 +10,8 @@ void probes_gen(lqt_ctx* c, uint64_t seed, long long j0, int nprobes, double2* o
 // partition probe vectors p0 .. p0+nvec-1 (hp probing signs, dilution into the 12
 // spin-colour components when dilute) of a single-lattice context
 void partition_probes_gen(lqt_ctx* c, uint64_t seed, long long p0, int nvec, int hp, int dilute, double2* out);
+// LQT_EINVAL unless (hp_vectors, dilute) is a valid partition for the context's lattice
+void check_partition(const lqt_ctx* c, int hp_vectors, int dilute);
 // z_j^T y_j for nprobes fields; per_lattice: out_dev[j * nlat + k] over the sites of lattice k
 void probe_dots(lqt_ctx* c, uint64_t seed, long long j0, const double2* y, int nprobes, double2* out_dev,
                 bool per_lattice = false);

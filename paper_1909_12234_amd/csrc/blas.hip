@@ -125,6 +125,22 @@ __global__ __launch_bounds__(256) void k_partition_probe_gen(uint64_t seed, long
             make_double2((nd == 1 || c == cc) ? sg * probe_entry(seed, (uint64_t)j, (uint64_t)(12LL * s + c)) : 0.0, 0.0);
 }
 
+void check_partition(const lqt_ctx* c, int hp_vectors, int dilute) {
+    LQT_CHECK(c->g.lat.nlat == 1, LQT_EINVAL, "partition probes serve single-lattice contexts");
+    LQT_CHECK(dilute == 0 || dilute == 1, LQT_EINVAL, "dilute must be 0 or 1");
+    LQT_CHECK(hp_vectors >= 1 && hp_vectors <= (1 << 20) && !(hp_vectors & (hp_vectors - 1)), LQT_EINVAL,
+              "hp_vectors must be a power of two (1 = no probing)");
+    // the highest level l of the nested colourings needs extents divisible by 2^(l+1)
+    int b = 0;
+    while ((1 << b) < hp_vectors) b++;
+    if (b > 0) {
+        const int m = 2 << ((b - 1) / 4);
+        for (int d = 0; d < 4; d++)
+            LQT_CHECK(c->g.L[d] % m == 0, LQT_EINVAL,
+                      std::to_string(hp_vectors) + " probing vectors need extents divisible by " + std::to_string(m));
+    }
+}
+
 void partition_probes_gen(lqt_ctx* c, uint64_t seed, long long p0, int nvec, int hp, int dilute, double2* out) {
     if (nvec <= 0) return;
     LQT_CHECK(nvec <= 65535, LQT_EINVAL, "partition probes: at most 65535 vectors per launch");

@@ -411,21 +411,7 @@ static int trace_impl(lqt_ctx* c, const lqt_basis* B, int projector, int nprobes
         LQT_CHECK(nprobes >= 1, LQT_EINVAL, "nprobes must be >= 1");
         LQT_CHECK(xi > 0 && xi < 1, LQT_EINVAL, "xi must be in (0, 1)");
         LQT_CHECK(projector == LQT_OBLIQUE_G5 || projector == LQT_ORTH, LQT_EINVAL, "bad projector");
-        LQT_CHECK(dilute == 0 || dilute == 1, LQT_EINVAL, "dilute must be 0 or 1");
-        LQT_CHECK(hp_vectors >= 1 && hp_vectors <= (1 << 20) && !(hp_vectors & (hp_vectors - 1)), LQT_EINVAL,
-                  "hp_vectors must be a power of two (1 = no probing)");
-        {
-            // the highest level l of the nested colourings needs extents divisible by 2^(l+1)
-            int b = 0;
-            while ((1 << b) < hp_vectors) b++;
-            if (b > 0) {
-                const int m = 2 << ((b - 1) / 4);
-                for (int d = 0; d < 4; d++)
-                    LQT_CHECK(c->g.L[d] % m == 0, LQT_EINVAL,
-                              std::to_string(hp_vectors) + " probing vectors need extents divisible by " +
-                                  std::to_string(m));
-            }
-        }
+        lqt::check_partition(c, hp_vectors, dilute);
         LQT_CHECK(!B || B->ctx == c, LQT_EINVAL, "basis belongs to another context");
         LQT_CHECK(!(B && projector == LQT_ORTH && B->kind == 0 && !B->orthonormal), LQT_EINVAL,
                   "the orthogonal projector needs an orthonormal fine basis (lqt_basis_eig)");
