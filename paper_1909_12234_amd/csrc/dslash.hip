@@ -267,6 +267,16 @@ struct pk_rule {
     static constexpr int cim = MU == 0 ? SG : MU == 2 ? (K == 0 ? SG : -SG) : 0;
 };
 
+// x.y of two FP16 pairs accumulated in FP32 from zero, as one three-operand instruction: the
+// compiler's tied-accumulator form of the dot product would first move 0 into the
+// destination, one extra instruction per product chain (12 per hop and right-hand side)
+__device__ __forceinline__ float dot2_from_zero(hv2 x, hv2 y) {
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "v"(__builtin_bit_cast(uint32_t, x)),
+        "v"(__builtin_bit_cast(uint32_t, y)));
+    return d;
+}
+
 template <int MU, int SG, bool BWD, int K>
 __device__ __forceinline__ void pk_half(const hv2 u[9], const hv2 p[12], cpx<float> o[3]) {
     using Rl = pk_rule<MU, SG, K>;
@@ -275,9 +285,10 @@ __device__ __forceinline__ void pk_half(const hv2 u[9], const hv2 p[12], cpx<flo
     for (int b = 0; b < 3; b++) hforms<BWD, Rl::cre, Rl::cim>(p[3 * K + b], p[3 * Rl::pb + b], f0[b], f1[b]);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        float re = 0.f, im = 0.f;
+        const hv2 l0 = BWD ? u[a] : u[3 * a];
+        float re = dot2_from_zero(l0, f0[0]), im = dot2_from_zero(l0, f1[0]);
 #pragma unroll
-        for (int b = 0; b < 3; b++) {
+        for (int b = 1; b < 3; b++) {
             const hv2 l = BWD ? u[3 * b + a] : u[3 * a + b];
             re = __builtin_amdgcn_fdot2(l, f0[b], re, false);
             im = __builtin_amdgcn_fdot2(l, f1[b], im, false);
