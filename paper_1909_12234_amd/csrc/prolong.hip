@@ -501,9 +501,12 @@ int lqt_basis_prolongator(lqt_ctx* c, const int block[4], int nv, int k, double 
         lqt::check_block(c, block, nv);
         LQT_CHECK(null_xi > 0 && null_xi < 1 && null_maxit >= 1, LQT_EINVAL, "bad null-vector tolerance");
         const long long n = 12LL * c->g.V;
+        {
+            const long long nc0 = 2LL * lqt::make_pg(c, block, nv).nagg * nv;
+            LQT_CHECK(k >= 0 && k <= nc0 / 8, LQT_EINVAL, "k must be in 0..nc/8");
+        }
         lqt_basis* B = new_prolongator(c, block, nv);
         const long long nc = 2LL * B->nagg * nv;
-        LQT_CHECK(k >= 0 && k <= nc / 8, LQT_EINVAL, "k must be in 0..nc/8");
         try {
             lqt::SolveOpts o = lqt::make_opts(opts);
             // near-null vectors: y = y0 - e, A e = A y0 to null_xi or null_maxit steps
