@@ -99,16 +99,28 @@ __global__ __launch_bounds__(256) void k_probe_part(const double2* __restrict__ 
         const long long site = ok ? kk - (long long)comp * V : 0;
         const uint64_t hi = gsm64((uint64_t)(12 * site + comp));
         const bool up = comp < 6;
+        // the step's 4 entries (one per lane quarter) lie on one side of the spin split unless
+        // they straddle 6V: then only the products of that side are formed (wave-uniform)
+        const long long split = 6LL * V;
+        const int side = (k0 + 3 < split) ? 1 : (k0 >= split ? 2 : 0);
 #pragma unroll
         for (int t = 0; t < NB; t++) {
             const int b = b0 + 16 * t + i;
             double z = 0;
             if (b < kb && ok) z = (gsm64(seed ^ gsm64((uint64_t)(j0 + b) ^ hi)) >> 63) ? -1.0 : 1.0;
-            const double zu = up ? z : 0.0, zd = up ? 0.0 : z;
-            ur[t] = mfma(xv.x, zu, ur[t]);
-            ui[t] = mfma(-xv.y, zu, ui[t]);
-            dr[t] = mfma(xv.x, zd, dr[t]);
-            di[t] = mfma(-xv.y, zd, di[t]);
+            if (side == 1) {
+                ur[t] = mfma(xv.x, z, ur[t]);
+                ui[t] = mfma(-xv.y, z, ui[t]);
+            } else if (side == 2) {
+                dr[t] = mfma(xv.x, z, dr[t]);
+                di[t] = mfma(-xv.y, z, di[t]);
+            } else {
+                const double zu = up ? z : 0.0, zd = up ? 0.0 : z;
+                ur[t] = mfma(xv.x, zu, ur[t]);
+                ui[t] = mfma(-xv.y, zu, ui[t]);
+                dr[t] = mfma(xv.x, zd, dr[t]);
+                di[t] = mfma(-xv.y, zd, di[t]);
+            }
         }
     }
 #pragma unroll
