@@ -45,8 +45,10 @@ void kry_finish(lqt_ctx* c, const double2* part, int nsb, int j, int ns, const K
 void kry_norm_givens(lqt_ctx* c, const double* part, int nsb, int j, int ns, const KryState& st);
 void kry_backsolve(lqt_ctx* c, int ns, const KryState& st);
 // s-step cycle end with the residual carried in the basis: x[act[q]] += K_s beta and
-// k_0 <- (r - A K_s beta) sqrt(N)/est; rn2[q] = |r - A K_s beta|^2 (part: ns * ceil(V/256)
-// doubles of workspace)
+// k_0 <- (r - A K_s beta) sqrt(N)/est; rn2[q] = |r - A K_s beta|^2 (part: ns *
+// kry_carry_blocks<S> doubles of workspace)
+template <typename S>
+int kry_carry_blocks(const lqt_ctx* c);
 template <typename S>
 void kry_sstep_carry(lqt_ctx* c, double2* x, const int* act, void* Kb, long long kstride, int ns, const KryState& st,
                      double theta, double sigma, double* part, double* rn2);

@@ -60,12 +60,17 @@ struct Lanes {
     static constexpr int SP = 16 / (int)sizeof(S);
 };
 
+// the 16 raw bytes, and their SP complex values (loads issued together, converted after)
+template <typename S>
+__device__ __forceinline__ uint4 ld16raw(const S* p) {
+    return *reinterpret_cast<const uint4*>(p);
+}
 template <typename S, typename C, int SP>
-__device__ __forceinline__ void ld16(const S* p, cx<C> o[SP]) {
+__device__ __forceinline__ void cvt16(uint4 r, cx<C> o[SP]) {
     if constexpr (SP == 1) {
-        o[0] = ldk<S, C>(p);
+        const double2 v = __builtin_bit_cast(double2, r);
+        o[0] = {(C)v.x, (C)v.y};
     } else {
-        const uint4 r = *reinterpret_cast<const uint4*>(p);
         const uint32_t w[4] = {r.x, r.y, r.z, r.w};
         if constexpr (sizeof(S) == 8) {  // float2 x 2
             o[0] = {(C)__uint_as_float(w[0]), (C)__uint_as_float(w[1])};
@@ -84,6 +89,10 @@ __device__ __forceinline__ void ld16(const S* p, cx<C> o[SP]) {
             }
         }
     }
+}
+template <typename S, typename C, int SP>
+__device__ __forceinline__ void ld16(const S* p, cx<C> o[SP]) {
+    cvt16<S, C, SP>(ld16raw(p), o);
 }
 
 // store SP values, return (through o) what the storage type holds after rounding
@@ -490,14 +499,41 @@ __global__ __launch_bounds__(256) void k_xupdate(double2* __restrict__ x, const 
 // (gamma_i = theta beta_i + beta_{i-1}/sigma), rho = |r|/sqrt(N) of the cycle's start.  It is
 // written over k_0 scaled by sqrt(N)/est (est: the cycle's least-squares residual norm, which
 // the next cycle takes as its |r|), so x and the next start vector come from one pass over
-// the basis.  part[q * gridDim.x + blk] = partial |r_new|^2 of the block's 256 sites.
+// the basis.  The pass is flat over the slot's 16-byte chunks of k_i (SP complex values, one
+// chunk per thread; x is read and written as the chunk's SP FP64 values) and keeps eight basis
+// vectors' loads in flight per trip.  part[q * gridDim.x + blk] = partial |r_new|^2 of the
+// block's 256 chunks.
+// U basis vectors of one carry trip: their loads are issued together, then
+// ax += sum_u bx[i+u] k_{i+u} and ak += sum_u wk[i+u] k_{i+u} in FP64, in the order of u
+template <typename S, int U, int SP>
+__device__ __forceinline__ void carry_trip(const S* kq, long long kstride, int i, const double2* bx,
+                                           const double2* wk, cx<double> ax[SP], cx<double> ak[SP]) {
+    uint4 r[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) r[u] = ld16raw(kq + (long long)(i + u) * kstride);
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        cx<double> v[SP];
+        cvt16<S, double, SP>(r[u], v);
+        const double2 b = bx[i + u], w = wk[i + u];
+#pragma unroll
+        for (int t = 0; t < SP; t++) {
+            ax[t].x += b.x * v[t].x - b.y * v[t].y;
+            ax[t].y += b.x * v[t].y + b.y * v[t].x;
+            ak[t].x += w.x * v[t].x - w.y * v[t].y;
+            ak[t].y += w.x * v[t].y + w.y * v[t].x;
+        }
+    }
+}
+
 template <typename S>
 __global__ __launch_bounds__(256) void k_sstep_carry(double2* __restrict__ x, const int* __restrict__ act,
-                                                     S* __restrict__ Kb, long long kstride, int V, KryState st,
-                                                     double theta, double sigma, double sqrtN,
+                                                     S* __restrict__ Kb, long long kstride, long long nch,
+                                                     KryState st, double theta, double sigma, double sqrtN,
                                                      double* __restrict__ part) {
+    constexpr int SP = Lanes<S>::SP;
     __shared__ double2 bx[KRY_MAXM + 1], wk[KRY_MAXM + 1];
-    __shared__ double red[256];
+    __shared__ double red[4];
     const int q = blockIdx.y;
     const int m = st.m;
     const int kd = st.kdim[q];
@@ -513,46 +549,39 @@ __global__ __launch_bounds__(256) void k_sstep_carry(double2* __restrict__ x, co
         wk[i] = make_double2((rho - theta * bi.x - bm.x / sigma) * f, (-theta * bi.y - bm.y / sigma) * f);
     }
     __syncthreads();
-    const int s = blockIdx.x * 256 + threadIdx.x;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long n = nch * SP;
     double nrm = 0;
-    if (s < V) {
-        const long long n = 12LL * V;
-        double2* xq = x + (long long)act[q] * n;
-        S* k0 = Kb + q * n;
-        double2 ax[12], ak[12];
+    if (k < nch) {
+        double2* xq = x + (long long)act[q] * n + k * SP;
+        const S* kq = Kb + q * n + k * SP;
+        cx<double> ax[SP], ak[SP];
 #pragma unroll
-        for (int c = 0; c < 12; c++) {
-            ax[c] = xq[(long long)c * V + s];
-            ak[c] = make_double2(0, 0);
+        for (int t = 0; t < SP; t++) {
+            const double2 v = xq[t];
+            ax[t] = {v.x, v.y};
+            ak[t] = {0, 0};
         }
-        for (int i = 0; i <= kd; i++) {
-            const double2 b = bx[i], w = wk[i];
-            const S* ki = Kb + (long long)i * kstride + q * n;
+        int i = 0;
+        for (; i + 7 <= kd; i += 8) carry_trip<S, 8, SP>(kq, kstride, i, bx, wk, ax, ak);
+        if (i + 3 <= kd) {
+            carry_trip<S, 4, SP>(kq, kstride, i, bx, wk, ax, ak);
+            i += 4;
+        }
+        for (; i <= kd; i++) carry_trip<S, 1, SP>(kq, kstride, i, bx, wk, ax, ak);
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                const cx<double> v = ldk<S, double>(ki + (long long)c * V + s);
-                ax[c].x += b.x * v.x - b.y * v.y;
-                ax[c].y += b.x * v.y + b.y * v.x;
-                ak[c].x += w.x * v.x - w.y * v.y;
-                ak[c].y += w.x * v.y + w.y * v.x;
-            }
+        for (int t = 0; t < SP; t++) {
+            xq[t] = make_double2(ax[t].x, ax[t].y);
+            nrm += ak[t].x * ak[t].x + ak[t].y * ak[t].y;
         }
-#pragma unroll
-        for (int c = 0; c < 12; c++) {
-            xq[(long long)c * V + s] = ax[c];
-            stk<S, double>(k0 + (long long)c * V + s, cx<double>{ak[c].x, ak[c].y});
-            nrm += ak[c].x * ak[c].x + ak[c].y * ak[c].y;
-        }
+        st16<S, double, SP>(Kb + q * n + k * SP, ak);
     }
-    red[threadIdx.x] = nrm;
+    nrm = wave_sum(nrm);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
         const double sc = st.est[q] / sqrtN;
-        part[(long long)q * gridDim.x + blockIdx.x] = red[0] * sc * sc;
+        part[(long long)q * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + (red[2] + red[3])) * sc * sc;
     }
 }
 
@@ -1026,12 +1055,16 @@ void kry_start(lqt_ctx* c, void* V0, const double2* r, const int* src, const dou
 }
 
 template <typename S>
+int kry_carry_blocks(const lqt_ctx* c) {
+    return (int)((kry_chunks<S>(c) + 255) / 256);
+}
+template <typename S>
 void kry_sstep_carry(lqt_ctx* c, double2* x, const int* act, void* Kb, long long kstride, int ns, const KryState& st,
                      double theta, double sigma, double* part, double* rn2) {
-    const int nblk = (c->g.V + 255) / 256;
+    const int nblk = kry_carry_blocks<S>(c);
     dim3 grid(nblk, ns);
-    hipLaunchKernelGGL(k_sstep_carry<S>, grid, dim3(256), 0, c->stream, x, act, (S*)Kb, kstride, c->g.V, st, theta,
-                       sigma, sqrt(12.0 * c->g.V), part);
+    hipLaunchKernelGGL(k_sstep_carry<S>, grid, dim3(256), 0, c->stream, x, act, (S*)Kb, kstride, kry_chunks<S>(c), st,
+                       theta, sigma, sqrt(12.0 * c->g.V), part);
     LQT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_carry_norms, dim3(ns), dim3(256), 0, c->stream, part, nblk, rn2);
     LQT_HIP(hipGetLastError());
@@ -1163,6 +1196,7 @@ void fields_from_f64(lqt_ctx* c, const double2* in, S* out, long long total) {
     template void fields_to_f64<S>(lqt_ctx*, const S*, double2*, long long);                             \
     template void fields_from_f64<S>(lqt_ctx*, const double2*, S*, long long);                           \
     template int kry_blocks<S>(const lqt_ctx*);                                                          \
+    template int kry_carry_blocks<S>(const lqt_ctx*);                                                    \
     template void kry_dots<S>(lqt_ctx*, const void*, long long, int, int, double2*);                     \
     template void kry_update<S>(lqt_ctx*, void*, long long, int, int, const KryState&, int, double*);    \
     template void kry_xupdate<S>(lqt_ctx*, double2*, const int*, const void*, long long, int,            \

@@ -109,7 +109,8 @@ int solve_batch(lqt_ctx* c, int prec, const double2* b, double2* x, int nb, doub
     rb.ensure((size_t)nb * n * sizeof(double2) + 4 * 256 * (size_t)nb);
     StateBuf sb;
     sb.carve(stb, nb, m);
-    partb.ensure(sizeof(double2) * (size_t)nb * nsb * (m + 2));
+    partb.ensure(std::max(sizeof(double2) * (size_t)nb * nsb * (m + 2),
+                          sizeof(double) * (size_t)nb * kry_carry_blocks<S>(c)));
     const int nlat = c->g.lat.nlat;
     const bool multi = nlat > 1;  // several lattices: every lattice block must meet xi
     // s-step basis k_{i+1} = sigma (A - theta) k_i: theta = 4 + m centres the spectrum of A
