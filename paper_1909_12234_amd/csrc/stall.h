@@ -1,7 +1,7 @@
 // Stall detection of restarted solves and the chain of more robust solver settings that a
 // stalled system falls back to (host code only).
 //
-// A restarted solve is judged on its FP64 true residuals (the only residuals that decide
+// A restarted solve is assessed on its FP64 true residuals (the only residuals that decide
 // convergence).  A system has stalled when
 //   - a cycle took no step at all: an s-step cycle whose Gram matrix kept fewer than two
 //     columns (the start vector is an eigenvector of A, or 16-bit storage overflowed); the
