@@ -57,6 +57,27 @@ def test_sstep_long_cycles_16bit(gpu, prec, s):
     c.close()
 
 
+@pytest.mark.parametrize("prec,s", [(0, 8), (1, 8), (2, 15), (3, 15)])
+def test_sstep_carry_ragged_lattice(gpu, prec, s):
+    """3x5x4x6 (V = 360): the pass that updates x and carries the residual covers a slot in
+    16-byte chunks (1080, 2160 and 4320 of them for 16-bit, FP32 and FP64 storage), 256 per
+    block, so its last block is partial; the solutions meet xi by the oracle's residual, with
+    carried residuals as without them."""
+    lq = gpu
+    dims, m, xi = (3, 5, 4, 6), -0.6, 1e-9
+    print(f"s-step carry on 3x5x4x6 s={s} prec={prec}", flush=True)
+    U = synth.su3_links(dims, 0.5, 5)
+    c = lq.Context(dims, m)
+    c.set_gauge(U)
+    b = synth.random_spinors(dims, 7, 6).reshape(7, -1)
+    bt = torch.as_tensor(b).cuda()
+    for reliable in (0.1, -1.0):  # carried residuals, then an FP64 residual at every cycle
+        x, st, _ = c.solve(bt, xi, prec=prec, restart=s, sstep=1, reliable=reliable, maxit=20000)
+        assert all(q[0] for q in st)
+        assert np.all(_relres(U, dims, m, b, x.cpu().numpy()) <= xi * 1.05)
+    c.close()
+
+
 def test_sstep_near_critical_16x8(gpu):
     """A harder operator (m = -1.4 on 8^3x16): BF16 storage, restart 8, to 1e-8."""
     lq = gpu
