@@ -493,16 +493,6 @@ __global__ __launch_bounds__(256) void k_xupdate(double2* __restrict__ x, const 
     for (int c = 0; c < 12; c++) xq[(long long)c * V + s] = acc[c];
 }
 
-// End of an s-step cycle that carries the residual in the basis (reliable updates): with
-// beta the cycle's coefficients (x += K_s beta) and A k_i = k_{i+1}/sigma + theta k_i for the
-// stored vectors, the new residual is r - A K_s beta = rho k_0 - K_{s+1} gamma, gamma = T beta
-// (gamma_i = theta beta_i + beta_{i-1}/sigma), rho = |r|/sqrt(N) of the cycle's start.  It is
-// written over k_0 scaled by sqrt(N)/est (est: the cycle's least-squares residual norm, which
-// the next cycle takes as its |r|), so x and the next start vector come from one pass over
-// the basis.  The pass is flat over the slot's 16-byte chunks of k_i (SP complex values, one
-// chunk per thread; x is read and written as the chunk's SP FP64 values) and keeps eight basis
-// vectors' loads in flight per trip.  part[q * gridDim.x + blk] = partial |r_new|^2 of the
-// block's 256 chunks.
 // U basis vectors of one carry trip: their loads are issued together, then
 // ax += sum_u bx[i+u] k_{i+u} and ak += sum_u wk[i+u] k_{i+u} in FP64, in the order of u
 template <typename S, int U, int SP>
@@ -526,6 +516,16 @@ __device__ __forceinline__ void carry_trip(const S* kq, long long kstride, int i
     }
 }
 
+// End of an s-step cycle that carries the residual in the basis (reliable updates): with
+// beta the cycle's coefficients (x += K_s beta) and A k_i = k_{i+1}/sigma + theta k_i for the
+// stored vectors, the new residual is r - A K_s beta = rho k_0 - K_{s+1} gamma, gamma = T beta
+// (gamma_i = theta beta_i + beta_{i-1}/sigma), rho = |r|/sqrt(N) of the cycle's start.  It is
+// written over k_0 scaled by sqrt(N)/est (est: the cycle's least-squares residual norm, which
+// the next cycle takes as its |r|), so x and the next start vector come from one pass over
+// the basis.  The pass is flat over the slot's 16-byte chunks of k_i (SP complex values, one
+// chunk per thread; x is read and written as the chunk's SP FP64 values) and keeps eight basis
+// vectors' loads in flight per trip.  part[q * gridDim.x + blk] = partial |r_new|^2 of the
+// block's 256 chunks.
 template <typename S>
 __global__ __launch_bounds__(256) void k_sstep_carry(double2* __restrict__ x, const int* __restrict__ act,
                                                      S* __restrict__ Kb, long long kstride, long long nch,
