@@ -126,10 +126,11 @@ def dslash_flops(byt, calls, sites, b):
     return 1392.0 * site_rhs
 
 
-def _measured_traffic(family, tile=None):
+def _measured_traffic(family, tile=None, workload=None):
     """HBM bytes per launch of a kernel family from the recorded counter runs (one record per
-    measured tile), or None when the kernel's source has changed since they were taken (hash
-    mismatch), the tuned tile is none of those measured, or none exist."""
+    measured workload and tile), or None when the kernel's source has changed since they were
+    taken (hash mismatch), the workload or the tuned tile is none of those measured, or none
+    exist."""
     import hashlib
 
     try:
@@ -140,6 +141,8 @@ def _measured_traffic(family, tile=None):
         if isinstance(recs, dict):
             recs = [recs]
         for rec in recs:
+            if rec.get("workload") != workload:
+                continue
             if tile is not None and "tile" in rec and list(rec["tile"]) != list(tile):
                 continue
             with open(os.path.join(ROOT, "paper_1909_12234_amd", rec["source"]), "rb") as f:
@@ -151,7 +154,7 @@ def _measured_traffic(family, tile=None):
         return None
 
 
-def _roofline(kt, sites=None, b=None, tile=None):
+def _roofline(kt, sites=None, b=None, tile=None, workload=None):
     """Dominant kernel family by device time among those with algorithmic bytes.  The
     reduced-precision Wilson operator with FP32 arithmetic on the vector ALUs (tile kind 0) is
     reported against their FMA peak; the packed-FP16 and matrix-core operators (kinds 2, 3, 1)
@@ -159,7 +162,8 @@ def _roofline(kt, sites=None, b=None, tile=None):
     kind = tile[3] if tile else 0
     fam = max((f for f in kt if kt[f][2] > 0), key=lambda f: kt[f][0])
     ms, calls, byt = kt[fam]
-    base = {"kernel": fam, "traffic": _measured_traffic(fam, tile if fam == "dslash" else None), "launches": calls,
+    base = {"kernel": fam, "traffic": _measured_traffic(fam, tile if fam == "dslash" else None, workload),
+            "launches": calls,
             "avg_launch_us": round(ms * 1e3 / max(calls, 1), 2)}
     if fam == "dslash" and sites and b and b < 8 and kind == 0:
         tf = dslash_flops(byt, calls, sites, b) / (ms * 1e-3) / 1e12
@@ -411,7 +415,7 @@ def run_mg(a, w):
     extra = {
         "dtype_detail": f"{w['inner_prec']} links and Krylov vectors, fp32 accumulate, fp64 defect correction; "
                         "fp64 prolongator, coarse operator and projections",
-        "roofline": _roofline(kt, V, bpr, tile=tile),
+        "roofline": _roofline(kt, V, bpr, tile=tile, workload=a.workload),
         "kernel_ms": {f: round(kt[f][0], 2) for f in kt},
         "iters_per_probe_mixed": round(sum(r["iters_total"] for r in results) / max(1, sum(r["nsolves"] for r in results)), 1),
         # restriction of the probes (W streamed once per 32 probes), algorithmic bytes / time
@@ -586,7 +590,7 @@ def main():
 
     # roofline of the dominant kernel family (by device time), from live HIP events
     bpr = {0: 8, 1: 4, 2: 2, 3: 2}[prec]  # bytes per real of the inner storage
-    roof = _roofline(kt, V, bpr, tile=tile)
+    roof = _roofline(kt, V, bpr, tile=tile, workload=a.workload)
     d_ms, d_calls, d_b = kt["dslash"]
     dslash_gbs = d_b / (d_ms * 1e-3) / 1e9 if d_ms > 0 else None
 

@@ -35,34 +35,40 @@ def test_roofline_takes_the_dominant_family_against_hbm():
     assert bench._roofline(kt2)["kernel"] == "cgs_dots"
 
 
-def test_recorded_traffic_is_used_only_for_its_source_and_tile(tmp_path, monkeypatch):
+def test_recorded_traffic_is_used_only_for_its_source_workload_and_tile(tmp_path, monkeypatch):
     import hashlib
 
     pkg = tmp_path / "paper_1909_12234_amd"
     (pkg / "csrc").mkdir(parents=True)
     src = b"// kernel source\n"
     (pkg / "csrc" / "k.hip").write_bytes(src)
-    rec = {"source": "csrc/k.hip", "sha256_16": hashlib.sha256(src).hexdigest()[:16],
+    rec = {"source": "csrc/k.hip", "sha256_16": hashlib.sha256(src).hexdigest()[:16], "workload": "w1",
            "tile": [2, 256, 64, 3], "fetch_bytes": 1000, "write_bytes": 24}
     other = dict(rec, tile=[2, 256, 64, 2], fetch_bytes=5)
     (pkg / "traffic.json").write_text(json.dumps({"kernels": {"dslash": [rec, other]}}))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench._measured_traffic("dslash", (2, 256, 64, 3)) == 1024
-    assert bench._measured_traffic("dslash", (2, 256, 64, 2)) == 29
-    assert bench._measured_traffic("dslash", (7, 7, 7, 7)) is None
-    assert bench._measured_traffic("no_such_kernel") is None
+    assert bench._measured_traffic("dslash", (2, 256, 64, 3), "w1") == 1024
+    assert bench._measured_traffic("dslash", (2, 256, 64, 2), "w1") == 29
+    assert bench._measured_traffic("dslash", (7, 7, 7, 7), "w1") is None
+    assert bench._measured_traffic("no_such_kernel", None, "w1") is None
+    # a record taken on another workload (other lattice, other batch size) is not used
+    assert bench._measured_traffic("dslash", (2, 256, 64, 3), "w2") is None
+    assert bench._measured_traffic("dslash", (2, 256, 64, 3)) is None
     # a kernel source that differs from the recorded hash voids the record
     (pkg / "csrc" / "k.hip").write_bytes(src + b"// edited\n")
-    assert bench._measured_traffic("dslash", (2, 256, 64, 3)) is None
+    assert bench._measured_traffic("dslash", (2, 256, 64, 3), "w1") is None
 
 
 def test_committed_traffic_records_are_well_formed():
     with open(os.path.join(ROOT, "paper_1909_12234_amd", "traffic.json")) as f:
         recs = json.load(f)["kernels"]["dslash"]
+    from paper_1909_12234_amd.workloads import WORKLOADS
+
     for rec in recs:
         assert os.path.exists(os.path.join(ROOT, "paper_1909_12234_amd", rec["source"]))
         assert len(rec["tile"]) == 4 and rec["fetch_bytes"] > 0 and rec["write_bytes"] > 0
         assert len(rec["sha256_16"]) == 16
+        assert rec["workload"] in WORKLOADS
 
 
 def test_more_than_one_gpu_exits_before_touching_a_device():
